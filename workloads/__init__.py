@@ -1,0 +1,172 @@
+"""Seeded synthetic inputs shared by the tests, the smoke check and the benchmark.
+
+This module holds none of the method's arithmetic: it only produces
+experiment parameters (grid sizes, wall angles, radii, wetting parameters)
+and initial density fields, following the set-ups of the paper's Sections 3
+and 4.  The wall mask rasters, the classification and every step of the
+update are computed by the oracle on one side and by the HIP library on the
+other, each from its own code.
+
+Angles are passed to both sides in radians, already converted here, so that
+the two rasters receive the same double.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+MC, LLKC, IMPROVED = 0, 1, 2
+BC_NAMES = {MC: "martys-chen", LLKC: "llkc", IMPROVED: "improved"}
+
+
+@dataclass
+class Case:
+    """One simulation: geometry recipe, parameters and initial densities."""
+
+    name: str
+    nx: int
+    ny: int
+    periodic: int = 0           # bit0 x, bit1 y
+    tau: float = 1.0
+    G: float = 0.9
+    bc: int = MC
+    Gw: float = 0.0
+    chiA: float = 1.0
+    chiB: float = 1.0
+    avg: int = 0                # 0 = D2Q25 average, 1 = D2Q9 average
+    steps: int = 100
+    # geometry recipe: ("rows", (y...)) | ("plane", beta_rad, R0) | ("disk", cx, cy, R) | ("none",)
+    geometry: tuple = ("none",)
+    rhoA0: np.ndarray | None = field(default=None, repr=False)
+    rhoB0: np.ndarray | None = field(default=None, repr=False)
+    mask_user: np.ndarray | None = field(default=None, repr=False)
+
+    def params(self) -> dict:
+        return dict(tau=self.tau, G=self.G, bc=self.bc, Gw=self.Gw, chiA=self.chiA,
+                    chiB=self.chiB, avg=self.avg, periodic=self.periodic)
+
+
+def rows_mask(nx: int, ny: int, rows) -> np.ndarray:
+    """A user mask with whole solid rows (on-grid walls)."""
+    m = np.zeros((ny, nx), np.uint8)
+    for r in rows:
+        m[r, :] = 1
+    return m
+
+
+def sharp_drop(nx, ny, cx, cy, R, rho_in=1.0, rho_out=0.03):
+    """Sharp circular drop of A in B (Section 3.1): inclusive circle."""
+    yy, xx = np.mgrid[0:ny, 0:nx]
+    inside = (xx - cx) ** 2 + (yy - cy) ** 2 <= R * R
+    rA = np.where(inside, rho_in, rho_out).astype(np.float64)
+    rB = np.where(inside, rho_out, rho_in).astype(np.float64)
+    return rA, rB
+
+
+def tanh_two_drops(nx, ny, xc1, xc2, yc, R0, rho1=1.0, rho2=0.055, delta=8.0):
+    """Two drops with smoothed interfaces, the initial condition of Section 4."""
+    yy, xx = np.mgrid[0:ny, 0:nx].astype(np.float64)
+    h1 = 0.5 * (rho1 - rho2) * (1.0 - np.tanh(((xx - xc1) ** 2 + (yy - yc) ** 2 - R0 * R0) / delta ** 2))
+    h2 = 0.5 * (rho1 - rho2) * (1.0 - np.tanh(((xx - xc2) ** 2 + (yy - yc) ** 2 - R0 * R0) / delta ** 2))
+    rA = rho2 + h1 + h2
+    rB = rho1 - h1 - h2
+    return rA, rB
+
+
+def random_mixture(nx, ny, seed, mean=0.5, amp=0.01):
+    """Near-uniform 50/50 mixture with seeded noise (spinodal start)."""
+    rng = np.random.default_rng(seed)
+    d = amp * (2.0 * rng.random((ny, nx)) - 1.0)
+    return mean + d, mean - d
+
+
+# ---------------------------------------------------------------------------
+# The five configurations and the out-of-cache roofline grid
+# ---------------------------------------------------------------------------
+
+def config1(G=0.9) -> Case:
+    """64x64, periodic in x, on-grid walls y=0,63, half drop R=15 on the bottom wall, Martys-Chen."""
+    nx = ny = 64
+    rA, rB = sharp_drop(nx, ny, 32.0, 0.5, 15.0, 1.0, 0.03)
+    return Case("c1-flat-wall-64x64-mc", nx, ny, periodic=1, tau=1.0, G=G, bc=MC, Gw=-0.2,
+                steps=2000, geometry=("rows", (0, ny - 1)), rhoA0=rA, rhoB0=rB,
+                mask_user=rows_mask(nx, ny, (0, ny - 1)))
+
+
+def plane_drop(nx, ny, beta_deg, R0, bc, *, G=0.9, tau=1.0, rho_out=0.03, Gw=None, chi=(1.0, 1.0),
+               steps=100, name=None) -> Case:
+    """Drop of radius R0 at the box centre, tangent to a plane inclined by beta (Section 3.1)."""
+    beta = math.radians(beta_deg)
+    rA, rB = sharp_drop(nx, ny, nx / 2.0, ny / 2.0, R0, 1.0, rho_out)
+    if Gw is None:
+        Gw = {MC: -0.2, LLKC: -0.5, IMPROVED: 0.0}[bc]
+    return Case(name or "plane-%dx%d-b%g-%s" % (nx, ny, beta_deg, BC_NAMES[bc]), nx, ny, periodic=0,
+                tau=tau, G=G, bc=bc, Gw=Gw, chiA=chi[0], chiB=chi[1], steps=steps,
+                geometry=("plane", beta, float(R0)), rhoA0=rA, rhoB0=rB)
+
+
+def config2() -> Case:
+    """512x256, 30 degree stair wall, drop R=40, improved scheme (chi = 1), FP32, 20k steps."""
+    return plane_drop(512, 256, 30.0, 40.0, IMPROVED, steps=20000,
+                      name="c2-plane30-512x256-improved")
+
+
+def config3(seed: int = 0) -> Case:
+    """1024x1024, solid disk R=300 at the centre, two tanh drops R0=60 touching on top."""
+    nx = ny = 1024
+    rng = np.random.default_rng(seed)
+    s = float(rng.uniform(0.3, 0.7))          # solid density of the run
+    cx, cy, Rs, R0 = 512.0, 512.0, 300.0, 60.0
+    theta = math.radians(71.0)
+    top = cy + Rs
+    xc1 = cx - R0 * math.sin(theta) - 1.0
+    xc2 = cx + R0 * math.sin(theta) + 1.0
+    yc = top - R0 * math.cos(theta)
+    rA, rB = tanh_two_drops(nx, ny, xc1, xc2, yc, R0, 1.0, 0.03, 8.0)
+    return Case("c3-disk-1024-improved-seed%d" % seed, nx, ny, periodic=0, tau=1.0, G=0.9,
+                bc=IMPROVED, chiA=2.0 * s, chiB=2.0 - 2.0 * s, steps=50000,
+                geometry=("disk", cx, cy, Rs), rhoA0=rA, rhoB0=rB)
+
+
+def config4_instances(n: int = 64, seed0: int = 0):
+    """Batch of seeded instances: W in 128..768, H in 64..384, beta in [0, 45] degrees."""
+    out = []
+    for s in range(seed0, seed0 + n):
+        rng = np.random.default_rng(1000 + s)
+        W = int(rng.integers(128, 769))
+        H = int(rng.integers(64, 385))
+        beta = float(rng.uniform(0.0, 45.0))
+        bc = int(rng.integers(0, 3))
+        R0 = H / 5.0
+        c = plane_drop(W, H, beta, R0, bc, steps=10000, name="c4-%02d-%dx%d-b%.1f-%s" % (
+            s, W, H, beta, BC_NAMES[bc]))
+        out.append(c)
+    return out
+
+
+def config5_requests(n: int = 400, seed: int = 12345, rate: float = 200.0):
+    """Served stream: Poisson arrivals, sizes 64x64..2048x1024, 2k-20k steps, mixed BCs."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    reqs = []
+    for k in range(n):
+        t += float(rng.exponential(1.0 / rate))
+        W = int(rng.integers(64, 2049))
+        H = int(rng.integers(64, 1025))
+        steps = int(rng.integers(2000, 20001))
+        beta = float(rng.uniform(0.0, 45.0))
+        bc = int(rng.integers(0, 3))
+        R0 = max(4.0, H / 5.0)
+        c = plane_drop(W, H, beta, R0, bc, steps=steps, name="c5-%03d" % k)
+        reqs.append((t, c))
+    return reqs
+
+
+def roofline_case(nx=5600, ny=4000, seed=7, G=3.0) -> Case:
+    """The paper's largest grid (Section 4 convergence study) as a fully periodic mixture."""
+    rA, rB = random_mixture(nx, ny, seed)
+    return Case("r-periodic-%dx%d" % (nx, ny), nx, ny, periodic=3, tau=1.0, G=G, bc=MC, Gw=0.0,
+                steps=1000, geometry=("none",), rhoA0=rA, rhoB0=rB,
+                mask_user=np.zeros((ny, nx), np.uint8))
