@@ -1,0 +1,217 @@
+/*
+ * mclbm — two-component pseudopotential lattice Boltzmann with wetting walls
+ * on AMD Instinct MI355X (gfx950).  C ABI of libmclbm.so.
+ *
+ * The method is the one of Coelho, Moura, Telo da Gama and Araujo,
+ * "Wetting boundary conditions for multicomponent pseudopotential lattice
+ * Boltzmann" (arXiv:2009.12584), Section 2:
+ *   - D2Q9 populations f_i^A, f_i^B, BGK collision with one relaxation time
+ *     tau for both components (Eq. 1), second-order equilibrium (Eq. 2) at the
+ *     common velocity shifted by half the total force (Eq. 3), Guo source
+ *     (Eq. 4);
+ *   - Shan-Chen inter-component force with psi = rho, summed over fluid
+ *     neighbours only (Eq. 5 and the paragraph after the equation of state);
+ *   - half-way bounce-back on the solid switch phi (1 = solid);
+ *   - adhesion force (Eq. 6) with one of three solid pseudopotentials:
+ *     Martys-Chen S = phi; Li-Luo-Kang-Chen S(x+c_i) = phi(x+c_i) rho(x);
+ *     improved virtual solid density S = phi rho~ (Eq. 7, averaged over the
+ *     fluid nodes of the D2Q25 or D2Q9 neighbourhood).
+ *
+ * Conventions for every entry point:
+ *   - Return 0 on success or a negative LBM_E* code; no exception crosses
+ *     the ABI.  lbm_strerror() names a code, lbm_last_error() gives detail.
+ *   - Host arrays are row-major, index = y * nx + x, and are read or written
+ *     only during the call (the library copies what it keeps).
+ *   - Device pointers are plain HIP device addresses on the handle's device.
+ *   - A handle owns all device memory it allocates until lbm_destroy.
+ *     A handle is not thread-safe; distinct handles are independent.
+ *   - Work is enqueued on the HIP stream given at creation (NULL = the null
+ *     stream).  Calls that return host data synchronise that stream.
+ *   - Solid nodes report zero density, velocity and force.
+ *
+ * D2Q9 order used by every bit mask and population index:
+ *   i : 0      1      2      3       4       5      6       7        8
+ *   c : (0,0)  (1,0)  (0,1)  (-1,0)  (0,-1)  (1,1)  (-1,1)  (-1,-1)  (1,-1)
+ */
+#ifndef MCLBM_H
+#define MCLBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ---- */
+#define LBM_OK 0
+#define LBM_EINVAL (-1)   /* invalid argument: sizes, tau <= 1/2, bad mask or densities */
+#define LBM_ENOMEM (-2)   /* device or host allocation failed */
+#define LBM_EAGAIN (-3)   /* pool: no free slot or HBM budget right now */
+#define LBM_EDEVICE (-4)  /* a HIP runtime call failed */
+#define LBM_ENUMERIC (-5) /* non-finite or negative density, or mass drift above tolerance */
+#define LBM_ENOTFOUND (-6) /* pool: slot not active */
+
+/* ---- enums ---- */
+typedef enum { LBM_BC_MARTYS_CHEN = 0, LBM_BC_LLKC = 1, LBM_BC_VIRTUAL_IMPROVED = 2 } lbm_bc;
+/* averaging lattice of the virtual solid density, Eq. 7 and the text after it */
+typedef enum { LBM_AVG_D2Q25 = 0, LBM_AVG_D2Q9 = 1 } lbm_avg;
+/* storage of the populations as deviations d_i = f_i - w_i rho_ref */
+typedef enum { LBM_STORE_F32 = 0, LBM_STORE_F16 = 1 } lbm_storage;
+
+/* Problem statement of one simulation (Sections 2 and 3.1). */
+typedef struct {
+    int32_t nx, ny;      /* lattice size L_X x L_Y, each >= 1 */
+    uint32_t periodic;   /* bit0: periodic in x, bit1: periodic in y; a non-periodic
+                            border row or column must be solid */
+    double tau;          /* relaxation time (tau^A = tau^B), > 1/2; nu = (tau - 1/2)/3 */
+    double G;            /* G_AB = G_BA of Eq. 5 (D2Q9 weights inside the sum) */
+    int32_t bc;          /* lbm_bc */
+    double G_w;          /* Martys-Chen, LLKC: G_As = G_w, G_Bs = -G_w; G_w < 0 wets A */
+    double chi[2];       /* improved scheme: chi^A, chi^B of Eq. 7 (G_{sigma s} = G) */
+    int32_t avg;         /* lbm_avg */
+    int32_t storage;     /* lbm_storage */
+    double rho_ref[2];   /* deviation reference per component; NaN = the smallest
+                            initial density over fluid nodes */
+    int32_t diag_every;  /* fused FP64 diagnostics every k steps; 0 = only on lbm_diag */
+    double drift_tol;    /* relative mass drift that flags LBM_ENUMERIC; <= 0 = off */
+    int32_t graph_steps; /* > 0: lbm_step replays a captured HIP graph of this many
+                            steps (rounded up to even); 0 = plain launches */
+    int32_t tile_y;      /* rows per tile: 0 = default, else one of 4, 8, 16 */
+} lbm_params;
+
+/* Diagnostics, reduced in FP64 over fluid nodes at the handle's current time. */
+typedef struct {
+    double mass[2];      /* sum rho^A, sum rho^B */
+    double mass0[2];     /* the same at step 0 */
+    double momentum[2];  /* sum (rho^A + rho^B) u, u of Eq. 3 */
+    double max_speed;    /* max |u| */
+    int64_t step;        /* time of these values */
+    int32_t flags;       /* bit0 non-finite, bit1 negative density, bit2 drift > drift_tol */
+    int32_t pad;
+} lbm_diag_t;
+
+typedef struct lbm_handle lbm_handle;
+
+/* Fills *p with defaults: tau 1, G 0.9, Martys-Chen with G_w 0, chi 1, D2Q25,
+ * FP32 storage, rho_ref NaN, diag_every 0, drift_tol 0, graph_steps 0. */
+void lbm_params_default(lbm_params *p);
+
+/* Creates one simulation.  mask: nx*ny bytes, non-zero = solid (phi of
+ * Section 2).  rhoA0, rhoB0: nx*ny initial densities (read on fluid nodes;
+ * each >= 0 and finite, their sum > 0).  The initial populations are the rest
+ * equilibrium w_i rho_0.  stream: a hipStream_t or NULL.  On success *out
+ * owns device memory until lbm_destroy.  Errors: LBM_EINVAL (sizes, tau,
+ * enum values, fluid on a non-periodic border, bad densities), LBM_ENOMEM,
+ * LBM_EDEVICE.  Synchronises the stream before returning. */
+int lbm_create(const lbm_params *p, const uint8_t *mask, const double *rhoA0, const double *rhoB0,
+               void *stream, lbm_handle **out);
+
+/* Advances nsteps >= 0 time steps (Eqs. 1-7 plus streaming), enqueued
+ * asynchronously on the handle's stream.  Returns LBM_ENUMERIC at once if an
+ * earlier lbm_diag found the state broken. */
+int lbm_step(lbm_handle *h, int64_t nsteps);
+
+/* Current time step count. */
+int64_t lbm_time(const lbm_handle *h);
+
+/* Fields at the current time into caller-owned host arrays of nx*ny doubles
+ * (any may be NULL): densities, and the velocity of Eq. 3.  Synchronises. */
+int lbm_fields(lbm_handle *h, double *rhoA, double *rhoB, double *ux, double *uy);
+
+/* Same into caller-owned DEVICE arrays of nx*ny floats, enqueued on the
+ * handle's stream, no synchronisation. */
+int lbm_fields_device(lbm_handle *h, float *rhoA, float *rhoB, float *ux, float *uy);
+
+/* Forces of Eqs. 5-6 per component and the virtual solid densities of Eq. 7
+ * (zero off interface solids, and for the other two rules) at the current
+ * time, into host arrays of nx*ny doubles (any may be NULL).  Synchronises. */
+int lbm_forces(lbm_handle *h, double *FAx, double *FAy, double *FBx, double *FBy, double *rtA,
+               double *rtB);
+
+/* FP64 mass / momentum / max-speed reduction at the current time (one fused
+ * pass on the device), plus the flags gathered since creation.  Synchronises.
+ * Returns LBM_ENUMERIC when a flag is set (the struct is still filled). */
+int lbm_diag(lbm_handle *h, lbm_diag_t *out);
+
+/* Stair classification computed on the device at creation (Fig. 1A caption;
+ * Section 3.1 on internal and external corners; Section 3.2 on interface
+ * solids).  nbr: bit (i-1) set when neighbour i = 1..8 is solid or lies
+ * beyond a non-periodic border.  cls: 0 bulk fluid, 1 fluid with a solid
+ * neighbour, 2 interface solid, 3 bulk solid.  Host arrays of nx*ny bytes. */
+int lbm_classify(lbm_handle *h, uint8_t *nbr, uint8_t *cls);
+
+/* Raw state for bit-exact checkpoint/resume: the population buffer in its
+ * storage format.  lbm_state_bytes gives the size; get/set copy to or from a
+ * host buffer of that size, together with the step counter. */
+size_t lbm_state_bytes(const lbm_handle *h);
+int lbm_get_state(lbm_handle *h, void *host, int64_t *step);
+int lbm_set_state(lbm_handle *h, const void *host, int64_t step);
+
+/* Destroys a handle; NULL is a no-op. */
+int lbm_destroy(lbm_handle *h);
+
+const char *lbm_strerror(int code);
+const char *lbm_last_error(const lbm_handle *h);
+
+/* ---- geometry rasters (computed on the device, FP64, no contraction) ---- */
+
+/* Plane of Section 3.1: y = tan(beta) [x - L_X/2 - R0 sin(beta)] + L_Y/2 - R0 cos(beta);
+ * a node is solid on or below it.  beta in radians, |beta| < pi/2.  borders != 0
+ * also makes x = 0, L_X-1 and y = 0, L_Y-1 solid.  out: host array, nx*ny bytes. */
+int lbm_mask_plane(int32_t nx, int32_t ny, double beta, double R0, int32_t borders, uint8_t *out);
+
+/* Disk of Section 4: (x - cx)^2 + (y - cy)^2 <= R^2 is solid. */
+int lbm_mask_disk(int32_t nx, int32_t ny, double cx, double cy, double R, int32_t borders,
+                  uint8_t *out);
+
+/* Measurement aid: a plain streaming copy of bytes (a multiple of 16) from
+ * src to dst, both device pointers, enqueued on stream.  Its achieved
+ * bandwidth is the practical HBM ceiling for a kernel that reads and writes
+ * equal byte counts; its PMC byte counters calibrate the step kernel's. */
+int lbm_copy_probe(void *dst, const void *src, size_t bytes, void *stream);
+
+/* ---- batched form: many independent simulations advanced by one launch per
+ *      step over a flattened (instance, tile) list ---- */
+typedef struct lbm_batch lbm_batch;
+
+/* n instances; arrays of n pointers to the same per-instance inputs as
+ * lbm_create.  Every instance must use the same storage.  graph_steps > 0
+ * captures that many steps of the whole batch in one HIP graph. */
+int lbm_batch_create(int32_t n, const lbm_params *params, const uint8_t *const *masks,
+                     const double *const *rhoA0, const double *const *rhoB0, void *stream,
+                     int32_t graph_steps, lbm_batch **out);
+int lbm_batch_step(lbm_batch *b, int64_t nsteps);
+int lbm_batch_fields(lbm_batch *b, int32_t idx, double *rhoA, double *rhoB, double *ux, double *uy);
+int lbm_batch_diag(lbm_batch *b, int32_t idx, lbm_diag_t *out);
+int64_t lbm_batch_fluid_nodes(const lbm_batch *b);
+int lbm_batch_destroy(lbm_batch *b);
+
+/* ---- served form: a pool of resident slots, continuous batching ---- */
+typedef struct lbm_pool lbm_pool;
+
+/* hbm_budget: bytes of device memory the pool may hold for simulation state;
+ * max_slots: most simultaneous solves; storage: lbm_storage for all slots. */
+int lbm_pool_create(size_t hbm_budget, int32_t max_slots, int32_t storage, void *stream,
+                    lbm_pool **out);
+/* Bytes of device memory one solve of these parameters occupies. */
+size_t lbm_pool_footprint(const lbm_params *p);
+/* Admits one solve of nsteps steps.  Returns LBM_EAGAIN when neither a slot
+ * nor enough budget is free; *slot receives the slot id otherwise. */
+int lbm_pool_admit(lbm_pool *pool, const lbm_params *p, const uint8_t *mask, const double *rhoA0,
+                   const double *rhoB0, int64_t nsteps, int32_t *slot);
+/* Advances every active, unfinished slot by up to chunk steps in one batched
+ * launch per step; a slot stops exactly at its own step count. */
+int lbm_pool_advance(lbm_pool *pool, int64_t chunk);
+/* Writes up to max ids of finished, unreleased slots; *n receives the count. */
+int lbm_pool_poll(lbm_pool *pool, int32_t *slots, int32_t max, int32_t *n);
+int lbm_pool_fields(lbm_pool *pool, int32_t slot, double *rhoA, double *rhoB, double *ux,
+                    double *uy);
+int lbm_pool_release(lbm_pool *pool, int32_t slot);
+int lbm_pool_stats(const lbm_pool *pool, int32_t *active, size_t *bytes_in_use);
+int lbm_pool_destroy(lbm_pool *pool);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

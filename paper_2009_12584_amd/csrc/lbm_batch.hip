@@ -1,0 +1,728 @@
+// Batched and served forms of the step.
+//
+// Batch: many independent simulations of uneven sizes advance together; one
+// launch per time step covers the flattened list of (instance, tile) pairs of
+// all instances, so small grids no longer pay one launch each and the tail
+// of one grid overlaps the bulk of another.  K steps can be captured in one
+// HIP graph.
+//
+// Pool: resident slots with continuous batching.  Solves are admitted while
+// others run, as slots and HBM budget free up; their set-up kernels run on a
+// second stream and overlap the running batch; every launch advances all
+// active slots, each slot stops exactly at its own step count (blocks of a
+// finished slot exit at once), and finished slots are polled, read back and
+// released without stopping the others.  Device memory comes from one arena
+// reserved at creation (first-fit, no allocation in the serving loop).
+#include <algorithm>
+#include <deque>
+#include <map>
+
+#include "lbm_common.hpp"
+
+using namespace mclbm;
+
+namespace {
+
+template <typename S, int TY>
+__global__ __launch_bounds__(NT) void k_batch_step(const Inst *__restrict__ insts, const int2 *__restrict__ tiles,
+                                                   int launch_parity, long long L) {
+    __shared__ Smem<TY> sm;
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    const int2 e = tiles[t];
+    const Inst I = insts[e.x];
+    if (L >= I.t_end) return;  // this slot has finished; the whole block leaves together
+    const int parity = (I.parity0 ^ launch_parity) & 1;
+    const int tx = e.y % I.tiles_x, ty = e.y / I.tiles_x;
+    DiagAcc acc;
+    Fields none{};
+    switch (I.bc) {
+    case BC_MC: process_tile<S, TY, BC_MC, MODE_STEP, false>(I, tx, ty, parity, sm, acc, none); break;
+    case BC_LLKC: process_tile<S, TY, BC_LLKC, MODE_STEP, false>(I, tx, ty, parity, sm, acc, none); break;
+    default: process_tile<S, TY, BC_IMPROVED, MODE_STEP, false>(I, tx, ty, parity, sm, acc, none); break;
+    }
+}
+
+void launch_batch(int storage, int ty, hipStream_t s, int ntiles, const Inst *insts, const int2 *tiles, int lp,
+                  long long L) {
+    if (ntiles <= 0) return;
+    dim3 g((unsigned)ntiles), b(NT);
+    if (storage == LBM_STORE_F16) {
+        if (ty == 4) hipLaunchKernelGGL((k_batch_step<__half, 4>), g, b, 0, s, insts, tiles, lp, L);
+        else if (ty == 16) hipLaunchKernelGGL((k_batch_step<__half, 16>), g, b, 0, s, insts, tiles, lp, L);
+        else hipLaunchKernelGGL((k_batch_step<__half, 8>), g, b, 0, s, insts, tiles, lp, L);
+    } else {
+        if (ty == 4) hipLaunchKernelGGL((k_batch_step<float, 4>), g, b, 0, s, insts, tiles, lp, L);
+        else if (ty == 16) hipLaunchKernelGGL((k_batch_step<float, 16>), g, b, 0, s, insts, tiles, lp, L);
+        else hipLaunchKernelGGL((k_batch_step<float, 8>), g, b, 0, s, insts, tiles, lp, L);
+    }
+}
+
+// Device memory of one instance, carved from one block.
+struct InstMem {
+    size_t bytes = 0;
+    size_t off_buf0, off_buf1, off_node, off_nbr, off_cls, off_tflag, off_part, off_dd, off_fields;
+};
+
+inline size_t al(size_t x) { return (x + 255) / 256 * 256; }
+
+InstMem layout(const lbm_params &p, int ty) {
+    InstMem m;
+    const size_t n = (size_t)p.nx * p.ny;
+    const size_t plane = (size_t)p.ny * pitch_of(p.nx);
+    const size_t tiles = (size_t)((p.nx + TX - 1) / TX) * ((p.ny + ty - 1) / ty);
+    size_t o = 0;
+    auto take = [&](size_t b) {
+        size_t r = o;
+        o += al(b);
+        return r;
+    };
+    m.off_buf0 = take(18 * plane * store_bytes(p.storage));
+    m.off_buf1 = take(18 * plane * store_bytes(p.storage));
+    m.off_node = take(n);
+    m.off_nbr = take(n);
+    m.off_cls = take(n);
+    m.off_tflag = take(tiles);
+    m.off_part = take(tiles * 6 * sizeof(double));
+    m.off_dd = take(sizeof(DiagDev));
+    m.off_fields = take(4 * n * sizeof(float));  // read-back staging: rhoA, rhoB, ux, uy
+    m.bytes = o;
+    return m;
+}
+
+// One prepared instance: Inst plus the pointers the host needs.
+struct Prepared {
+    lbm_params p;
+    Inst I{};
+    InstMem m;
+    char *base = nullptr;
+    uint8_t *nbr = nullptr, *cls = nullptr;
+    double *partials = nullptr;
+    DiagDev *dd = nullptr;
+    float *fields = nullptr;
+    int ntiles = 0;
+    int ty = 8;
+    int64_t fluid = 0;
+};
+
+// Classification, tile flags, initial populations and step-0 mass for one
+// instance whose memory block is at base; enqueued on stream s.  The temporary
+// upload buffers are owned by the caller until the stream has drained them.
+int prepare(Prepared &P, const lbm_params &p, int ty, char *base, const uint8_t *mask, const double *rA,
+            const double *rB, hipStream_t s, uint8_t *dmask, uint8_t *node0, double *drA, double *drB) {
+    P.p = p;
+    P.ty = ty;
+    P.m = layout(p, ty);
+    P.base = base;
+    double rref[2];
+    resolve_rref(p, mask, rA, rB, rref);
+    fill_inst(P.I, p, rref, ty);
+    P.ntiles = P.I.tiles_x * P.I.tiles_y;
+    const size_t n = (size_t)p.nx * p.ny;
+    int64_t fl = 0;
+    for (size_t k = 0; k < n; ++k) fl += mask[k] ? 0 : 1;
+    P.fluid = fl;
+    P.I.buf[0] = base + P.m.off_buf0;
+    P.I.buf[1] = base + P.m.off_buf1;
+    uint8_t *node = (uint8_t *)(base + P.m.off_node);
+    P.nbr = (uint8_t *)(base + P.m.off_nbr);
+    P.cls = (uint8_t *)(base + P.m.off_cls);
+    uint8_t *tflag = (uint8_t *)(base + P.m.off_tflag);
+    P.partials = (double *)(base + P.m.off_part);
+    P.dd = (DiagDev *)(base + P.m.off_dd);
+    P.fields = (float *)(base + P.m.off_fields);
+    P.I.node = node;
+    P.I.tflag = tflag;
+    const size_t bufbytes = 18 * (size_t)P.I.plane * store_bytes(p.storage);
+    MCLBM_HIP(hipMemsetAsync(P.I.buf[0], 0, bufbytes, s));
+    MCLBM_HIP(hipMemsetAsync(P.I.buf[1], 0, bufbytes, s));
+    MCLBM_HIP(hipMemsetAsync(P.dd, 0, sizeof(DiagDev), s));
+    MCLBM_HIP(hipMemcpyAsync(dmask, mask, n, hipMemcpyHostToDevice, s));
+    MCLBM_HIP(hipMemcpyAsync(drA, rA, n * sizeof(double), hipMemcpyHostToDevice, s));
+    MCLBM_HIP(hipMemcpyAsync(drB, rB, n * sizeof(double), hipMemcpyHostToDevice, s));
+    const unsigned nb = (unsigned)((n + 255) / 256);
+    hipLaunchKernelGGL(k_classify, dim3(nb), dim3(256), 0, s, dmask, p.nx, p.ny, p.periodic, P.nbr, P.cls, node0);
+    hipLaunchKernelGGL(k_near, dim3(nb), dim3(256), 0, s, node0, p.nx, p.ny, p.periodic, node);
+    hipLaunchKernelGGL(k_tileflags, dim3(P.ntiles), dim3(256), 0, s, P.cls, p.nx, p.ny, ty, P.I.tiles_x, tflag);
+    if (p.storage == LBM_STORE_F16)
+        hipLaunchKernelGGL(k_init<__half>, dim3(nb), dim3(256), 0, s, P.I, drA, drB, (double)P.I.rrefA,
+                           (double)P.I.rrefB, 0);
+    else
+        hipLaunchKernelGGL(k_init<float>, dim3(nb), dim3(256), 0, s, P.I, drA, drB, (double)P.I.rrefA,
+                           (double)P.I.rrefB, 0);
+    MCLBM_HIP(hipGetLastError());
+    // drift threshold off in batched forms; step-0 mass recorded by the first fields pass
+    launch_step(Launch{p.storage, ty, p.bc, MODE_FIELDS, true}, s, P.I, 0, Fields{}, P.partials, P.dd, 0);
+    MCLBM_HIP(hipGetLastError());
+    return LBM_OK;
+}
+
+// Fields of a prepared instance at buffer parity `parity` into host arrays.
+int read_fields(Prepared &P, int parity, long long step, hipStream_t s, double *out[4]) {
+    const size_t n = (size_t)P.p.nx * P.p.ny;
+    Fields fo{};
+    fo.rhoA = P.fields;
+    fo.rhoB = P.fields + n;
+    fo.ux = P.fields + 2 * n;
+    fo.uy = P.fields + 3 * n;
+    launch_step(Launch{P.p.storage, P.ty, P.p.bc, MODE_FIELDS, true}, s, P.I, parity, fo, P.partials, P.dd, step);
+    MCLBM_HIP(hipGetLastError());
+    std::vector<float> tmp(n);
+    for (int q = 0; q < 4; ++q) {
+        if (!out[q]) continue;
+        MCLBM_HIP(hipMemcpyAsync(tmp.data(), P.fields + q * n, n * sizeof(float), hipMemcpyDeviceToHost, s));
+        MCLBM_HIP(hipStreamSynchronize(s));
+        for (size_t k = 0; k < n; ++k) out[q][k] = (double)tmp[k];
+    }
+    MCLBM_HIP(hipStreamSynchronize(s));
+    return LBM_OK;
+}
+
+int read_diag(Prepared &P, int parity, long long step, hipStream_t s, lbm_diag_t *out) {
+    launch_step(Launch{P.p.storage, P.ty, P.p.bc, MODE_FIELDS, true}, s, P.I, parity, Fields{}, P.partials, P.dd,
+                step);
+    MCLBM_HIP(hipGetLastError());
+    DiagDev d;
+    MCLBM_HIP(hipMemcpyAsync(&d, P.dd, sizeof d, hipMemcpyDeviceToHost, s));
+    MCLBM_HIP(hipStreamSynchronize(s));
+    out->mass[0] = d.mass[0];
+    out->mass[1] = d.mass[1];
+    out->mass0[0] = d.mass0[0];
+    out->mass0[1] = d.mass0[1];
+    out->momentum[0] = d.mom[0];
+    out->momentum[1] = d.mom[1];
+    out->max_speed = d.max_speed;
+    out->step = step;
+    out->flags = d.flags;
+    out->pad = 0;
+    return d.flags ? LBM_ENUMERIC : LBM_OK;
+}
+
+// Temporary upload buffers sized for the largest instance of a create/admit call.
+struct Staging {
+    uint8_t *mask = nullptr, *node0 = nullptr;
+    double *rA = nullptr, *rB = nullptr;
+    size_t cap = 0;
+    int ensure(size_t n) {
+        if (n <= cap) return LBM_OK;
+        release();
+        MCLBM_HIP(hipMalloc(&mask, n));
+        MCLBM_HIP(hipMalloc(&node0, n));
+        MCLBM_HIP(hipMalloc(&rA, n * sizeof(double)));
+        MCLBM_HIP(hipMalloc(&rB, n * sizeof(double)));
+        cap = n;
+        return LBM_OK;
+    }
+    void release() {
+        for (void *q : {(void *)mask, (void *)node0, (void *)rA, (void *)rB})
+            if (q) (void)hipFree(q);
+        mask = node0 = nullptr;
+        rA = rB = nullptr;
+        cap = 0;
+    }
+};
+
+}  // namespace
+
+// =====================================================================  batch
+
+struct lbm_batch {
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int storage = 0, ty = 8;
+    std::vector<Prepared> inst;
+    std::vector<char *> blocks;
+    Inst *d_inst = nullptr;
+    int2 *d_tiles = nullptr;
+    int ntiles = 0;
+    int64_t t = 0;
+    int64_t fluid = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    int glen = 0;
+};
+
+static void batch_release(lbm_batch *b) {
+    if (!b) return;
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    for (char *q : b->blocks)
+        if (q) (void)hipFree(q);
+    if (b->d_inst) (void)hipFree(b->d_inst);
+    if (b->d_tiles) (void)hipFree(b->d_tiles);
+    if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
+    delete b;
+}
+
+extern "C" {
+
+int lbm_batch_create(int32_t n, const lbm_params *params, const uint8_t *const *masks, const double *const *rhoA0,
+                     const double *const *rhoB0, void *stream, int32_t graph_steps, lbm_batch **out) {
+    if (!out || n < 1 || !params || !masks || !rhoA0 || !rhoB0 || graph_steps < 0) {
+        set_err("bad batch arguments");
+        return LBM_EINVAL;
+    }
+    *out = nullptr;
+    for (int k = 0; k < n; ++k) {
+        int rc = validate(&params[k], masks[k], rhoA0[k], rhoB0[k]);
+        if (rc) return rc;
+        if (params[k].storage != params[0].storage || default_ty(params[k]) != default_ty(params[0])) {
+            set_err("instance %d: every instance of a batch uses the same storage and tile rows", k);
+            return LBM_EINVAL;
+        }
+    }
+    lbm_batch *b = new lbm_batch();
+    b->storage = params[0].storage;
+    b->ty = default_ty(params[0]);
+    b->stream = (hipStream_t)stream;
+    auto bail = [&](int code) {
+        batch_release(b);
+        return code;
+    };
+    if (!b->stream) {
+        if (hipStreamCreate(&b->stream) != hipSuccess) {
+            set_err("hipStreamCreate failed");
+            return bail(LBM_EDEVICE);
+        }
+        b->own_stream = true;
+    }
+    Staging st;
+    size_t maxn = 0;
+    for (int k = 0; k < n; ++k) maxn = std::max(maxn, (size_t)params[k].nx * params[k].ny);
+    int rc = st.ensure(maxn);
+    if (rc) {
+        st.release();
+        return bail(rc);
+    }
+    b->inst.resize(n);
+    std::vector<int2> tiles;
+    std::vector<Inst> host_inst(n);
+    for (int k = 0; k < n; ++k) {
+        lbm_params p = params[k];
+        InstMem m = layout(p, b->ty);
+        char *base = nullptr;
+        if (hipMalloc(&base, m.bytes) != hipSuccess) {
+            set_err("instance %d: hipMalloc(%zu) failed", k, m.bytes);
+            st.release();
+            return bail(LBM_ENOMEM);
+        }
+        b->blocks.push_back(base);
+        rc = prepare(b->inst[k], p, b->ty, base, masks[k], rhoA0[k], rhoB0[k], b->stream, st.mask, st.node0, st.rA,
+                     st.rB);
+        if (rc == LBM_OK && hipStreamSynchronize(b->stream) != hipSuccess) rc = LBM_EDEVICE;
+        if (rc) {
+            st.release();
+            return bail(rc);
+        }
+        host_inst[k] = b->inst[k].I;
+        b->fluid += b->inst[k].fluid;
+        for (int t = 0; t < b->inst[k].ntiles; ++t) tiles.push_back(make_int2(k, t));
+    }
+    st.release();
+    b->ntiles = (int)tiles.size();
+    if (hipMalloc(&b->d_inst, sizeof(Inst) * n) != hipSuccess ||
+        hipMalloc(&b->d_tiles, sizeof(int2) * tiles.size()) != hipSuccess) {
+        set_err("batch tables: hipMalloc failed");
+        return bail(LBM_ENOMEM);
+    }
+    if (hipMemcpy(b->d_inst, host_inst.data(), sizeof(Inst) * n, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(b->d_tiles, tiles.data(), sizeof(int2) * tiles.size(), hipMemcpyHostToDevice) != hipSuccess) {
+        set_err("batch tables: upload failed");
+        return bail(LBM_EDEVICE);
+    }
+    if (graph_steps > 0) {
+        const int K = (graph_steps + 1) / 2 * 2;
+        if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeRelaxed) != hipSuccess) {
+            set_err("graph capture failed");
+            return bail(LBM_EDEVICE);
+        }
+        for (int s = 0; s < K; ++s) launch_batch(b->storage, b->ty, b->stream, b->ntiles, b->d_inst, b->d_tiles, s & 1, 0);
+        if (hipStreamEndCapture(b->stream, &b->graph) != hipSuccess ||
+            hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0) != hipSuccess) {
+            set_err("graph instantiate failed");
+            return bail(LBM_EDEVICE);
+        }
+        b->glen = K;
+    }
+    *out = b;
+    return LBM_OK;
+}
+
+int lbm_batch_step(lbm_batch *b, int64_t nsteps) {
+    if (!b || nsteps < 0) return LBM_EINVAL;
+    while (nsteps > 0) {
+        if (b->gexec && (b->t & 1) == 0 && nsteps >= b->glen) {
+            MCLBM_HIP(hipGraphLaunch(b->gexec, b->stream));
+            b->t += b->glen;
+            nsteps -= b->glen;
+            continue;
+        }
+        launch_batch(b->storage, b->ty, b->stream, b->ntiles, b->d_inst, b->d_tiles, (int)(b->t & 1), 0);
+        b->t += 1;
+        nsteps -= 1;
+    }
+    MCLBM_HIP(hipGetLastError());
+    return LBM_OK;
+}
+
+int lbm_batch_fields(lbm_batch *b, int32_t idx, double *rhoA, double *rhoB, double *ux, double *uy) {
+    if (!b || idx < 0 || idx >= (int)b->inst.size()) return LBM_EINVAL;
+    double *outs[4] = {rhoA, rhoB, ux, uy};
+    return read_fields(b->inst[idx], (int)(b->t & 1), b->t, b->stream, outs);
+}
+
+int lbm_batch_diag(lbm_batch *b, int32_t idx, lbm_diag_t *out) {
+    if (!b || !out || idx < 0 || idx >= (int)b->inst.size()) return LBM_EINVAL;
+    return read_diag(b->inst[idx], (int)(b->t & 1), b->t, b->stream, out);
+}
+
+int64_t lbm_batch_fluid_nodes(const lbm_batch *b) { return b ? b->fluid : -1; }
+
+int lbm_batch_destroy(lbm_batch *b) {
+    batch_release(b);
+    return LBM_OK;
+}
+
+}  // extern "C"
+
+// =====================================================================  pool
+
+namespace {
+
+// First-fit allocator over one device arena.
+struct Arena {
+    char *base = nullptr;
+    size_t size = 0;
+    std::map<size_t, size_t> free_;  // offset -> length
+    void init(char *b, size_t n) {
+        base = b;
+        size = n;
+        free_.clear();
+        free_[0] = n;
+    }
+    bool alloc(size_t n, size_t *off) {
+        n = al(n);
+        for (auto it = free_.begin(); it != free_.end(); ++it)
+            if (it->second >= n) {
+                *off = it->first;
+                const size_t rest = it->second - n, o = it->first + n;
+                free_.erase(it);
+                if (rest) free_[o] = rest;
+                return true;
+            }
+        return false;
+    }
+    void release(size_t off, size_t n) {
+        n = al(n);
+        auto it = free_.emplace(off, n).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+};
+
+struct Slot {
+    bool used = false;
+    bool joined = false;    // part of the launched tile list
+    bool released = true;
+    Prepared P;
+    size_t off = 0, bytes = 0;
+    int64_t nsteps = 0;
+    int64_t L0 = 0;         // pool launch counter at which the slot joined
+    hipEvent_t ready = nullptr;  // set-up finished on the init stream
+};
+
+}  // namespace
+
+struct lbm_pool {
+    hipStream_t stream = nullptr, init_stream = nullptr;
+    bool own_stream = false;
+    int storage = 0, ty = 8, max_slots = 0;
+    Arena arena;
+    size_t in_use = 0;
+    std::vector<Slot> slots;
+    Inst *d_inst = nullptr;
+    int2 *d_tiles = nullptr;
+    size_t tiles_cap = 0;
+    int ntiles = 0;
+    bool dirty = false;
+    int64_t L = 0;  // launches enqueued so far
+    std::deque<std::pair<int64_t, hipEvent_t>> marks;  // (launch count reached, event)
+    int64_t L_done = 0;                                  // launches known complete
+    Staging st;
+    Inst *h_inst = nullptr;   // pinned staging of the slot table
+    int2 *h_tiles = nullptr;  // pinned staging of the tile list
+    hipEvent_t upload_done = nullptr;
+};
+
+static void pool_release_all(lbm_pool *P) {
+    if (!P) return;
+    if (P->stream) (void)hipStreamSynchronize(P->stream);
+    if (P->init_stream) (void)hipStreamSynchronize(P->init_stream);
+    for (auto &m : P->marks) (void)hipEventDestroy(m.second);
+    for (auto &s : P->slots)
+        if (s.ready) (void)hipEventDestroy(s.ready);
+    if (P->upload_done) (void)hipEventDestroy(P->upload_done);
+    P->st.release();
+    if (P->arena.base) (void)hipFree(P->arena.base);
+    if (P->d_inst) (void)hipFree(P->d_inst);
+    if (P->d_tiles) (void)hipFree(P->d_tiles);
+    if (P->h_inst) (void)hipHostFree(P->h_inst);
+    if (P->h_tiles) (void)hipHostFree(P->h_tiles);
+    if (P->init_stream) (void)hipStreamDestroy(P->init_stream);
+    if (P->own_stream && P->stream) (void)hipStreamDestroy(P->stream);
+    delete P;
+}
+
+// Re-uploads the slot table and tile list, in stream order after all launches
+// already enqueued (they keep reading the previous contents until then).
+static int pool_upload(lbm_pool *P) {
+    MCLBM_HIP(hipEventSynchronize(P->upload_done));  // previous upload has left the staging buffers
+    std::vector<int2> tiles;
+    for (int k = 0; k < P->max_slots; ++k) {
+        Slot &s = P->slots[k];
+        if (!s.used || !s.joined) continue;
+        P->h_inst[k] = s.P.I;
+        for (int t = 0; t < s.P.ntiles; ++t) tiles.push_back(make_int2(k, t));
+    }
+    if (tiles.size() > P->tiles_cap) {
+        // grow: wait for launches that read the old list, then reallocate
+        MCLBM_HIP(hipStreamSynchronize(P->stream));
+        if (P->d_tiles) (void)hipFree(P->d_tiles);
+        if (P->h_tiles) (void)hipHostFree(P->h_tiles);
+        P->d_tiles = nullptr;
+        P->h_tiles = nullptr;
+        const size_t cap = std::max(tiles.size() * 2, (size_t)4096);
+        MCLBM_HIP(hipMalloc(&P->d_tiles, cap * sizeof(int2)));
+        MCLBM_HIP(hipHostMalloc((void **)&P->h_tiles, cap * sizeof(int2), hipHostMallocDefault));
+        P->tiles_cap = cap;
+    }
+    std::copy(tiles.begin(), tiles.end(), P->h_tiles);
+    MCLBM_HIP(hipMemcpyAsync(P->d_inst, P->h_inst, sizeof(Inst) * P->max_slots, hipMemcpyHostToDevice, P->stream));
+    if (!tiles.empty())
+        MCLBM_HIP(hipMemcpyAsync(P->d_tiles, P->h_tiles, sizeof(int2) * tiles.size(), hipMemcpyHostToDevice,
+                                 P->stream));
+    MCLBM_HIP(hipEventRecord(P->upload_done, P->stream));
+    P->ntiles = (int)tiles.size();
+    P->dirty = false;
+    return LBM_OK;
+}
+
+static void pool_reap_marks(lbm_pool *P) {
+    while (!P->marks.empty() && hipEventQuery(P->marks.front().second) == hipSuccess) {
+        P->L_done = P->marks.front().first;
+        (void)hipEventDestroy(P->marks.front().second);
+        P->marks.pop_front();
+    }
+}
+
+extern "C" {
+
+size_t lbm_pool_footprint(const lbm_params *p) {
+    if (!p || p->nx < 1 || p->ny < 1) return 0;
+    return layout(*p, default_ty(*p)).bytes;
+}
+
+int lbm_pool_create(size_t hbm_budget, int32_t max_slots, int32_t storage, void *stream, lbm_pool **out) {
+    if (!out || max_slots < 1 || hbm_budget < 4096 || storage < 0 || storage > 1) {
+        set_err("bad pool arguments");
+        return LBM_EINVAL;
+    }
+    *out = nullptr;
+    lbm_pool *P = new lbm_pool();
+    P->storage = storage;
+    P->max_slots = max_slots;
+    P->slots.resize(max_slots);
+    P->stream = (hipStream_t)stream;
+    auto bail = [&](int code) {
+        pool_release_all(P);
+        return code;
+    };
+    if (!P->stream) {
+        if (hipStreamCreate(&P->stream) != hipSuccess) return bail(LBM_EDEVICE);
+        P->own_stream = true;
+    }
+    if (hipStreamCreateWithFlags(&P->init_stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&P->upload_done, hipEventDisableTiming) != hipSuccess) {
+        set_err("pool streams/events failed");
+        return bail(LBM_EDEVICE);
+    }
+    char *base = nullptr;
+    if (hipMalloc(&base, hbm_budget) != hipSuccess) {
+        set_err("pool arena hipMalloc(%zu) failed", hbm_budget);
+        return bail(LBM_ENOMEM);
+    }
+    P->arena.init(base, hbm_budget);
+    if (hipMalloc(&P->d_inst, sizeof(Inst) * max_slots) != hipSuccess ||
+        hipHostMalloc((void **)&P->h_inst, sizeof(Inst) * max_slots, hipHostMallocDefault) != hipSuccess) {
+        set_err("pool tables failed");
+        return bail(LBM_ENOMEM);
+    }
+    std::memset((void *)P->h_inst, 0, sizeof(Inst) * max_slots);
+    if (hipEventRecord(P->upload_done, P->stream) != hipSuccess) return bail(LBM_EDEVICE);
+    *out = P;
+    return LBM_OK;
+}
+
+int lbm_pool_admit(lbm_pool *P, const lbm_params *p, const uint8_t *mask, const double *rhoA0, const double *rhoB0,
+                   int64_t nsteps, int32_t *slot) {
+    if (!P || !slot || nsteps < 0) return LBM_EINVAL;
+    int rc = validate(p, mask, rhoA0, rhoB0);
+    if (rc) return rc;
+    if (p->storage != P->storage) {
+        set_err("pool storage is %d, request asks for %d", P->storage, p->storage);
+        return LBM_EINVAL;
+    }
+    if (default_ty(*p) != P->ty) {
+        set_err("pool tiles have %d rows", P->ty);
+        return LBM_EINVAL;
+    }
+    int k = -1;
+    for (int q = 0; q < P->max_slots; ++q)
+        if (!P->slots[q].used) {
+            k = q;
+            break;
+        }
+    if (k < 0) {
+        set_err("all %d slots busy", P->max_slots);
+        return LBM_EAGAIN;
+    }
+    const InstMem m = layout(*p, P->ty);
+    size_t off;
+    if (!P->arena.alloc(m.bytes, &off)) {
+        set_err("HBM budget: %zu bytes needed, %zu of %zu in use", m.bytes, P->in_use, P->arena.size);
+        return LBM_EAGAIN;
+    }
+    Slot &s = P->slots[k];
+    // set-up on the init stream overlaps the running batch
+    const size_t n = (size_t)p->nx * p->ny;
+    MCLBM_HIP(hipStreamSynchronize(P->init_stream));  // staging reuse
+    rc = P->st.ensure(n);
+    if (rc) {
+        P->arena.release(off, m.bytes);
+        return rc;
+    }
+    rc = prepare(s.P, *p, P->ty, P->arena.base + off, mask, rhoA0, rhoB0, P->init_stream, P->st.mask, P->st.node0,
+                 P->st.rA, P->st.rB);
+    if (rc) {
+        P->arena.release(off, m.bytes);
+        return rc;
+    }
+    if (!s.ready) MCLBM_HIP(hipEventCreateWithFlags(&s.ready, hipEventDisableTiming));
+    MCLBM_HIP(hipEventRecord(s.ready, P->init_stream));
+    // host inputs were copied with pageable memcpy: wait until they are read before returning
+    MCLBM_HIP(hipStreamSynchronize(P->init_stream));
+    s.used = true;
+    s.joined = false;
+    s.released = false;
+    s.off = off;
+    s.bytes = m.bytes;
+    s.nsteps = nsteps;
+    P->in_use += al(m.bytes);
+    *slot = k;
+    return LBM_OK;
+}
+
+int lbm_pool_advance(lbm_pool *P, int64_t chunk) {
+    if (!P || chunk < 0) return LBM_EINVAL;
+    pool_reap_marks(P);
+    // slots admitted since the last advance join at the next launch
+    for (int k = 0; k < P->max_slots; ++k) {
+        Slot &s = P->slots[k];
+        if (!s.used || s.joined) continue;
+        MCLBM_HIP(hipStreamWaitEvent(P->stream, s.ready, 0));
+        s.L0 = P->L;
+        s.P.I.parity0 = (int)(P->L & 1);
+        s.P.I.t_end = P->L + s.nsteps;
+        s.joined = true;
+        P->dirty = true;
+    }
+    if (P->dirty) {
+        int rc = pool_upload(P);
+        if (rc) return rc;
+    }
+    // launch only while some slot still has steps left
+    int64_t last_end = P->L;
+    for (auto &s : P->slots)
+        if (s.used && s.joined) last_end = std::max(last_end, s.P.I.t_end);
+    const int64_t n = std::min(chunk, last_end - P->L);
+    for (int64_t q = 0; q < n; ++q) {
+        launch_batch(P->storage, P->ty, P->stream, P->ntiles, P->d_inst, P->d_tiles, (int)(P->L & 1),
+                     (long long)P->L);
+        P->L += 1;
+    }
+    MCLBM_HIP(hipGetLastError());
+    if (n > 0) {
+        hipEvent_t e;
+        MCLBM_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        MCLBM_HIP(hipEventRecord(e, P->stream));
+        P->marks.emplace_back(P->L, e);
+    }
+    return LBM_OK;
+}
+
+int lbm_pool_poll(lbm_pool *P, int32_t *slots, int32_t max, int32_t *n) {
+    if (!P || !n || (max > 0 && !slots)) return LBM_EINVAL;
+    pool_reap_marks(P);
+    int c = 0;
+    for (int k = 0; k < P->max_slots && c < max; ++k) {
+        const Slot &s = P->slots[k];
+        if (s.used && s.joined && s.P.I.t_end <= P->L_done) slots[c++] = k;
+    }
+    *n = c;
+    return LBM_OK;
+}
+
+int lbm_pool_fields(lbm_pool *P, int32_t k, double *rhoA, double *rhoB, double *ux, double *uy) {
+    if (!P || k < 0 || k >= P->max_slots) return LBM_EINVAL;
+    Slot &s = P->slots[k];
+    if (!s.used || !s.joined) return LBM_ENOTFOUND;
+    // finished: the final buffer is the one the launch at t_end would read; else the current one
+    const int64_t Lr = std::min(P->L, s.P.I.t_end);
+    const int parity = (int)((s.P.I.parity0 ^ (Lr & 1)) & 1);
+    double *outs[4] = {rhoA, rhoB, ux, uy};
+    return read_fields(s.P, parity, (long long)(Lr - s.L0), P->stream, outs);
+}
+
+int lbm_pool_release(lbm_pool *P, int32_t k) {
+    if (!P || k < 0 || k >= P->max_slots) return LBM_EINVAL;
+    Slot &s = P->slots[k];
+    if (!s.used) return LBM_ENOTFOUND;
+    if (!(s.joined && s.P.I.t_end <= P->L_done)) {
+        // cancelling a running solve: its blocks may still be in flight
+        MCLBM_HIP(hipStreamSynchronize(P->stream));
+        MCLBM_HIP(hipStreamSynchronize(P->init_stream));
+    }
+    P->arena.release(s.off, s.bytes);
+    P->in_use -= al(s.bytes);
+    s.used = false;
+    s.joined = false;
+    s.released = true;
+    P->dirty = true;
+    return LBM_OK;
+}
+
+int lbm_pool_stats(const lbm_pool *P, int32_t *active, size_t *bytes_in_use) {
+    if (!P) return LBM_EINVAL;
+    int a = 0;
+    for (auto &s : P->slots) a += s.used ? 1 : 0;
+    if (active) *active = a;
+    if (bytes_in_use) *bytes_in_use = P->in_use;
+    return LBM_OK;
+}
+
+int lbm_pool_destroy(lbm_pool *P) {
+    pool_release_all(P);
+    return LBM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,393 @@
+// Host-side pieces shared by the single, batched and pooled forms: set-up
+// kernels (classification, near-wall flags, tile flags, initial populations),
+// kernel dispatch over the template parameters, and parameter validation.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <algorithm>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/mclbm.h"
+#include "lbm_device.hpp"
+
+namespace mclbm {
+
+#define MCLBM_HIP(call)                                                                     \
+    do {                                                                                    \
+        hipError_t e_ = (call);                                                             \
+        if (e_ != hipSuccess) {                                                             \
+            set_err("%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), __FILE__, __LINE__); \
+            return LBM_EDEVICE;                                                             \
+        }                                                                                   \
+    } while (0)
+
+// thread-local detail of the last error raised outside a handle
+inline std::string &tls_err() {
+    static thread_local std::string s;
+    return s;
+}
+inline void set_err(const char *fmt, ...) {
+    char b[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(b, sizeof b, fmt, ap);
+    va_end(ap);
+    tls_err() = b;
+}
+
+inline int pitch_of(int nx) { return (nx + 63) / 64 * 64; }
+inline int default_ty(const lbm_params &p) { return p.tile_y > 0 ? p.tile_y : 8; }
+inline size_t store_bytes(int storage) { return storage == LBM_STORE_F16 ? 2 : 4; }
+
+// Bytes of device memory one simulation holds (two population buffers, node
+// flags, classification, tile flags, diagnostic partials and targets).
+inline size_t footprint_bytes(const lbm_params &p) {
+    const size_t n = (size_t)p.nx * p.ny;
+    const size_t plane = (size_t)p.ny * pitch_of(p.nx);
+    const int ty = default_ty(p);
+    const size_t tiles = (size_t)((p.nx + TX - 1) / TX) * ((p.ny + ty - 1) / ty);
+    return 2 * 18 * plane * store_bytes(p.storage) + 3 * n + tiles + tiles * 48 + sizeof(DiagDev) + 4096;
+}
+
+// Validation of everything that can be checked on the host before any device
+// call (Section 2: tau > 1/2; Section 3.1: closed borders are solid walls).
+inline int validate(const lbm_params *p, const uint8_t *mask, const double *rA, const double *rB) {
+    if (!p || !mask || !rA || !rB) {
+        set_err("null argument");
+        return LBM_EINVAL;
+    }
+    if (p->nx < 1 || p->ny < 1) {
+        set_err("grid %d x %d: both sizes must be >= 1", p->nx, p->ny);
+        return LBM_EINVAL;
+    }
+    // one component's 9 planes are addressed with 32-bit byte offsets
+    if ((double)p->ny * pitch_of(p->nx) * 9.0 * (double)store_bytes(p->storage) >= 4294967296.0) {
+        set_err("grid %d x %d: one component exceeds 4 GiB of populations", p->nx, p->ny);
+        return LBM_EINVAL;
+    }
+    if (!(p->tau > 0.5) || !std::isfinite(p->tau)) {
+        set_err("tau = %g: must be finite and > 1/2", p->tau);
+        return LBM_EINVAL;
+    }
+    if (!std::isfinite(p->G) || !std::isfinite(p->G_w) || !std::isfinite(p->chi[0]) ||
+        !std::isfinite(p->chi[1])) {
+        set_err("non-finite G, G_w or chi");
+        return LBM_EINVAL;
+    }
+    if (p->bc < 0 || p->bc > 2 || p->avg < 0 || p->avg > 1 || p->storage < 0 || p->storage > 1) {
+        set_err("bc %d / avg %d / storage %d out of range", p->bc, p->avg, p->storage);
+        return LBM_EINVAL;
+    }
+    if (p->periodic > 3u) {
+        set_err("periodic = %u: only bits 0 and 1 may be set", p->periodic);
+        return LBM_EINVAL;
+    }
+    if (p->tile_y != 0 && p->tile_y != 4 && p->tile_y != 8 && p->tile_y != 16) {
+        set_err("tile_y = %d: must be 0, 4, 8 or 16", p->tile_y);
+        return LBM_EINVAL;
+    }
+    if (p->diag_every < 0 || p->graph_steps < 0) {
+        set_err("diag_every and graph_steps must be >= 0");
+        return LBM_EINVAL;
+    }
+    const int nx = p->nx, ny = p->ny;
+    size_t nfluid = 0;
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            const size_t k = (size_t)y * nx + x;
+            if (mask[k]) continue;
+            ++nfluid;
+            if (!(p->periodic & 1u) && (x == 0 || x == nx - 1)) {
+                set_err("fluid node (%d,%d) on a non-periodic x border", x, y);
+                return LBM_EINVAL;
+            }
+            if (!(p->periodic & 2u) && (y == 0 || y == ny - 1)) {
+                set_err("fluid node (%d,%d) on a non-periodic y border", x, y);
+                return LBM_EINVAL;
+            }
+            const double a = rA[k], b = rB[k];
+            if (!std::isfinite(a) || !std::isfinite(b) || a < 0.0 || b < 0.0 || !(a + b > 0.0)) {
+                set_err("initial densities at (%d,%d) = (%g, %g): need finite, >= 0, sum > 0", x, y, a, b);
+                return LBM_EINVAL;
+            }
+        }
+    (void)nfluid;
+    return LBM_OK;
+}
+
+// Deviation references: the caller's, or per component the smallest initial
+// density over fluid nodes.  A component's populations then stay near zero in
+// the phase where it is the minority (0.03 against 1.0 in the paper's set-ups),
+// so FP32 and FP16 rounding is relative to that small density rather than to
+// a volume mean 30 times larger.
+inline void resolve_rref(const lbm_params &p, const uint8_t *mask, const double *rA, const double *rB,
+                         double out[2]) {
+    double lo[2] = {INFINITY, INFINITY};
+    const size_t N = (size_t)p.nx * p.ny;
+    for (size_t k = 0; k < N; ++k)
+        if (!mask[k]) {
+            lo[0] = std::min(lo[0], rA[k]);
+            lo[1] = std::min(lo[1], rB[k]);
+        }
+    for (int c = 0; c < 2; ++c) {
+        if (!std::isfinite(lo[c])) lo[c] = 0.0;
+        out[c] = std::isnan(p.rho_ref[c]) ? lo[c] : p.rho_ref[c];
+    }
+}
+
+inline void fill_inst(Inst &I, const lbm_params &p, const double rref[2], int ty) {
+    I.nx = p.nx;
+    I.ny = p.ny;
+    I.pitch = pitch_of(p.nx);
+    I.tiles_x = (p.nx + TX - 1) / TX;
+    I.tiles_y = (p.ny + ty - 1) / ty;
+    I.plane = (int64_t)p.ny * I.pitch;
+    I.periodic = p.periodic;
+    // the compare-and-add wrap covers excursions of a tile plus halo; shorter
+    // periodic sizes wrap by modulo
+    I.small = (((p.periodic & 1u) && p.nx < TX + 2 * FH + 8) || ((p.periodic & 2u) && p.ny < 16 + 2 * FH + 8)) ? 1 : 0;
+    I.bc = p.bc;
+    I.avg = p.avg;
+    I.omega = (float)(1.0 / p.tau);
+    I.guo = (float)(1.0 - 1.0 / (2.0 * p.tau));
+    I.G = (float)p.G;
+    if (p.bc == LBM_BC_VIRTUAL_IMPROVED) {
+        // virtual-density schemes use G_{sigma s} = G_{sigma sigma-bar} (Section 2)
+        I.GsA = (float)p.G;
+        I.GsB = (float)p.G;
+    } else {
+        I.GsA = (float)p.G_w;
+        I.GsB = (float)(-p.G_w);
+    }
+    I.chiA = (float)p.chi[0];
+    I.chiB = (float)p.chi[1];
+    I.rrefA = (float)rref[0];
+    I.rrefB = (float)rref[1];
+    I.parity0 = 0;
+    I.t_end = INT64_MAX;
+}
+
+// ---------------------------------------------------------------- set-up kernels
+
+// Stair classification and node flags (Fig. 1A caption; Sections 3.1, 3.2).
+static __global__ void k_classify(const uint8_t *__restrict__ mask, int nx, int ny, uint32_t periodic,
+                           uint8_t *__restrict__ nbr, uint8_t *__restrict__ cls, uint8_t *__restrict__ node) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= (int64_t)nx * ny) return;
+    const int x = (int)(k % nx), y = (int)(k / nx);
+    unsigned bits = 0;
+#pragma unroll
+    for (int i = 1; i < 9; ++i) {
+        int xn = x + CX[i], yn = y + CY[i];
+        bool outside = false;
+        if (xn < 0 || xn >= nx) {
+            if (periodic & 1u) xn = wrap(xn, nx, true);
+            else outside = true;
+        }
+        if (yn < 0 || yn >= ny) {
+            if (periodic & 2u) yn = wrap(yn, ny, true);
+            else outside = true;
+        }
+        if (outside || mask[(int64_t)yn * nx + xn]) bits |= 1u << (i - 1);
+    }
+    const bool solid = mask[k] != 0;
+    const uint8_t c = solid ? (bits != 0xFFu ? 2 : 3) : (bits ? 1 : 0);
+    nbr[k] = (uint8_t)bits;
+    cls[k] = c;
+    node[k] = solid ? (uint8_t)(NF_SOLID | (c == 2 ? NF_IFACE : 0)) : (uint8_t)0;
+}
+
+// Fluid nodes within Chebyshev distance 2 of an interface solid: the only
+// fluid nodes whose density enters an Eq. 7 average.
+static __global__ void k_near(const uint8_t *__restrict__ node_in, int nx, int ny, uint32_t periodic,
+                       uint8_t *__restrict__ node_out) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= (int64_t)nx * ny) return;
+    const int x = (int)(k % nx), y = (int)(k / nx);
+    uint8_t f = node_in[k];
+    if (!(f & NF_SOLID)) {
+        bool near = false;
+        for (int dy = -2; dy <= 2 && !near; ++dy)
+            for (int dx = -2; dx <= 2; ++dx) {
+                int xn = x + dx, yn = y + dy;
+                if (xn < 0 || xn >= nx) {
+                    if (!(periodic & 1u)) continue;
+                    xn = wrap(xn, nx, true);
+                }
+                if (yn < 0 || yn >= ny) {
+                    if (!(periodic & 2u)) continue;
+                    yn = wrap(yn, ny, true);
+                }
+                if (node_in[(int64_t)yn * nx + xn] & NF_IFACE) {
+                    near = true;
+                    break;
+                }
+            }
+        if (near) f |= NF_NEAR;
+    }
+    node_out[k] = f;
+}
+
+// Per tile: does an owned fluid node touch a solid (then the improved scheme
+// needs virtual densities, and the 3-node halo, in this tile)?
+static __global__ void k_tileflags(const uint8_t *__restrict__ cls, int nx, int ny, int ty, int tiles_x,
+                            uint8_t *__restrict__ tflag) {
+    const int t = blockIdx.x;
+    const int x0 = (t % tiles_x) * TX, y0 = (t / tiles_x) * ty;
+    int hit = 0;
+    for (int k = threadIdx.x; k < TX * ty; k += blockDim.x) {
+        const int x = x0 + k % TX, y = y0 + k / TX;
+        if (x < nx && y < ny && cls[(int64_t)y * nx + x] == 1) hit = 1;
+    }
+    hit = __syncthreads_or(hit);
+    if (threadIdx.x == 0) tflag[t] = hit ? TF_NEEDS_RT : 0;
+}
+
+// Initial buffer such that the first pull yields f_i(x, 0) = w_i rho_0(x):
+// d*_j(y) = w_j (rho_0(y + c_j) - rho_ref) when y + c_j is fluid, else
+// w_j (rho_0(y) - rho_ref) (the value bounce-back returns to y).
+template <typename S>
+__global__ void k_init(Inst I, const double *__restrict__ rA, const double *__restrict__ rB, double rrefA,
+                       double rrefB, int which) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= (int64_t)I.nx * I.ny) return;
+    const int x = (int)(k % I.nx), y = (int)(k / I.nx);
+    if (I.node[k] & NF_SOLID) return;
+    S *b = (S *)I.buf[which];
+    const int64_t own = (int64_t)y * I.pitch + x;
+    const double wd[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+    for (int j = 0; j < 9; ++j) {
+        const int xs = wrap(x + CX[j], I.nx, true), ys = wrap(y + CY[j], I.ny, true);
+        int64_t src = (int64_t)ys * I.nx + xs;
+        if (I.node[src] & NF_SOLID) src = k;
+        Store<S>::put(b + (int64_t)j * I.plane + own, Store<S>::enc((float)(wd[j] * (rA[src] - rrefA))));
+        Store<S>::put(b + (int64_t)(9 + j) * I.plane + own, Store<S>::enc((float)(wd[j] * (rB[src] - rrefB))));
+    }
+}
+
+// ---------------------------------------------------------------- step kernels
+
+// Tile index for a block: consecutive blocks go round-robin to the 8 XCDs, so
+// block b is mapped to the b/8-th tile of the contiguous band of tiles given
+// to XCD b%8.  Neighbouring tiles then share an L2, and each XCD keeps the
+// same band from step to step.
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+    const int q = nb >> 3, r = nb & 7, x = b & 7;
+    return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + (b >> 3);
+}
+
+template <typename S, int TY, int BC, int MODE, bool DIAG>
+__global__ __launch_bounds__(NT) void k_step(Inst I, int parity, Fields fo, double *partials) {
+    __shared__ Smem<TY> sm;
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    DiagAcc acc;
+    process_tile<S, TY, BC, MODE, DIAG>(I, t % I.tiles_x, t / I.tiles_x, parity, sm, acc, fo);
+    if (DIAG) diag_partial<TY>(sm, acc, partials, blockIdx.x);
+}
+
+// Final FP64 reduction of the per-tile partials in a fixed order, the drift
+// check against step 0 and the sticky failure flags.  One block.
+static __global__ __launch_bounds__(256) void k_diag_reduce(const double *__restrict__ partials, int nblocks,
+                                                            DiagDev *dd, long long step) {
+    __shared__ double red[256][5];
+    __shared__ int redi[256];
+    double s[4] = {0, 0, 0, 0}, m = 0.0;
+    int f = 0;
+    for (int b = threadIdx.x; b < nblocks; b += 256) {
+        const double *p = partials + (size_t)b * 6;
+        for (int q = 0; q < 4; ++q) s[q] += p[q];
+        m = fmax(m, p[4]);
+        f |= (int)p[5];
+    }
+    for (int q = 0; q < 4; ++q) red[threadIdx.x][q] = s[q];
+    red[threadIdx.x][4] = m;
+    redi[threadIdx.x] = f;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            for (int q = 0; q < 4; ++q) red[threadIdx.x][q] += red[threadIdx.x + w][q];
+            red[threadIdx.x][4] = fmax(red[threadIdx.x][4], red[threadIdx.x + w][4]);
+            redi[threadIdx.x] |= redi[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        int ff = redi[0];
+        dd->mass[0] = red[0][0];
+        dd->mass[1] = red[0][1];
+        dd->mom[0] = red[0][2];
+        dd->mom[1] = red[0][3];
+        dd->max_speed = sqrt(red[0][4]);
+        if (step >= 0) dd->step = step;
+        if (!dd->have_mass0) {
+            dd->mass0[0] = red[0][0];
+            dd->mass0[1] = red[0][1];
+            dd->have_mass0 = 1;
+        }
+        if (dd->drift_tol > 0.0)
+            for (int c = 0; c < 2; ++c) {
+                const double m0 = dd->mass0[c];
+                if (m0 > 0.0 && fabs(red[0][c] - m0) > dd->drift_tol * m0) ff |= 4;
+            }
+        dd->flags |= ff;
+    }
+}
+
+// Runtime dispatch over (storage, tile rows, BC, mode, diag).
+struct Launch {
+    int storage, ty, bc, mode;
+    bool diag;
+};
+
+template <typename S, int TY, int BC>
+inline void launch3(const Launch &L, dim3 g, hipStream_t s, const Inst &I, int parity, const Fields &fo,
+                    double *partials) {
+    if (L.mode == MODE_FIELDS)
+        hipLaunchKernelGGL((k_step<S, TY, BC, MODE_FIELDS, true>), g, dim3(NT), 0, s, I, parity, fo, partials);
+    else if (L.diag)
+        hipLaunchKernelGGL((k_step<S, TY, BC, MODE_STEP, true>), g, dim3(NT), 0, s, I, parity, fo, partials);
+    else
+        hipLaunchKernelGGL((k_step<S, TY, BC, MODE_STEP, false>), g, dim3(NT), 0, s, I, parity, fo, partials);
+}
+
+template <typename S, int TY>
+inline void launch2(const Launch &L, dim3 g, hipStream_t s, const Inst &I, int parity, const Fields &fo,
+                    double *partials) {
+    switch (L.bc) {
+    case BC_MC: launch3<S, TY, BC_MC>(L, g, s, I, parity, fo, partials); break;
+    case BC_LLKC: launch3<S, TY, BC_LLKC>(L, g, s, I, parity, fo, partials); break;
+    default: launch3<S, TY, BC_IMPROVED>(L, g, s, I, parity, fo, partials); break;
+    }
+}
+
+template <typename S>
+inline void launch1(const Launch &L, dim3 g, hipStream_t s, const Inst &I, int parity, const Fields &fo,
+                    double *partials) {
+    switch (L.ty) {
+    case 4: launch2<S, 4>(L, g, s, I, parity, fo, partials); break;
+    case 16: launch2<S, 16>(L, g, s, I, parity, fo, partials); break;
+    default: launch2<S, 8>(L, g, s, I, parity, fo, partials); break;
+    }
+}
+
+// One step (or fields pass) of one simulation; with diagnostics, followed by
+// the one-block reduction (step < 0 leaves the recorded time unchanged).
+inline void launch_step(const Launch &L, hipStream_t s, const Inst &I, int parity, const Fields &fo,
+                        double *partials, DiagDev *dd, long long step) {
+    const int nt = I.tiles_x * I.tiles_y;
+    dim3 g((unsigned)nt);
+    if (L.storage == LBM_STORE_F16)
+        launch1<__half>(L, g, s, I, parity, fo, partials);
+    else
+        launch1<float>(L, g, s, I, parity, fo, partials);
+    if (L.diag || L.mode == MODE_FIELDS)
+        hipLaunchKernelGGL(k_diag_reduce, dim3(1), dim3(256), 0, s, partials, nt, dd, step);
+}
+
+}  // namespace mclbm

@@ -1,0 +1,557 @@
+// Device side of the two-component pseudopotential LBM with wetting walls
+// (arXiv:2009.12584, Section 2) for gfx950.
+//
+// One workgroup of 256 threads (4 wavefronts) owns a tile of 64 x TY lattice
+// nodes and performs one whole time step for it:
+//   phase 0  node flags of the tile plus a halo of 4 into LDS
+//   phase 1  pull streaming with half-way bounce-back for the owned nodes
+//            (populations kept in registers) and for a ring of halo nodes
+//            (densities only); densities rho^A, rho^B into LDS  (Eqs. 1, 3)
+//   phase 2  improved scheme: virtual solid densities of the interface solids
+//            in tile + 1 from the LDS densities                  (Eq. 7)
+//   phase 3  Shan-Chen force over fluid neighbours and adhesion force
+//            (Eqs. 5, 6), velocity shifted by half the force (Eq. 3), BGK
+//            collision with the Guo source (Eqs. 1, 2, 4), coalesced store
+//            of the post-collision deviations at the node itself; optional
+//            FP64 partial sums of mass, momentum and max speed per tile.
+// The halo is 1 node for Martys-Chen and LLKC.  The improved scheme needs the
+// density 3 nodes out (2 for the D2Q25 average of a solid that is itself 1
+// node out), but only at fluid nodes within reach of an interface solid and
+// only in tiles that touch a wall; all other tiles use the 1-node halo.
+//
+// Populations are stored per (component, direction) plane, row pitch a
+// multiple of 64 elements, as deviations d_i = f_i - w_i rho_ref in FP32 or
+// scaled FP16.  The buffer read in a step holds the post-collision values of
+// the previous step at their node of origin (pull scheme).  Loads address a
+// component's 9 planes from one uniform base with 32-bit byte offsets (one
+// component stays below 4 GiB), stores a plane base plus the node offset.
+#pragma once
+
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mclbm {
+
+constexpr int TX = 64;        // tile width: one wavefront per tile row
+constexpr int NT = 256;       // threads per workgroup
+constexpr int HMAX = 3;       // widest density halo (improved scheme, D2Q25 average)
+constexpr int FH = HMAX + 1;  // flag halo: a halo node's pull needs its neighbours' phi
+
+enum : uint8_t { NF_SOLID = 1, NF_IFACE = 2, NF_NEAR = 4 };
+enum : uint8_t { TF_NEEDS_RT = 1 };
+enum : int { BC_MC = 0, BC_LLKC = 1, BC_IMPROVED = 2 };
+enum : int { MODE_STEP = 0, MODE_FIELDS = 1 };
+
+// D2Q9 lattice (Section 2): rest node, 4 axis neighbours, 4 diagonals.
+__device__ constexpr int CX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+__device__ constexpr int CY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+__device__ constexpr int OPP[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+__device__ constexpr float WF[9] = {4.f / 9.f,  1.f / 9.f,  1.f / 9.f,  1.f / 9.f, 1.f / 9.f,
+                                    1.f / 36.f, 1.f / 36.f, 1.f / 36.f, 1.f / 36.f};
+
+// D2Q25 averaging weights of Eq. 7, indexed by |e|^2 (0 for the absent 3, 6, 7).
+__device__ constexpr float W25_BY_R2[9] = {0.f,        4.f / 21.f, 4.f / 45.f, 0.f, 1.f / 60.f,
+                                           2.f / 315.f, 0.f,        0.f,        1.f / 5040.f};
+
+// FP16 deviations are stored multiplied by 2^10, which keeps the smallest
+// populations of a 0.03 minority phase clear of the subnormal range.
+constexpr float F16_SCALE = 1024.f;
+constexpr float F16_INV = 1.f / 1024.f;
+
+// Storage format of the deviations: ld() reads one as float, enc()/dec()
+// convert between float and the stored type, put() writes a stored value.
+template <typename S> struct Store;
+template <> struct Store<float> {
+    static __device__ __forceinline__ float ld(const float *p) { return *p; }
+    static __device__ __forceinline__ float enc(float v) { return v; }
+    static __device__ __forceinline__ float dec(float v) { return v; }
+    static __device__ __forceinline__ void put(float *p, float v) { *p = v; }
+};
+template <> struct Store<__half> {
+    static __device__ __forceinline__ float ld(const __half *p) { return __half2float(*p) * F16_INV; }
+    static __device__ __forceinline__ __half enc(float v) { return __float2half_rn(v * F16_SCALE); }
+    static __device__ __forceinline__ float dec(__half v) { return __half2float(v) * F16_INV; }
+    static __device__ __forceinline__ void put(__half *p, __half v) { *p = v; }
+};
+
+template <typename S> __device__ __forceinline__ const S *at(const S *base, uint32_t byte_off) {
+    return (const S *)((const char *)base + byte_off);
+}
+template <typename S> __device__ __forceinline__ S *at(S *base, uint32_t byte_off) {
+    return (S *)((char *)base + byte_off);
+}
+
+// Exact sum of the 9 deviations of one component (a double holds the sum of
+// nine floats of this range without rounding), in a fixed order.
+__device__ __forceinline__ double dsum9(const float d[9]) {
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) s += (double)d[i];
+    return s;
+}
+
+// Everything one simulation needs on the device.  The single-instance kernels
+// take it by value; the batched kernels read it from a table.
+struct Inst {
+    void *buf[2];             // population buffers; parity selects the one read
+    const uint8_t *node;      // NF_* per node, row-major nx * ny
+    const uint8_t *tflag;     // TF_* per tile
+    int nx, ny, pitch, tiles_x, tiles_y;
+    int64_t plane;            // elements per population plane = ny * pitch
+    uint32_t periodic;        // bit0 x, bit1 y
+    int small;                // a periodic size below a tile plus halo: wrap by modulo
+    int bc, avg;
+    float omega, guo;         // 1/tau and 1 - 1/(2 tau)
+    float G, GsA, GsB;        // Eq. 5 strength and the adhesion strengths of Eq. 6
+    float chiA, chiB;         // Eq. 7
+    float rrefA, rrefB;       // deviation references
+    int parity0;              // pool: parity of the buffer read at launch counter 0
+    int64_t t_end;            // pool: launch counter at which this instance stops
+};
+
+// FP64 reduction targets of one simulation.
+struct DiagDev {
+    double mass[2];
+    double mass0[2];
+    double mom[2];
+    double max_speed;
+    long long step;
+    int flags;
+    int have_mass0;
+    double drift_tol;
+};
+
+struct Fields {  // fields mode outputs, unpadded nx * ny planes, any may be null
+    float *rhoA, *rhoB, *ux, *uy, *FAx, *FAy, *FBx, *FBy, *rtA, *rtB;
+};
+
+// Periodic wrap of a coordinate at most a tile plus halo outside [0, n).
+__device__ __forceinline__ int wrap(int g, int n, bool small) {
+    if (small) {
+        g %= n;
+        return g < 0 ? g + n : g;
+    }
+    return g < 0 ? g + n : (g >= n ? g - n : g);
+}
+
+template <int TY> struct Smem {
+    static constexpr int FW = TX + 2 * FH;   // flag tile width
+    static constexpr int FHh = TY + 2 * FH;  // flag tile height
+    static constexpr int RW = TX + 2 * HMAX; // density tile width
+    static constexpr int RH = TY + 2 * HMAX;
+    static constexpr int VW = TX + 2;        // virtual density tile width
+    static constexpr int VH = TY + 2;
+    uint8_t flag[FHh * FW];
+    float rho[2][RH * RW];
+    float rt[2][VH * VW];
+    double red[NT / 64][5];
+    int redi[NT / 64];
+};
+
+template <int TY> __device__ __forceinline__ uint8_t flag_at(const Smem<TY> &sm, int lx, int ly) {
+    return sm.flag[(ly + FH) * Smem<TY>::FW + (lx + FH)];
+}
+template <int TY> __device__ __forceinline__ int rho_idx(int lx, int ly) {
+    return (ly + HMAX) * Smem<TY>::RW + (lx + HMAX);
+}
+template <int TY> __device__ __forceinline__ int rt_idx(int lx, int ly) {
+    return (ly + 1) * Smem<TY>::VW + (lx + 1);
+}
+
+// Bit i set when the upstream node x - c_i of local node (lx, ly) is solid.
+template <int TY> __device__ __forceinline__ unsigned upstream_solid(const Smem<TY> &sm, int lx, int ly) {
+    unsigned m = 0;
+#pragma unroll
+    for (int i = 1; i < 9; ++i) m |= (unsigned)(flag_at<TY>(sm, lx - CX[i], ly - CY[i]) & NF_SOLID) << i;
+    return m;
+}
+
+// Byte offsets, within one population plane, of the 3 x 3 block around a node.
+struct Around {
+    uint32_t row[3], col[3];
+};
+
+template <typename S> __device__ __forceinline__ Around around(const Inst &I, int gx, int gy) {
+    const bool small = I.small != 0;
+    Around a;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        a.col[j] = (uint32_t)wrap(gx - 1 + j, I.nx, small) * (uint32_t)sizeof(S);
+        a.row[j] = (uint32_t)wrap(gy - 1 + j, I.ny, small) * (uint32_t)(I.pitch * sizeof(S));
+    }
+    return a;
+}
+
+// Pull the 9 populations of one component at a fluid node (Eq. 1 streaming,
+// half-way bounce-back where the upstream node x - c_i is solid).  cbase is
+// the component's first plane, pb the plane size in bytes.
+template <typename S>
+__device__ __forceinline__ void pull9(const S *__restrict__ cbase, uint32_t pb, const Around &a, unsigned solid_up,
+                                      float d[9]) {
+    const uint32_t own = a.row[1] + a.col[1];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const uint32_t up = a.row[1 - CY[i]] + a.col[1 - CX[i]];
+        const bool bb = (solid_up >> i) & 1u;
+        const uint32_t off = bb ? (uint32_t)OPP[i] * pb + own : (uint32_t)i * pb + up;
+        d[i] = Store<S>::ld(at(cbase, off));
+    }
+}
+
+struct DiagAcc {
+    double mA = 0, mB = 0, px = 0, py = 0;
+    float u2max = 0.f;
+    int flags = 0;
+};
+
+template <typename T> __device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ int wave_or(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v |= __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Per-tile FP64 partials (mass A, mass B, momentum x, y, max |u|^2, flags),
+// combined in a fixed order; a separate one-block kernel reduces the tiles.
+template <int TY> __device__ void diag_partial(Smem<TY> &sm, const DiagAcc &a, double *partials, int block) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const double v0 = wave_sum(a.mA), v1 = wave_sum(a.mB), v2 = wave_sum(a.px), v3 = wave_sum(a.py);
+    const float um = wave_max(a.u2max);
+    const int fl = wave_or(a.flags);
+    __syncthreads();
+    if (lane == 0) {
+        sm.red[wv][0] = v0;
+        sm.red[wv][1] = v1;
+        sm.red[wv][2] = v2;
+        sm.red[wv][3] = v3;
+        sm.red[wv][4] = (double)um;
+        sm.redi[wv] = fl;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s[4] = {0, 0, 0, 0}, m = 0.0;
+        int f = 0;
+        for (int w = 0; w < NT / 64; ++w) {
+            for (int q = 0; q < 4; ++q) s[q] += sm.red[w][q];
+            m = fmax(m, sm.red[w][4]);
+            f |= sm.redi[w];
+        }
+        double *p = partials + (size_t)block * 6;
+        p[0] = s[0];
+        p[1] = s[1];
+        p[2] = s[2];
+        p[3] = s[3];
+        p[4] = m;
+        p[5] = (double)f;
+    }
+}
+
+// Density pass over the halo frame of width HF (compile time): rows above and
+// below the tile, columns left and right of it.  Beyond the first ring only
+// fluid nodes within reach of an interface solid are needed (Eq. 7).
+template <typename S, int TY, int HF>
+__device__ __forceinline__ void frame_pass(const Inst &I, Smem<TY> &sm, const S *__restrict__ fin, uint32_t pb,
+                                           int tx0, int ty0, const float rref[2]) {
+    constexpr int W = TX + 2 * HF;
+    constexpr int NBAND = HF * W;
+    constexpr int NSIDE = HF * TY;
+    constexpr int TOTAL = 2 * NBAND + 2 * NSIDE;
+    const S *finB = fin + 9 * I.plane;
+    for (int k = threadIdx.x; k < TOTAL; k += NT) {
+        int hx, hy;
+        if (k < NBAND) {
+            hy = -HF + k / W;
+            hx = -HF + k % W;
+        } else if (k < 2 * NBAND) {
+            const int q = k - NBAND;
+            hy = TY + q / W;
+            hx = -HF + q % W;
+        } else if (k < 2 * NBAND + NSIDE) {
+            const int q = k - 2 * NBAND;
+            hy = q / HF;
+            hx = -HF + q % HF;
+        } else {
+            const int q = k - 2 * NBAND - NSIDE;
+            hy = q / HF;
+            hx = TX + q % HF;
+        }
+        const uint8_t f = flag_at<TY>(sm, hx, hy);
+        const int ring = max(max(-hx, hx - (TX - 1)), max(-hy, hy - (TY - 1)));
+        float ra = 0.f, rb = 0.f;
+        const bool want = !(f & NF_SOLID) && (HF == 1 || ring <= 1 || (f & NF_NEAR));
+        if (want) {
+            const Around a = around<S>(I, tx0 + hx, ty0 + hy);
+            const unsigned su = upstream_solid<TY>(sm, hx, hy);
+            float dd[9];
+            pull9<S>(fin, pb, a, su, dd);
+            ra = (float)((double)rref[0] + dsum9(dd));
+            pull9<S>(finB, pb, a, su, dd);
+            rb = (float)((double)rref[1] + dsum9(dd));
+        }
+        sm.rho[0][rho_idx<TY>(hx, hy)] = ra;
+        sm.rho[1][rho_idx<TY>(hx, hy)] = rb;
+    }
+}
+
+// One time step (MODE_STEP) or the fields at the current time (MODE_FIELDS)
+// for the tile (tile_x, tile_y) of instance I.  parity selects the buffer read.
+template <typename S, int TY, int BC, int MODE, bool DIAG>
+__device__ void process_tile(const Inst &I, int tile_x, int tile_y, int parity, Smem<TY> &sm, DiagAcc &acc,
+                             const Fields &fo) {
+    constexpr int RPT = TY / 4;  // tile rows per thread
+    const int tid = threadIdx.x;
+    const int tx0 = tile_x * TX, ty0 = tile_y * TY;
+    const S *__restrict__ fin = (const S *)I.buf[parity];
+    S *__restrict__ fout = (S *)I.buf[parity ^ 1];
+    const uint32_t pb = (uint32_t)(I.plane * (int64_t)sizeof(S));
+    const S *finB = fin + 9 * I.plane;
+    const bool px = I.periodic & 1u, py = (I.periodic >> 1) & 1u;
+    const bool small = I.small != 0;
+    const float rref[2] = {I.rrefA, I.rrefB};
+
+    const bool need_rt = (BC == BC_IMPROVED) &&
+                         (MODE == MODE_FIELDS || (I.tflag[tile_y * I.tiles_x + tile_x] & TF_NEEDS_RT));
+
+    // ---- phase 0: node flags with a halo of FH, wrapped or solid outside
+    for (int k = tid; k < Smem<TY>::FW * Smem<TY>::FHh; k += NT) {
+        const int lx = k % Smem<TY>::FW - FH, ly = k / Smem<TY>::FW - FH;
+        int gx = tx0 + lx, gy = ty0 + ly;
+        uint8_t f = NF_SOLID;
+        const bool inx = (gx >= 0 && gx < I.nx) || px;
+        const bool iny = (gy >= 0 && gy < I.ny) || py;
+        if (inx && iny) {
+            gx = wrap(gx, I.nx, small);
+            gy = wrap(gy, I.ny, small);
+            f = I.node[(size_t)gy * I.nx + gx];
+        }
+        sm.flag[k] = f;
+    }
+    __syncthreads();
+
+    // ---- phase 1a: owned rectangle; populations stay in registers
+    const int lx = tid & (TX - 1);
+    const int lr = tid >> 6;
+    float d[RPT][2][9];
+    double sd[RPT][2];  // exact incoming deviation sums
+    bool fluid[RPT];
+    uint32_t own[RPT];  // byte offset of the owned node in a plane
+    bool owned[RPT];
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+        const int ly = lr + 4 * r;
+        const int gx = tx0 + lx, gy = ty0 + ly;
+        const uint8_t f = flag_at<TY>(sm, lx, ly);
+        owned[r] = gx < I.nx && gy < I.ny;
+        fluid[r] = !(f & NF_SOLID);
+        own[r] = (uint32_t)(gy * I.pitch + gx) * (uint32_t)sizeof(S);
+        float ra = 0.f, rb = 0.f;
+        sd[r][0] = sd[r][1] = 0.0;
+        if (fluid[r]) {
+            const Around a = around<S>(I, gx, gy);
+            const unsigned su = upstream_solid<TY>(sm, lx, ly);
+            pull9<S>(fin, pb, a, su, d[r][0]);
+            pull9<S>(finB, pb, a, su, d[r][1]);
+            sd[r][0] = dsum9(d[r][0]);
+            sd[r][1] = dsum9(d[r][1]);
+            ra = (float)((double)rref[0] + sd[r][0]);
+            rb = (float)((double)rref[1] + sd[r][1]);
+        }
+        sm.rho[0][rho_idx<TY>(lx, ly)] = ra;
+        sm.rho[1][rho_idx<TY>(lx, ly)] = rb;
+    }
+
+    // ---- phase 1b: halo frame
+    if (need_rt)
+        frame_pass<S, TY, HMAX>(I, sm, fin, pb, tx0, ty0, rref);
+    else
+        frame_pass<S, TY, 1>(I, sm, fin, pb, tx0, ty0, rref);
+    __syncthreads();
+
+    // ---- phase 2: virtual solid density of Eq. 7 on interface solids in tile + 1
+    if (BC == BC_IMPROVED && need_rt) {
+        const float chi[2] = {I.chiA, I.chiB};
+        for (int k = tid; k < Smem<TY>::VW * Smem<TY>::VH; k += NT) {
+            const int vx = k % Smem<TY>::VW - 1, vy = k / Smem<TY>::VW - 1;
+            float ta = 0.f, tb = 0.f;
+            if (flag_at<TY>(sm, vx, vy) & NF_IFACE) {
+                float na = 0.f, nb = 0.f, den = 0.f;
+                if (I.avg == 0) {
+#pragma unroll
+                    for (int ey = -2; ey <= 2; ++ey)
+#pragma unroll
+                        for (int ex = -2; ex <= 2; ++ex) {
+                            if (ex == 0 && ey == 0) continue;
+                            const float w = W25_BY_R2[ex * ex + ey * ey];
+                            if (!(flag_at<TY>(sm, vx + ex, vy + ey) & NF_SOLID)) {
+                                na += w * sm.rho[0][rho_idx<TY>(vx + ex, vy + ey)];
+                                nb += w * sm.rho[1][rho_idx<TY>(vx + ex, vy + ey)];
+                                den += w;
+                            }
+                        }
+                } else {
+#pragma unroll
+                    for (int i = 1; i < 9; ++i) {
+                        if (!(flag_at<TY>(sm, vx + CX[i], vy + CY[i]) & NF_SOLID)) {
+                            na += WF[i] * sm.rho[0][rho_idx<TY>(vx + CX[i], vy + CY[i])];
+                            nb += WF[i] * sm.rho[1][rho_idx<TY>(vx + CX[i], vy + CY[i])];
+                            den += WF[i];
+                        }
+                    }
+                }
+                // den > 0: an interface solid has a fluid first-belt neighbour
+                ta = chi[0] * na / den;
+                tb = chi[1] * nb / den;
+            }
+            sm.rt[0][k] = ta;
+            sm.rt[1][k] = tb;
+        }
+        __syncthreads();
+    }
+
+    // ---- phase 3: forces, velocity, collision, store
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+        const int ly = lr + 4 * r;
+        if (!owned[r]) continue;
+        const size_t oidx = (size_t)(ty0 + ly) * I.nx + (tx0 + lx);
+        if (!fluid[r]) {
+            if (MODE == MODE_FIELDS) {
+                if (fo.rhoA) fo.rhoA[oidx] = 0.f;
+                if (fo.rhoB) fo.rhoB[oidx] = 0.f;
+                if (fo.ux) fo.ux[oidx] = 0.f;
+                if (fo.uy) fo.uy[oidx] = 0.f;
+                if (fo.FAx) fo.FAx[oidx] = 0.f;
+                if (fo.FAy) fo.FAy[oidx] = 0.f;
+                if (fo.FBx) fo.FBx[oidx] = 0.f;
+                if (fo.FBy) fo.FBy[oidx] = 0.f;
+                const bool v = (BC == BC_IMPROVED);
+                if (fo.rtA) fo.rtA[oidx] = v ? sm.rt[0][rt_idx<TY>(lx, ly)] : 0.f;
+                if (fo.rtB) fo.rtB[oidx] = v ? sm.rt[1][rt_idx<TY>(lx, ly)] : 0.f;
+            }
+            continue;
+        }
+        const float ra = sm.rho[0][rho_idx<TY>(lx, ly)];
+        const float rb = sm.rho[1][rho_idx<TY>(lx, ly)];
+        // Eq. 5 over fluid neighbours, Eq. 6 over solid neighbours
+        float sax = 0.f, say = 0.f, sbx = 0.f, sby = 0.f;  // sum w psi c (A and B)
+        float nxs = 0.f, nys = 0.f;                          // sum w phi c
+        float tax = 0.f, tay = 0.f, tbx = 0.f, tby = 0.f;  // sum w rho~ c
+#pragma unroll
+        for (int i = 1; i < 9; ++i) {
+            const int qx = lx + CX[i], qy = ly + CY[i];
+            const float w = WF[i];
+            if (!(flag_at<TY>(sm, qx, qy) & NF_SOLID)) {
+                const float a = w * sm.rho[0][rho_idx<TY>(qx, qy)];
+                const float b = w * sm.rho[1][rho_idx<TY>(qx, qy)];
+                sax += a * CX[i];
+                say += a * CY[i];
+                sbx += b * CX[i];
+                sby += b * CY[i];
+            } else {
+                nxs += w * CX[i];
+                nys += w * CY[i];
+                if (BC == BC_IMPROVED) {
+                    const float a = w * sm.rt[0][rt_idx<TY>(qx, qy)];
+                    const float b = w * sm.rt[1][rt_idx<TY>(qx, qy)];
+                    tax += a * CX[i];
+                    tay += a * CY[i];
+                    tbx += b * CX[i];
+                    tby += b * CY[i];
+                }
+            }
+        }
+        float FAx = -I.G * ra * sbx, FAy = -I.G * ra * sby;
+        float FBx = -I.G * rb * sax, FBy = -I.G * rb * say;
+        if (BC == BC_MC) {
+            FAx -= I.GsA * ra * nxs;
+            FAy -= I.GsA * ra * nys;
+            FBx -= I.GsB * rb * nxs;
+            FBy -= I.GsB * rb * nys;
+        } else if (BC == BC_LLKC) {
+            FAx -= I.GsA * ra * rb * nxs;
+            FAy -= I.GsA * ra * rb * nys;
+            FBx -= I.GsB * rb * ra * nxs;
+            FBy -= I.GsB * rb * ra * nys;
+        } else {
+            FAx -= I.G * ra * tbx;
+            FAy -= I.G * ra * tby;
+            FBx -= I.G * rb * tax;
+            FBy -= I.G * rb * tay;
+        }
+        // Eq. 3: sum_i f_i c_i equals sum_i d_i c_i since sum_i w_i c_i = 0
+        float jx = 0.f, jy = 0.f;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            jx += (d[r][c][1] - d[r][c][3]) + (d[r][c][5] - d[r][c][6]) + (d[r][c][8] - d[r][c][7]);
+            jy += (d[r][c][2] - d[r][c][4]) + (d[r][c][5] - d[r][c][8]) + (d[r][c][6] - d[r][c][7]);
+        }
+        const float rt = ra + rb;
+        const float inv = 1.f / rt;
+        const float ux = (jx + 0.5f * (FAx + FBx)) * inv;
+        const float uy = (jy + 0.5f * (FAy + FBy)) * inv;
+
+        if (DIAG) {
+            // exact per-node mass: reference plus the exact deviation sum
+            acc.mA += (double)rref[0] + sd[r][0];
+            acc.mB += (double)rref[1] + sd[r][1];
+            acc.px += (double)rt * (double)ux;
+            acc.py += (double)rt * (double)uy;
+            acc.u2max = fmaxf(acc.u2max, ux * ux + uy * uy);
+            if (!isfinite(ra + rb + ux + uy)) acc.flags |= 1;
+            if (ra < 0.f || rb < 0.f) acc.flags |= 2;
+        }
+        if (MODE == MODE_FIELDS) {
+            if (fo.rhoA) fo.rhoA[oidx] = ra;
+            if (fo.rhoB) fo.rhoB[oidx] = rb;
+            if (fo.ux) fo.ux[oidx] = ux;
+            if (fo.uy) fo.uy[oidx] = uy;
+            if (fo.FAx) fo.FAx[oidx] = FAx;
+            if (fo.FAy) fo.FAy[oidx] = FAy;
+            if (fo.FBx) fo.FBx[oidx] = FBx;
+            if (fo.FBy) fo.FBy[oidx] = FBy;
+            if (fo.rtA) fo.rtA[oidx] = 0.f;
+            if (fo.rtB) fo.rtB[oidx] = 0.f;
+            continue;
+        }
+        // Eqs. 1, 2, 4 in deviation form.  The 8 moving populations are computed
+        // and rounded to storage; the rest population takes the exact remainder
+        // of the incoming deviation sum, so the stored node mass equals the
+        // incoming one up to a single rounding (no systematic FP32 mass drift).
+        const float uu = ux * ux + uy * uy;
+        const float rho_c[2] = {ra, rb};
+        const float Fx_c[2] = {FAx, FBx}, Fy_c[2] = {FAy, FBy};
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const float rc = rho_c[c], fx = Fx_c[c], fy = Fy_c[c];
+            const double s_in = sd[r][c];
+            const float drho = (float)s_in;
+            const float uF = ux * fx + uy * fy;
+            S *o = at(fout + (int64_t)c * 9 * I.plane, own[r]);
+            double s_out = 0.0;
+#pragma unroll
+            for (int i = 1; i < 9; ++i) {
+                const float cu = CX[i] * ux + CY[i] * uy;
+                const float cF = CX[i] * fx + CY[i] * fy;
+                const float deq = WF[i] * (drho + rc * (3.f * cu + 4.5f * cu * cu - 1.5f * uu));
+                const float src = WF[i] * I.guo * (3.f * (cF - uF) + 9.f * cu * cF);
+                const float di = d[r][c][i];
+                const auto q = Store<S>::enc(di + I.omega * (deq - di) + src);
+                s_out += (double)Store<S>::dec(q);
+                Store<S>::put(at(o, (uint32_t)i * pb), q);
+            }
+            Store<S>::put(o, Store<S>::enc((float)(s_in - s_out)));
+        }
+    }
+}
+
+}  // namespace mclbm

@@ -1,0 +1,79 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol the
+header declares, and rejects invalid problems before any device call."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "mclbm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"\b(lbm_[a-z_0-9]+)\s*\(", src)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2009_12584_amd import capi
+
+    L = capi.lib()
+    declared = header_functions()
+    assert len(declared) >= 30
+    missing = [n for n in declared if not hasattr(L, n)]
+    assert not missing, missing
+    assert sorted(declared) == sorted(capi.EXPORTS)
+
+
+def _sim(**kw):
+    import paper_2009_12584_amd as M
+
+    mask = kw.pop("mask", None)
+    n = kw.pop("n", 8)
+    if mask is None:
+        mask = np.zeros((n, n), np.uint8)
+        mask[0] = mask[-1] = 1
+        mask[:, 0] = mask[:, -1] = 1
+    rA = kw.pop("rA", np.full(mask.shape, 0.5))
+    rB = kw.pop("rB", np.full(mask.shape, 0.5))
+    return M.Simulation(mask, rA, rB, **kw)
+
+
+@pytest.mark.parametrize("kw,needle", [
+    (dict(tau=0.5), "tau"),
+    (dict(tau=float("nan")), "tau"),
+    (dict(bc=3), "bc"),
+    (dict(avg=2), "avg"),
+    (dict(storage=7, tile_y=3), "tile_y"),
+    (dict(periodic=4), "periodic"),
+    (dict(G=float("inf")), "non-finite"),
+    (dict(mask=np.zeros((8, 8), np.uint8)), "border"),
+    (dict(rA=np.full((8, 8), -0.1)), "densities"),
+    (dict(rB=np.full((8, 8), np.nan)), "densities"),
+    (dict(diag_every=-1), "diag_every"),
+])
+def test_invalid_problems_rejected_on_host(kw, needle):
+    import paper_2009_12584_amd as M
+
+    with pytest.raises(M.LbmError) as e:
+        _sim(**kw)
+    assert e.value.code == -1
+    assert needle in str(e.value)
+
+
+def test_strerror_names_codes():
+    from paper_2009_12584_amd import capi
+
+    for code in (0, -1, -2, -3, -4, -5, -6):
+        assert capi.lib().lbm_strerror(code).decode() != "unknown error"
+
+
+def test_pool_footprint_counts_both_buffers():
+    import paper_2009_12584_amd as M
+
+    f32 = M.Pool.footprint(512, 256)
+    f16 = M.Pool.footprint(512, 256, storage="f16")
+    assert f32 >= 2 * 18 * 512 * 256 * 4
+    assert f16 >= 2 * 18 * 512 * 256 * 2 and f16 < f32

@@ -1,0 +1,164 @@
+"""GPU tests of the batched and served forms: every instance matches the same
+simulation run alone (bit-identical: same kernel body, same per-node
+arithmetic) and the FP64 oracle within the FP32 bar."""
+import time
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def M():
+    import torch
+
+    assert torch.cuda.is_available()
+    import paper_2009_12584_amd as M
+
+    return M
+
+
+def small_cases(n, seed=0):
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(n):
+        nx = int(rng.integers(70, 260))
+        ny = int(rng.integers(40, 140))
+        c = W.plane_drop(nx, ny, float(rng.uniform(0, 45)), ny / 5.0, k % 3, G=3.0 if k % 2 else 0.9)
+        out.append(c)
+    return out
+
+
+def masks_of(M, cases):
+    return [M.mask_plane(c.nx, c.ny, c.geometry[1], c.geometry[2]) for c in cases]
+
+
+def test_batch_matches_single_and_oracle(M, ora):
+    cases = small_cases(7)
+    masks = masks_of(M, cases)
+    say("batch of", [(c.nx, c.ny, c.bc) for c in cases])
+    b = M.Batch([(m, c.rhoA0, c.rhoB0, c.params()) for m, c in zip(masks, cases)])
+    b.step(60)
+    for k, (m, c) in enumerate(zip(masks, cases)):
+        s = M.Simulation(m, c.rhoA0, c.rhoB0, **c.params())
+        s.step(60)
+        ref = s.fields()
+        s.close()
+        got = b.fields(k)
+        for x, y in zip(got, ref):
+            assert np.array_equal(x, y), k
+        o = ora.Oracle(m, c.rhoA0, c.rhoB0, **c.params())
+        o.step(60)
+        of = o.fields()
+        fl = m == 0
+        er = max(np.max(np.abs(got[0] - of[0])[fl] / of[0][fl]), np.max(np.abs(got[1] - of[1])[fl] / of[1][fl]))
+        eu = max(np.max(np.abs(got[2] - of[2])[fl]), np.max(np.abs(got[3] - of[3])[fl]))
+        assert er <= 1e-5 and eu <= 1e-6, (k, er, eu)
+    d = b.diag(0)
+    assert d["flags"] == 0 and abs(d["mass"][0] - d["mass0"][0]) < 1e-5 * d["mass0"][0]
+    b.close()
+
+
+def test_batch_graph_equals_plain(M):
+    cases = small_cases(5, seed=3)
+    masks = masks_of(M, cases)
+    items = [(m, c.rhoA0, c.rhoB0, c.params()) for m, c in zip(masks, cases)]
+    a = M.Batch(items)
+    g = M.Batch(items, graph_steps=20)
+    a.step(41)
+    g.step(41)
+    for k in range(len(cases)):
+        for x, y in zip(a.fields(k), g.fields(k)):
+            assert np.array_equal(x, y)
+    a.close()
+    g.close()
+
+
+def test_batch_fp16_close_to_fp32(M):
+    cases = small_cases(4, seed=5)
+    masks = masks_of(M, cases)
+    items = [(m, c.rhoA0, c.rhoB0, c.params()) for m, c in zip(masks, cases)]
+    a = M.Batch(items)
+    h = M.Batch(items, storage="f16")
+    a.step(50)
+    h.step(50)
+    for k in range(len(cases)):
+        fa, fh = a.fields(k), h.fields(k)
+        fl = masks[k] == 0
+        er = np.max(np.abs(fa[0] - fh[0])[fl] / fa[0][fl])
+        say("fp16 vs fp32 instance", k, "rel rho", er)
+        assert er < 2e-2  # FP16 storage: reported, not held to the FP32 bar
+    a.close()
+    h.close()
+
+
+def test_pool_results_same_alone_and_in_the_mix(M):
+    """Continuous batching: requests join while others run, each stops at its own
+    step count, and each result equals the same solve run alone."""
+    cases = small_cases(6, seed=11)
+    masks = masks_of(M, cases)
+    steps = [37, 80, 15, 64, 101, 50]
+    budget = sum(M.Pool.footprint(c.nx, c.ny) for c in cases[:3]) + 4096
+    pool = M.Pool(budget, 4)
+    slots = {}
+    pending = list(range(len(cases)))
+    done = {}
+    rounds = 0
+    while pending or slots:
+        # admit while memory and slots allow
+        while pending:
+            k = pending[0]
+            c = cases[k]
+            s = pool.admit(masks[k], c.rhoA0, c.rhoB0, steps[k], **c.params())
+            if s is None:
+                break
+            slots[s] = k
+            pending.pop(0)
+        pool.advance(13)
+        finished = pool.poll()
+        for s in finished:
+            k = slots.pop(s)
+            done[k] = pool.fields(s)
+            pool.release(s)
+        if not finished:
+            time.sleep(0.002)
+        rounds += 1
+        assert rounds < 20000
+    active, used = pool.stats()
+    assert active == 0 and used == 0
+    pool.close()
+    for k, c in enumerate(cases):
+        s = M.Simulation(masks[k], c.rhoA0, c.rhoB0, **c.params())
+        s.step(steps[k])
+        ref = s.fields()
+        s.close()
+        for x, y in zip(done[k], ref):
+            assert np.array_equal(x, y), k
+
+
+def test_pool_admission_limits(M):
+    c = small_cases(1, seed=2)[0]
+    m = masks_of(M, [c])[0]
+    fp = M.Pool.footprint(c.nx, c.ny)
+    pool = M.Pool(fp + 1024, 8)
+    s0 = pool.admit(m, c.rhoA0, c.rhoB0, 10, **c.params())
+    assert s0 is not None
+    assert pool.admit(m, c.rhoA0, c.rhoB0, 10, **c.params()) is None  # budget
+    pool.advance(20)
+    t0 = time.time()
+    while not pool.poll() and time.time() - t0 < 30:
+        time.sleep(0.01)
+    pool.release(s0)
+    assert pool.admit(m, c.rhoA0, c.rhoB0, 10, **c.params()) is not None
+    pool.close()
+    p2 = M.Pool(10 * fp, 1)
+    assert p2.admit(m, c.rhoA0, c.rhoB0, 10, **c.params()) is not None
+    assert p2.admit(m, c.rhoA0, c.rhoB0, 10, **c.params()) is None  # slots
+    p2.close()

@@ -1,0 +1,285 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Bar (FP32 storage): max over fluid nodes of |rho_gpu - rho_ora| / rho_ora <= 1e-5
+and |u_gpu - u_ora| <= 1e-6; wall masks and stair classification bit-exact.
+"""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+RHO_TOL = 1e-5
+U_TOL = 1e-6
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2009_12584_amd as M
+
+    return M
+
+
+def gpu_mask(M, c):
+    if c.mask_user is not None:
+        return c.mask_user
+    g = c.geometry
+    if g[0] == "plane":
+        return M.mask_plane(c.nx, c.ny, g[1], g[2])
+    if g[0] == "disk":
+        return M.mask_disk(c.nx, c.ny, g[1], g[2], g[3])
+    raise ValueError(g)
+
+
+def ora_mask(ora, c):
+    if c.mask_user is not None:
+        return c.mask_user
+    g = c.geometry
+    if g[0] == "plane":
+        return ora.mask_plane(c.nx, c.ny, g[1], g[2])
+    return ora.mask_disk(c.nx, c.ny, g[1], g[2], g[3])
+
+
+def errors(mask, gf, of):
+    fl = mask == 0
+    ga, gb, gux, guy = gf
+    oa, ob, oux, ouy = of
+    er = max(np.max(np.abs(ga - oa)[fl] / oa[fl]), np.max(np.abs(gb - ob)[fl] / ob[fl]))
+    eu = max(np.max(np.abs(gux - oux)[fl]), np.max(np.abs(guy - ouy)[fl]))
+    return er, eu
+
+
+def compare_run(M, ora, c, checkpoints, **extra):
+    say("case", c.name, c.nx, c.ny, "bc", c.bc, "checkpoints", checkpoints, extra)
+    mask = gpu_mask(M, c)
+    assert np.array_equal(mask, ora_mask(ora, c)), "wall mask differs"
+    sim = M.Simulation(mask, c.rhoA0, c.rhoB0, **c.params(), **extra)
+    o = ora.Oracle(mask, c.rhoA0, c.rhoB0, **c.params())
+    out = []
+    for T in checkpoints:
+        sim.step(T - sim.t)
+        o.step(T - o.t)
+        er, eu = errors(mask, sim.fields(), o.fields())
+        say("  t=%d rel rho %.3e abs u %.3e" % (T, er, eu))
+        out.append((T, er, eu))
+    sim.close()
+    return out
+
+
+# ------------------------------------------------------------ geometry
+
+@pytest.mark.parametrize("nx,ny,beta_deg,R0", [(64, 64, 0.0, 15.0), (512, 256, 30.0, 40.0), (400, 400, 70.0, 18.0),
+                                               (333, 121, 17.3, 20.0), (1000, 1000, 45.0, 100.0),
+                                               (5600, 4000, 30.0, 400.0)])
+def test_plane_mask_bit_exact(gpu, ora, nx, ny, beta_deg, R0):
+    b = math.radians(beta_deg)
+    assert np.array_equal(gpu.mask_plane(nx, ny, b, R0), ora.mask_plane(nx, ny, b, R0))
+    assert np.array_equal(gpu.mask_plane(nx, ny, b, R0, borders=False),
+                          ora.mask_plane(nx, ny, b, R0, borders=False))
+
+
+def test_disk_mask_bit_exact(gpu, ora):
+    c = W.config3(0)
+    g = c.geometry
+    assert np.array_equal(gpu.mask_disk(c.nx, c.ny, g[1], g[2], g[3]), ora.mask_disk(c.nx, c.ny, g[1], g[2], g[3]))
+    assert np.array_equal(gpu.mask_disk(301, 257, 150.5, 100.25, 77.7), ora.mask_disk(301, 257, 150.5, 100.25, 77.7))
+
+
+@pytest.mark.parametrize("which", ["c1", "c2", "c3", "periodic-xy"])
+def test_classification_bit_exact(gpu, ora, which):
+    if which == "c1":
+        c = W.config1()
+    elif which == "c2":
+        c = W.config2()
+    elif which == "c3":
+        c = W.config3(1)
+    else:
+        rng = np.random.default_rng(5)
+        m = (rng.random((70, 130)) < 0.2).astype(np.uint8)
+        c = W.Case("rand", 130, 70, periodic=3, rhoA0=np.full((70, 130), 0.5), rhoB0=np.full((70, 130), 0.5),
+                   mask_user=m)
+    mask = gpu_mask(gpu, c)
+    sim = gpu.Simulation(mask, c.rhoA0, c.rhoB0, **c.params())
+    nbr, cls = sim.classify()
+    sim.close()
+    onbr, ocls = ora.classify(mask, c.periodic)
+    assert np.array_equal(nbr, onbr) and np.array_equal(cls, ocls)
+
+
+# ------------------------------------------------------ step-0 quantities
+
+@pytest.mark.parametrize("bc", [W.MC, W.LLKC, W.IMPROVED])
+@pytest.mark.parametrize("avg", [0, 1])
+def test_forces_and_virtual_density_at_step0(gpu, ora, bc, avg):
+    if bc != W.IMPROVED and avg == 1:
+        pytest.skip("averaging lattice only matters for the improved scheme")
+    c = W.plane_drop(203, 97, 25.0, 15.0, bc, G=3.0, chi=(1.2, 0.8))
+    c.avg = avg
+    rA, rB = W.random_mixture(c.nx, c.ny, seed=9, mean=0.5, amp=0.3)
+    mask = gpu_mask(gpu, c)
+    sim = gpu.Simulation(mask, rA, rB, **c.params())
+    o = ora.Oracle(mask, rA, rB, **c.params())
+    g = sim.forces()
+    f = o.forces() + o.virtual_density()
+    sim.close()
+    scale = max(np.abs(x).max() for x in f[:4])
+    for k in range(4):
+        assert np.max(np.abs(g[k] - f[k])) <= 2e-6 * scale, k
+    for k in (4, 5):
+        assert np.max(np.abs(g[k] - f[k])) <= 1e-6 * max(1.0, np.abs(f[k]).max()), k
+
+
+# ------------------------------------------------------------ dynamics
+
+@pytest.mark.parametrize("bc", [W.MC, W.LLKC, W.IMPROVED])
+def test_parity_ragged_tiles_all_bcs(gpu, ora, bc):
+    """Several tiles with ragged right/bottom edges, G = 3 demixing, all three rules."""
+    c = W.plane_drop(203, 97, 25.0, 15.0, bc, G=3.0, rho_out=0.055)
+    for T, er, eu in compare_run(gpu, ora, c, [1, 10, 100, 300]):
+        assert er <= RHO_TOL and eu <= U_TOL, (T, er, eu)
+
+
+@pytest.mark.parametrize("periodic", [1, 2, 3])
+def test_parity_periodic_wrap(gpu, ora, periodic):
+    nx, ny = 130, 37
+    m = np.zeros((ny, nx), np.uint8)
+    if not periodic & 1:
+        m[:, 0] = m[:, -1] = 1
+    if not periodic & 2:
+        m[0, :] = m[-1, :] = 1
+    m[10:20, 40:47] = 1  # an obstacle
+    rA, rB = W.random_mixture(nx, ny, seed=periodic, amp=0.1)
+    c = W.Case("periodic%d" % periodic, nx, ny, periodic=periodic, tau=0.8, G=2.5, bc=W.IMPROVED, chiA=1.1,
+               chiB=0.9, rhoA0=rA, rhoB0=rB, mask_user=m)
+    for T, er, eu in compare_run(gpu, ora, c, [1, 50, 200]):
+        assert er <= RHO_TOL and eu <= U_TOL, (T, er, eu)
+
+
+def test_parity_tiny_periodic_box_smaller_than_tile(gpu, ora):
+    nx, ny = 5, 3
+    rA, rB = W.random_mixture(nx, ny, seed=2, amp=0.2)
+    c = W.Case("tiny", nx, ny, periodic=3, G=2.0, bc=W.MC, rhoA0=rA, rhoB0=rB, mask_user=np.zeros((ny, nx), np.uint8))
+    for T, er, eu in compare_run(gpu, ora, c, [1, 7, 60]):
+        assert er <= RHO_TOL and eu <= U_TOL, (T, er, eu)
+
+
+def test_parity_config1_full(gpu, ora):
+    """64x64, periodic x, flat walls, Martys-Chen, 2000 steps (the oracle in FP64)."""
+    c = W.config1()
+    for T, er, eu in compare_run(gpu, ora, c, [1, 10, 100, 1000, 2000]):
+        assert er <= RHO_TOL and eu <= U_TOL, (T, er, eu)
+
+
+def test_parity_config2_full_size(gpu, ora):
+    """512x256 30-degree stair, improved scheme, at the size and launch shape the bench times."""
+    c = W.config2()
+    for T, er, eu in compare_run(gpu, ora, c, [1, 10, 200]):
+        assert er <= RHO_TOL and eu <= U_TOL, (T, er, eu)
+
+
+def test_parity_config3_full_size(gpu, ora):
+    c = W.config3(2)
+    for T, er, eu in compare_run(gpu, ora, c, [1, 10]):
+        assert er <= RHO_TOL and eu <= U_TOL, (T, er, eu)
+
+
+# ------------------------------------------------- determinism and invariants
+
+def test_tile_shapes_bit_identical_and_runs_repeat(gpu, ora):
+    c = W.plane_drop(300, 150, 33.0, 20.0, W.IMPROVED, G=3.0)
+    mask = gpu_mask(gpu, c)
+    res = []
+    for ty in (4, 8, 16, 8):
+        sim = gpu.Simulation(mask, c.rhoA0, c.rhoB0, tile_y=ty, **c.params())
+        sim.step(150)
+        res.append(sim.fields())
+        sim.close()
+    for r in res[1:]:
+        for a, b in zip(res[0], r):
+            assert np.array_equal(a, b)
+
+
+def test_graph_replay_matches_plain_launches(gpu, ora):
+    c = W.plane_drop(256, 128, 30.0, 20.0, W.IMPROVED, G=3.0)
+    mask = gpu_mask(gpu, c)
+    a = gpu.Simulation(mask, c.rhoA0, c.rhoB0, **c.params())
+    b = gpu.Simulation(mask, c.rhoA0, c.rhoB0, graph_steps=16, diag_every=1, **c.params())
+    for n in (1, 40, 33, 64):  # odd counts fall back to plain launches until even again
+        a.step(n)
+        b.step(n)
+        for x, y in zip(a.fields(), b.fields()):
+            assert np.array_equal(x, y)
+    a.close()
+    b.close()
+
+
+def test_checkpoint_resume_bit_exact(gpu, ora):
+    c = W.plane_drop(200, 100, 30.0, 15.0, W.LLKC, G=3.0)
+    mask = gpu_mask(gpu, c)
+    a = gpu.Simulation(mask, c.rhoA0, c.rhoB0, **c.params())
+    a.step(37)
+    st, t = a.get_state()
+    a.step(50)
+    ref = a.fields()
+    b = gpu.Simulation(mask, c.rhoA0, c.rhoB0, **c.params())
+    b.set_state(st, t)
+    b.step(50)
+    for x, y in zip(ref, b.fields()):
+        assert np.array_equal(x, y)
+    a.close()
+    b.close()
+
+
+def test_diagnostics_match_oracle_totals(gpu, ora):
+    c = W.plane_drop(203, 97, 25.0, 15.0, W.IMPROVED, G=3.0)
+    mask = gpu_mask(gpu, c)
+    sim = gpu.Simulation(mask, c.rhoA0, c.rhoB0, diag_every=10, drift_tol=1e-5, **c.params())
+    o = ora.Oracle(mask, c.rhoA0, c.rhoB0, **c.params())
+    sim.step(200)
+    o.step(200)
+    d = sim.diag()
+    t = o.totals()
+    assert d["step"] == 200 and d["flags"] == 0
+    assert d["mass"][0] == pytest.approx(t[0], rel=1e-6)
+    assert d["mass"][1] == pytest.approx(t[1], rel=1e-6)
+    assert d["mass0"][0] == pytest.approx(t[0], rel=1e-6)
+    assert abs(d["momentum"][0] - t[2]) < 1e-6 * t[1]
+    assert abs(d["momentum"][1] - t[3]) < 1e-6 * t[1]
+    _, _, ux, uy = o.fields()
+    assert d["max_speed"] == pytest.approx(np.sqrt(ux ** 2 + uy ** 2).max(), rel=1e-4)
+    sim.close()
+
+
+def test_mass_conserved_config2_20k_steps(gpu, ora):
+    """Property at full size and full length: per-component mass stays at step 0's
+    value (FP32 storage, FP64 reduction) and the drift flag stays clear."""
+    c = W.config2()
+    mask = gpu_mask(gpu, c)
+    sim = gpu.Simulation(mask, c.rhoA0, c.rhoB0, diag_every=1000, drift_tol=1e-4, **c.params())
+    sim.step(c.steps)
+    d = sim.diag()
+    for k in range(2):
+        assert abs(d["mass"][k] - d["mass0"][k]) / d["mass0"][k] < 2e-5
+    sim.close()
+
+
+def test_fp16_storage_error_is_reported_and_small(gpu, ora):
+    """FP16 deviation storage: error against the FP64 oracle stated (not pinned to the FP32 bar)."""
+    c = W.plane_drop(203, 97, 25.0, 15.0, W.IMPROVED)
+    res = compare_run(gpu, ora, c, [10, 100], storage="f16")
+    say("fp16 errors", res)
+    for T, er, eu in res:
+        assert er < 5e-3 and eu < 1e-3
