@@ -209,6 +209,9 @@ int lbm_pool_fields(lbm_pool *pool, int32_t slot, double *rhoA, double *rhoB, do
                     double *uy);
 int lbm_pool_release(lbm_pool *pool, int32_t slot);
 int lbm_pool_stats(const lbm_pool *pool, int32_t *active, size_t *bytes_in_use);
+/* Launches enqueued so far and launches the device has completed; a serving
+ * loop keeps their difference small so that new solves join quickly. */
+int lbm_pool_progress(lbm_pool *pool, int64_t *launched, int64_t *completed);
 int lbm_pool_destroy(lbm_pool *pool);
 
 #ifdef __cplusplus

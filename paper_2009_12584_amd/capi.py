@@ -24,7 +24,8 @@ EXPORTS = [
     "lbm_destroy", "lbm_strerror", "lbm_last_error", "lbm_mask_plane", "lbm_mask_disk", "lbm_copy_probe",
     "lbm_batch_create", "lbm_batch_step", "lbm_batch_fields", "lbm_batch_diag", "lbm_batch_fluid_nodes",
     "lbm_batch_destroy", "lbm_pool_create", "lbm_pool_footprint", "lbm_pool_admit", "lbm_pool_advance",
-    "lbm_pool_poll", "lbm_pool_fields", "lbm_pool_release", "lbm_pool_stats", "lbm_pool_destroy",
+    "lbm_pool_poll", "lbm_pool_fields", "lbm_pool_release", "lbm_pool_stats", "lbm_pool_progress",
+    "lbm_pool_destroy",
 ]
 
 
@@ -97,6 +98,7 @@ def lib():
             "lbm_pool_fields": (I32, [P, I32, P, P, P, P]),
             "lbm_pool_release": (I32, [P, I32]),
             "lbm_pool_stats": (I32, [P, ctypes.POINTER(I32), ctypes.POINTER(SZ)]),
+            "lbm_pool_progress": (I32, [P, ctypes.POINTER(I64), ctypes.POINTER(I64)]),
             "lbm_pool_destroy": (I32, [P]),
         }
         for name, (res, args) in sig.items():

@@ -23,37 +23,66 @@ using namespace mclbm;
 
 namespace {
 
-template <typename S, int TY>
+template <typename S, int TY, int BC>
 __global__ __launch_bounds__(NT) void k_batch_step(const Inst *__restrict__ insts, const int2 *__restrict__ tiles,
                                                    int launch_parity, long long L) {
     __shared__ Smem<TY> sm;
     const int t = xcd_tile(blockIdx.x, gridDim.x);
     const int2 e = tiles[t];
-    const Inst I = insts[e.x];
+    const Inst &I = insts[e.x];  // uniform, read-only: scalar loads, no private copy
     if (L >= I.t_end) return;  // this slot has finished; the whole block leaves together
     const int parity = (I.parity0 ^ launch_parity) & 1;
-    const int tx = e.y % I.tiles_x, ty = e.y / I.tiles_x;
+    int tx, ty;
+    tile_coords(e.y, I.tiles_x, I.tiles_y, tx, ty);
     DiagAcc acc;
-    Fields none{};
-    switch (I.bc) {
-    case BC_MC: process_tile<S, TY, BC_MC, MODE_STEP, false>(I, tx, ty, parity, sm, acc, none); break;
-    case BC_LLKC: process_tile<S, TY, BC_LLKC, MODE_STEP, false>(I, tx, ty, parity, sm, acc, none); break;
-    default: process_tile<S, TY, BC_IMPROVED, MODE_STEP, false>(I, tx, ty, parity, sm, acc, none); break;
-    }
+    process_tile<S, TY, BC, MODE_STEP, false>(I, tx, ty, parity, sm, acc, Fields{});
 }
 
-void launch_batch(int storage, int ty, hipStream_t s, int ntiles, const Inst *insts, const int2 *tiles, int lp,
+// Tile lists are grouped by boundary rule so that each launch runs a kernel
+// specialised (and register-allocated) for one rule.
+struct TileLists {
+    int off[3] = {0, 0, 0}, cnt[3] = {0, 0, 0};
+    int total() const { return cnt[0] + cnt[1] + cnt[2]; }
+};
+
+// Flattened (instance, tile) pairs, grouped by rule; within an instance tiles
+// follow the grouped order of the single-instance kernel.
+template <typename InstOf>
+TileLists build_tiles(int n, InstOf inst_of, std::vector<int2> &out) {
+    TileLists T;
+    out.clear();
+    for (int bc = 0; bc < 3; ++bc) {
+        T.off[bc] = (int)out.size();
+        for (int k = 0; k < n; ++k) {
+            const Inst *I = inst_of(k);
+            if (!I || I->bc != bc) continue;
+            const int nt = I->tiles_x * I->tiles_y;
+            for (int t = 0; t < nt; ++t) out.push_back(make_int2(k, t));
+        }
+        T.cnt[bc] = (int)out.size() - T.off[bc];
+    }
+    return T;
+}
+
+template <typename S, int TY>
+void launch_batch_ty(hipStream_t s, const TileLists &T, const Inst *insts, const int2 *tiles, int lp, long long L) {
+    const dim3 b(NT);
+    if (T.cnt[0]) hipLaunchKernelGGL((k_batch_step<S, TY, BC_MC>), dim3(T.cnt[0]), b, 0, s, insts, tiles + T.off[0], lp, L);
+    if (T.cnt[1]) hipLaunchKernelGGL((k_batch_step<S, TY, BC_LLKC>), dim3(T.cnt[1]), b, 0, s, insts, tiles + T.off[1], lp, L);
+    if (T.cnt[2])
+        hipLaunchKernelGGL((k_batch_step<S, TY, BC_IMPROVED>), dim3(T.cnt[2]), b, 0, s, insts, tiles + T.off[2], lp, L);
+}
+
+void launch_batch(int storage, int ty, hipStream_t s, const TileLists &T, const Inst *insts, const int2 *tiles, int lp,
                   long long L) {
-    if (ntiles <= 0) return;
-    dim3 g((unsigned)ntiles), b(NT);
     if (storage == LBM_STORE_F16) {
-        if (ty == 4) hipLaunchKernelGGL((k_batch_step<__half, 4>), g, b, 0, s, insts, tiles, lp, L);
-        else if (ty == 16) hipLaunchKernelGGL((k_batch_step<__half, 16>), g, b, 0, s, insts, tiles, lp, L);
-        else hipLaunchKernelGGL((k_batch_step<__half, 8>), g, b, 0, s, insts, tiles, lp, L);
+        if (ty == 4) launch_batch_ty<__half, 4>(s, T, insts, tiles, lp, L);
+        else if (ty == 16) launch_batch_ty<__half, 16>(s, T, insts, tiles, lp, L);
+        else launch_batch_ty<__half, 8>(s, T, insts, tiles, lp, L);
     } else {
-        if (ty == 4) hipLaunchKernelGGL((k_batch_step<float, 4>), g, b, 0, s, insts, tiles, lp, L);
-        else if (ty == 16) hipLaunchKernelGGL((k_batch_step<float, 16>), g, b, 0, s, insts, tiles, lp, L);
-        else hipLaunchKernelGGL((k_batch_step<float, 8>), g, b, 0, s, insts, tiles, lp, L);
+        if (ty == 4) launch_batch_ty<float, 4>(s, T, insts, tiles, lp, L);
+        else if (ty == 16) launch_batch_ty<float, 16>(s, T, insts, tiles, lp, L);
+        else launch_batch_ty<float, 8>(s, T, insts, tiles, lp, L);
     }
 }
 
@@ -233,7 +262,7 @@ struct lbm_batch {
     std::vector<char *> blocks;
     Inst *d_inst = nullptr;
     int2 *d_tiles = nullptr;
-    int ntiles = 0;
+    TileLists lists;
     int64_t t = 0;
     int64_t fluid = 0;
     hipGraph_t graph = nullptr;
@@ -316,10 +345,9 @@ int lbm_batch_create(int32_t n, const lbm_params *params, const uint8_t *const *
         }
         host_inst[k] = b->inst[k].I;
         b->fluid += b->inst[k].fluid;
-        for (int t = 0; t < b->inst[k].ntiles; ++t) tiles.push_back(make_int2(k, t));
     }
     st.release();
-    b->ntiles = (int)tiles.size();
+    b->lists = build_tiles(n, [&](int k) { return &host_inst[k]; }, tiles);
     if (hipMalloc(&b->d_inst, sizeof(Inst) * n) != hipSuccess ||
         hipMalloc(&b->d_tiles, sizeof(int2) * tiles.size()) != hipSuccess) {
         set_err("batch tables: hipMalloc failed");
@@ -336,7 +364,7 @@ int lbm_batch_create(int32_t n, const lbm_params *params, const uint8_t *const *
             set_err("graph capture failed");
             return bail(LBM_EDEVICE);
         }
-        for (int s = 0; s < K; ++s) launch_batch(b->storage, b->ty, b->stream, b->ntiles, b->d_inst, b->d_tiles, s & 1, 0);
+        for (int s = 0; s < K; ++s) launch_batch(b->storage, b->ty, b->stream, b->lists, b->d_inst, b->d_tiles, s & 1, 0);
         if (hipStreamEndCapture(b->stream, &b->graph) != hipSuccess ||
             hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0) != hipSuccess) {
             set_err("graph instantiate failed");
@@ -357,7 +385,7 @@ int lbm_batch_step(lbm_batch *b, int64_t nsteps) {
             nsteps -= b->glen;
             continue;
         }
-        launch_batch(b->storage, b->ty, b->stream, b->ntiles, b->d_inst, b->d_tiles, (int)(b->t & 1), 0);
+        launch_batch(b->storage, b->ty, b->stream, b->lists, b->d_inst, b->d_tiles, (int)(b->t & 1), 0);
         b->t += 1;
         nsteps -= 1;
     }
@@ -453,7 +481,7 @@ struct lbm_pool {
     Inst *d_inst = nullptr;
     int2 *d_tiles = nullptr;
     size_t tiles_cap = 0;
-    int ntiles = 0;
+    TileLists lists;
     bool dirty = false;
     int64_t L = 0;  // launches enqueued so far
     std::deque<std::pair<int64_t, hipEvent_t>> marks;  // (launch count reached, event)
@@ -490,10 +518,11 @@ static int pool_upload(lbm_pool *P) {
     std::vector<int2> tiles;
     for (int k = 0; k < P->max_slots; ++k) {
         Slot &s = P->slots[k];
-        if (!s.used || !s.joined) continue;
-        P->h_inst[k] = s.P.I;
-        for (int t = 0; t < s.P.ntiles; ++t) tiles.push_back(make_int2(k, t));
+        if (s.used && s.joined) P->h_inst[k] = s.P.I;
     }
+    const TileLists T = build_tiles(
+        P->max_slots, [&](int k) { return (P->slots[k].used && P->slots[k].joined) ? &P->slots[k].P.I : nullptr; },
+        tiles);
     if (tiles.size() > P->tiles_cap) {
         // grow: wait for launches that read the old list, then reallocate
         MCLBM_HIP(hipStreamSynchronize(P->stream));
@@ -512,7 +541,7 @@ static int pool_upload(lbm_pool *P) {
         MCLBM_HIP(hipMemcpyAsync(P->d_tiles, P->h_tiles, sizeof(int2) * tiles.size(), hipMemcpyHostToDevice,
                                  P->stream));
     MCLBM_HIP(hipEventRecord(P->upload_done, P->stream));
-    P->ntiles = (int)tiles.size();
+    P->lists = T;
     P->dirty = false;
     return LBM_OK;
 }
@@ -656,7 +685,7 @@ int lbm_pool_advance(lbm_pool *P, int64_t chunk) {
         if (s.used && s.joined) last_end = std::max(last_end, s.P.I.t_end);
     const int64_t n = std::min(chunk, last_end - P->L);
     for (int64_t q = 0; q < n; ++q) {
-        launch_batch(P->storage, P->ty, P->stream, P->ntiles, P->d_inst, P->d_tiles, (int)(P->L & 1),
+        launch_batch(P->storage, P->ty, P->stream, P->lists, P->d_inst, P->d_tiles, (int)(P->L & 1),
                      (long long)P->L);
         P->L += 1;
     }
@@ -717,6 +746,14 @@ int lbm_pool_stats(const lbm_pool *P, int32_t *active, size_t *bytes_in_use) {
     for (auto &s : P->slots) a += s.used ? 1 : 0;
     if (active) *active = a;
     if (bytes_in_use) *bytes_in_use = P->in_use;
+    return LBM_OK;
+}
+
+int lbm_pool_progress(lbm_pool *P, int64_t *launched, int64_t *completed) {
+    if (!P) return LBM_EINVAL;
+    pool_reap_marks(P);
+    if (launched) *launched = P->L;
+    if (completed) *completed = P->L_done;
     return LBM_OK;
 }
 

@@ -266,8 +266,9 @@ __global__ void k_init(Inst I, const double *__restrict__ rA, const double *__re
         const int xs = wrap(x + CX[j], I.nx, true), ys = wrap(y + CY[j], I.ny, true);
         int64_t src = (int64_t)ys * I.nx + xs;
         if (I.node[src] & NF_SOLID) src = k;
-        Store<S>::put(b + (int64_t)j * I.plane + own, Store<S>::enc((float)(wd[j] * (rA[src] - rrefA))));
-        Store<S>::put(b + (int64_t)(9 + j) * I.plane + own, Store<S>::enc((float)(wd[j] * (rB[src] - rrefB))));
+        const double sc = (double)Store<S>::SC;
+        Store<S>::put(b + (int64_t)j * I.plane + own, Store<S>::enc((float)(wd[j] * (rA[src] - rrefA) * sc)));
+        Store<S>::put(b + (int64_t)(9 + j) * I.plane + own, Store<S>::enc((float)(wd[j] * (rB[src] - rrefB) * sc)));
     }
 }
 
@@ -275,19 +276,32 @@ __global__ void k_init(Inst I, const double *__restrict__ rA, const double *__re
 
 // Tile index for a block: consecutive blocks go round-robin to the 8 XCDs, so
 // block b is mapped to the b/8-th tile of the contiguous band of tiles given
-// to XCD b%8.  Neighbouring tiles then share an L2, and each XCD keeps the
-// same band from step to step.
+// to XCD b%8; each XCD keeps the same band from step to step.
 __device__ __forceinline__ int xcd_tile(int b, int nb) {
     const int q = nb >> 3, r = nb & 7, x = b & 7;
     return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + (b >> 3);
 }
 
+// Tile coordinates of logical tile t: tiles are walked in groups of TG tile
+// columns (TG x 64 nodes = 4 KiB of FP32 per row, long contiguous HBM runs),
+// down each group row by row, so the tile below a tile runs TG tiles later on
+// the same XCD while the rows their density halos share are still in L2.
+constexpr int TG = 16;
+__device__ __forceinline__ void tile_coords(int t, int tiles_x, int tiles_y, int &tx, int &ty) {
+    const int per_group = TG * tiles_y;
+    const int g = t / per_group, r = t - g * per_group;
+    const int gw = min(TG, tiles_x - g * TG);
+    ty = r / gw;
+    tx = g * TG + (r - ty * gw);
+}
+
 template <typename S, int TY, int BC, int MODE, bool DIAG>
 __global__ __launch_bounds__(NT) void k_step(Inst I, int parity, Fields fo, double *partials) {
     __shared__ Smem<TY> sm;
-    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    int tx, ty;
+    tile_coords(xcd_tile(blockIdx.x, gridDim.x), I.tiles_x, I.tiles_y, tx, ty);
     DiagAcc acc;
-    process_tile<S, TY, BC, MODE, DIAG>(I, t % I.tiles_x, t / I.tiles_x, parity, sm, acc, fo);
+    process_tile<S, TY, BC, MODE, DIAG>(I, tx, ty, parity, sm, acc, fo);
     if (DIAG) diag_partial<TY>(sm, acc, partials, blockIdx.x);
 }
 

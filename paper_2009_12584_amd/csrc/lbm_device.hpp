@@ -55,23 +55,23 @@ __device__ constexpr float W25_BY_R2[9] = {0.f,        4.f / 21.f, 4.f / 45.f, 0
                                            2.f / 315.f, 0.f,        0.f,        1.f / 5040.f};
 
 // FP16 deviations are stored multiplied by 2^10, which keeps the smallest
-// populations of a 0.03 minority phase clear of the subnormal range.
-constexpr float F16_SCALE = 1024.f;
-constexpr float F16_INV = 1.f / 1024.f;
-
-// Storage format of the deviations: ld() reads one as float, enc()/dec()
-// convert between float and the stored type, put() writes a stored value.
+// populations of a 0.03 minority phase clear of the subnormal range.  The
+// kernels work in storage units (deviation x SC): the power-of-two scale is
+// folded into the equilibrium and source weights and into the density and
+// momentum sums, so loads and stores are bare conversions.
 template <typename S> struct Store;
 template <> struct Store<float> {
+    static constexpr float SC = 1.f;
     static __device__ __forceinline__ float ld(const float *p) { return *p; }
     static __device__ __forceinline__ float enc(float v) { return v; }
     static __device__ __forceinline__ float dec(float v) { return v; }
     static __device__ __forceinline__ void put(float *p, float v) { *p = v; }
 };
 template <> struct Store<__half> {
-    static __device__ __forceinline__ float ld(const __half *p) { return __half2float(*p) * F16_INV; }
-    static __device__ __forceinline__ __half enc(float v) { return __float2half_rn(v * F16_SCALE); }
-    static __device__ __forceinline__ float dec(__half v) { return __half2float(v) * F16_INV; }
+    static constexpr float SC = 1024.f;
+    static __device__ __forceinline__ float ld(const __half *p) { return __half2float(*p); }
+    static __device__ __forceinline__ __half enc(float v) { return __float2half_rn(v); }
+    static __device__ __forceinline__ float dec(__half v) { return __half2float(v); }
     static __device__ __forceinline__ void put(__half *p, __half v) { *p = v; }
 };
 
@@ -294,9 +294,9 @@ __device__ __forceinline__ void frame_pass(const Inst &I, Smem<TY> &sm, const S 
             const unsigned su = upstream_solid<TY>(sm, hx, hy);
             float dd[9];
             pull9<S>(fin, pb, a, su, dd);
-            ra = (float)((double)rref[0] + dsum9(dd));
+            ra = (float)((double)rref[0] + dsum9(dd) * (double)(1.f / Store<S>::SC));
             pull9<S>(finB, pb, a, su, dd);
-            rb = (float)((double)rref[1] + dsum9(dd));
+            rb = (float)((double)rref[1] + dsum9(dd) * (double)(1.f / Store<S>::SC));
         }
         sm.rho[0][rho_idx<TY>(hx, hy)] = ra;
         sm.rho[1][rho_idx<TY>(hx, hy)] = rb;
@@ -361,10 +361,10 @@ __device__ void process_tile(const Inst &I, int tile_x, int tile_y, int parity, 
             const unsigned su = upstream_solid<TY>(sm, lx, ly);
             pull9<S>(fin, pb, a, su, d[r][0]);
             pull9<S>(finB, pb, a, su, d[r][1]);
-            sd[r][0] = dsum9(d[r][0]);
+            sd[r][0] = dsum9(d[r][0]);  // storage units
             sd[r][1] = dsum9(d[r][1]);
-            ra = (float)((double)rref[0] + sd[r][0]);
-            rb = (float)((double)rref[1] + sd[r][1]);
+            ra = (float)((double)rref[0] + sd[r][0] * (double)(1.f / Store<S>::SC));
+            rb = (float)((double)rref[1] + sd[r][1] * (double)(1.f / Store<S>::SC));
         }
         sm.rho[0][rho_idx<TY>(lx, ly)] = ra;
         sm.rho[1][rho_idx<TY>(lx, ly)] = rb;
@@ -495,6 +495,8 @@ __device__ void process_tile(const Inst &I, int tile_x, int tile_y, int parity, 
             jx += (d[r][c][1] - d[r][c][3]) + (d[r][c][5] - d[r][c][6]) + (d[r][c][8] - d[r][c][7]);
             jy += (d[r][c][2] - d[r][c][4]) + (d[r][c][5] - d[r][c][8]) + (d[r][c][6] - d[r][c][7]);
         }
+        jx *= 1.f / Store<S>::SC;
+        jy *= 1.f / Store<S>::SC;
         const float rt = ra + rb;
         const float inv = 1.f / rt;
         const float ux = (jx + 0.5f * (FAx + FBx)) * inv;
@@ -502,8 +504,8 @@ __device__ void process_tile(const Inst &I, int tile_x, int tile_y, int parity, 
 
         if (DIAG) {
             // exact per-node mass: reference plus the exact deviation sum
-            acc.mA += (double)rref[0] + sd[r][0];
-            acc.mB += (double)rref[1] + sd[r][1];
+            acc.mA += (double)rref[0] + sd[r][0] * (double)(1.f / Store<S>::SC);
+            acc.mB += (double)rref[1] + sd[r][1] * (double)(1.f / Store<S>::SC);
             acc.px += (double)rt * (double)ux;
             acc.py += (double)rt * (double)uy;
             acc.u2max = fmaxf(acc.u2max, ux * ux + uy * uy);
@@ -523,10 +525,12 @@ __device__ void process_tile(const Inst &I, int tile_x, int tile_y, int parity, 
             if (fo.rtB) fo.rtB[oidx] = 0.f;
             continue;
         }
-        // Eqs. 1, 2, 4 in deviation form.  The 8 moving populations are computed
-        // and rounded to storage; the rest population takes the exact remainder
-        // of the incoming deviation sum, so the stored node mass equals the
-        // incoming one up to a single rounding (no systematic FP32 mass drift).
+        // Eqs. 1, 2, 4 in deviation form, in storage units.  The 8 moving
+        // populations are computed and rounded to storage; the rest population
+        // takes the exact remainder of the incoming deviation sum, so the stored
+        // node mass equals the incoming one up to a single rounding (no
+        // systematic FP32 mass drift).
+        constexpr float SC = Store<S>::SC;
         const float uu = ux * ux + uy * uy;
         const float rho_c[2] = {ra, rb};
         const float Fx_c[2] = {FAx, FBx}, Fy_c[2] = {FAy, FBy};
@@ -534,7 +538,7 @@ __device__ void process_tile(const Inst &I, int tile_x, int tile_y, int parity, 
         for (int c = 0; c < 2; ++c) {
             const float rc = rho_c[c], fx = Fx_c[c], fy = Fy_c[c];
             const double s_in = sd[r][c];
-            const float drho = (float)s_in;
+            const float drho = (float)s_in * (1.f / SC);
             const float uF = ux * fx + uy * fy;
             S *o = at(fout + (int64_t)c * 9 * I.plane, own[r]);
             double s_out = 0.0;
@@ -542,8 +546,8 @@ __device__ void process_tile(const Inst &I, int tile_x, int tile_y, int parity, 
             for (int i = 1; i < 9; ++i) {
                 const float cu = CX[i] * ux + CY[i] * uy;
                 const float cF = CX[i] * fx + CY[i] * fy;
-                const float deq = WF[i] * (drho + rc * (3.f * cu + 4.5f * cu * cu - 1.5f * uu));
-                const float src = WF[i] * I.guo * (3.f * (cF - uF) + 9.f * cu * cF);
+                const float deq = (WF[i] * SC) * (drho + rc * (3.f * cu + 4.5f * cu * cu - 1.5f * uu));
+                const float src = (WF[i] * SC) * I.guo * (3.f * (cF - uF) + 9.f * cu * cF);
                 const float di = d[r][c][i];
                 const auto q = Store<S>::enc(di + I.omega * (deq - di) + src);
                 s_out += (double)Store<S>::dec(q);

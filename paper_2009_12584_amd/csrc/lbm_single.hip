@@ -416,12 +416,13 @@ extern "C" int lbm_mask_disk(int32_t nx, int32_t ny, double cx, double cy, doubl
 // ---------------------------------------------------------------- copy probe
 
 namespace {
-// Streaming copy, 16 bytes per lane per iteration: the practical HBM ceiling
-// for a kernel that reads and writes the same byte count.
+// Streaming copy, one 16-byte vector per lane and one pass per workgroup
+// (no grid-stride loop): the practical HBM ceiling for a kernel that reads
+// and writes the same byte count.
 __global__ __launch_bounds__(256) void k_copy_probe(const uint4 *__restrict__ src, uint4 *__restrict__ dst,
                                                     size_t n16) {
-    const size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n16; k += stride) dst[k] = src[k];
+    const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n16) dst[k] = src[k];
 }
 }  // namespace
 
@@ -432,7 +433,11 @@ extern "C" int lbm_copy_probe(void *dst, const void *src, size_t bytes, void *st
     }
     const size_t n16 = bytes / 16;
     if (n16 == 0) return LBM_OK;
-    const unsigned blocks = (unsigned)std::min<size_t>((n16 + 255) / 256, 256 * 64);
+    if ((n16 + 255) / 256 > 0x7fffffffu) {
+        set_err("copy probe: at most 2^31 - 1 workgroups");
+        return LBM_EINVAL;
+    }
+    const unsigned blocks = (unsigned)((n16 + 255) / 256);
     hipLaunchKernelGGL(k_copy_probe, dim3(blocks), dim3(256), 0, (hipStream_t)stream, (const uint4 *)src,
                        (uint4 *)dst, n16);
     MCLBM_HIP(hipGetLastError());

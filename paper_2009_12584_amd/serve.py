@@ -1,0 +1,105 @@
+"""Served form: a request loop over the resident-slot pool (continuous batching).
+
+Requests arrive on a wall clock; each carries its wall mask, initial densities,
+parameters and step count.  The loop admits requests first-come first-served
+whenever the pool has a free slot and HBM budget (lbm_pool_admit), advances
+every active slot together in chunks of time steps (lbm_pool_advance: one
+batched launch per step; new slots join at the next chunk while older ones
+keep running), and retires finished slots (lbm_pool_poll / fields / release)
+without stopping the others.  Completion latency = retirement time - arrival
+time.  All stepping happens in the HIP library; this loop only schedules.
+"""
+from __future__ import annotations
+
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from .sim import Pool
+
+
+@dataclass
+class Request:
+    arrival: float          # seconds after the start of the trace
+    mask: np.ndarray
+    rhoA0: np.ndarray
+    rhoB0: np.ndarray
+    steps: int
+    params: dict
+    tag: object = None
+    fluid: int = 0
+
+
+@dataclass
+class Done:
+    tag: object
+    arrival: float
+    admitted: float
+    finished: float
+    steps: int
+    fluid: int
+    fields: tuple | None = field(default=None, repr=False)
+
+    @property
+    def latency(self) -> float:
+        return self.finished - self.arrival
+
+
+def serve(requests, *, hbm_budget, max_slots, storage="f32", chunk=200, depth=2, keep_fields=False, stream=None,
+          time_scale=1.0, idle_sleep=0.0002):
+    """Run the trace; returns (list of Done, makespan seconds).
+
+    At most `depth` chunks are in flight on the device, so a new solve waits
+    at most that many chunks before it joins the running batch.  time_scale
+    stretches the arrival times (1.0 = as given)."""
+    reqs = sorted(requests, key=lambda r: r.arrival)
+    for r in reqs:
+        if not r.fluid:
+            r.fluid = int((np.asarray(r.mask) == 0).sum())
+    pool = Pool(hbm_budget, max_slots, storage=storage, stream=stream)
+    queue = []
+    live = {}
+    done = []
+    nxt = 0
+    t0 = time.perf_counter()
+    try:
+        while nxt < len(reqs) or queue or live:
+            now = time.perf_counter() - t0
+            while nxt < len(reqs) and reqs[nxt].arrival * time_scale <= now:
+                queue.append(reqs[nxt])
+                nxt += 1
+            while queue:  # FIFO admission while a slot and the budget allow
+                r = queue[0]
+                slot = pool.admit(r.mask, r.rhoA0, r.rhoB0, r.steps, **r.params)
+                if slot is None:
+                    break
+                live[slot] = (r, time.perf_counter() - t0)
+                queue.pop(0)
+            if live:
+                launched, completed = pool.progress()
+                if launched - completed < depth * chunk:
+                    pool.advance(chunk)
+            finished = pool.poll() if live else []
+            for slot in finished:
+                r, ta = live.pop(slot)
+                f = pool.fields(slot) if keep_fields else None
+                pool.release(slot)
+                done.append(Done(r.tag, r.arrival * time_scale, ta, time.perf_counter() - t0, r.steps, r.fluid, f))
+            if not finished and not queue and nxt < len(reqs) and not live:
+                # nothing to do until the next arrival
+                time.sleep(max(0.0, min(0.01, reqs[nxt].arrival * time_scale - (time.perf_counter() - t0))))
+            elif not finished and live:
+                time.sleep(idle_sleep)
+        makespan = time.perf_counter() - t0
+    finally:
+        pool.close()
+    return done, makespan
+
+
+def summarize(done, makespan):
+    lat = np.array([d.latency for d in done])
+    lu = float(sum(d.fluid * d.steps for d in done))
+    return dict(requests=len(done), makespan_s=makespan, p50_latency_s=float(np.percentile(lat, 50)),
+                p99_latency_s=float(np.percentile(lat, 99)), mean_latency_s=float(lat.mean()),
+                fluid_mlups=lu / makespan / 1e6)

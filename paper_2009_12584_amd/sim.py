@@ -246,6 +246,13 @@ class Pool:
         check(lib().lbm_pool_release(self._h, int(slot)))
         self.shapes.pop(slot, None)
 
+    def progress(self):
+        """(launches enqueued, launches completed on the device)."""
+        a = ctypes.c_int64()
+        b = ctypes.c_int64()
+        check(lib().lbm_pool_progress(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
     def stats(self):
         a = ctypes.c_int32()
         b = ctypes.c_size_t()
