@@ -35,7 +35,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_FLUID = {"f32": 144, "f16": 72}   # 18 populations read + written per fluid node
-BYTES_PER_NODE_FLAGS = 1                     # one flag byte per node
+BYTES_PER_NODE_FLAGS = 2                     # one 16-bit node word per node
 KERNEL_SOURCES = ["lbm_device.hpp", "lbm_common.hpp", "lbm_single.hip", "lbm_batch.hip"]
 
 
@@ -225,7 +225,7 @@ def headline_row(M, torch, case, mask, fluid, nodes, args, probe, tile_y_for):
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic(kname, "k_step_improved_plane30_512x256.md"), "kernel": kname,
                      "bytes_per_launch": alg_bytes(fluid, nodes),
-                     "note": "algorithmic bytes = 144 B per fluid node + 1 B per node; the 18.9 MB working set "
+                     "note": "algorithmic bytes = 144 B per fluid node + 2 B node word per node; the 18.9 MB working set "
                              "stays in L2/Infinity Cache, see roofline_out_of_cache for HBM"},
         "copy_probe": probe,
     }

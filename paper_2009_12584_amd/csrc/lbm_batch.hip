@@ -89,7 +89,7 @@ void launch_batch(int storage, int ty, hipStream_t s, const TileLists &T, const 
 // Device memory of one instance, carved from one block.
 struct InstMem {
     size_t bytes = 0;
-    size_t off_buf0, off_buf1, off_node, off_nbr, off_cls, off_tflag, off_part, off_dd, off_fields;
+    size_t off_buf0, off_buf1, off_word, off_m25, off_nbr, off_cls, off_tflag, off_part, off_dd, off_fields;
 };
 
 inline size_t al(size_t x) { return (x + 255) / 256 * 256; }
@@ -107,7 +107,8 @@ InstMem layout(const lbm_params &p, int ty) {
     };
     m.off_buf0 = take(18 * plane * store_bytes(p.storage));
     m.off_buf1 = take(18 * plane * store_bytes(p.storage));
-    m.off_node = take(n);
+    m.off_word = take(plane * sizeof(uint16_t));
+    m.off_m25 = take(plane * sizeof(uint32_t));
     m.off_nbr = take(n);
     m.off_cls = take(n);
     m.off_tflag = take(tiles);
@@ -137,7 +138,7 @@ struct Prepared {
 // instance whose memory block is at base; enqueued on stream s.  The temporary
 // upload buffers are owned by the caller until the stream has drained them.
 int prepare(Prepared &P, const lbm_params &p, int ty, char *base, const uint8_t *mask, const double *rA,
-            const double *rB, hipStream_t s, uint8_t *dmask, uint8_t *node0, double *drA, double *drB) {
+            const double *rB, hipStream_t s, uint8_t *dmask, uint16_t *word0, double *drA, double *drB) {
     P.p = p;
     P.ty = ty;
     P.m = layout(p, ty);
@@ -147,38 +148,33 @@ int prepare(Prepared &P, const lbm_params &p, int ty, char *base, const uint8_t 
     fill_inst(P.I, p, rref, ty);
     P.ntiles = P.I.tiles_x * P.I.tiles_y;
     const size_t n = (size_t)p.nx * p.ny;
+    const size_t np = (size_t)P.I.plane;
     int64_t fl = 0;
     for (size_t k = 0; k < n; ++k) fl += mask[k] ? 0 : 1;
     P.fluid = fl;
     P.I.buf[0] = base + P.m.off_buf0;
     P.I.buf[1] = base + P.m.off_buf1;
-    uint8_t *node = (uint8_t *)(base + P.m.off_node);
+    uint16_t *word = (uint16_t *)(base + P.m.off_word);
+    uint32_t *m25 = (uint32_t *)(base + P.m.off_m25);
     P.nbr = (uint8_t *)(base + P.m.off_nbr);
     P.cls = (uint8_t *)(base + P.m.off_cls);
     uint8_t *tflag = (uint8_t *)(base + P.m.off_tflag);
     P.partials = (double *)(base + P.m.off_part);
     P.dd = (DiagDev *)(base + P.m.off_dd);
     P.fields = (float *)(base + P.m.off_fields);
-    P.I.node = node;
-    P.I.tflag = tflag;
-    const size_t bufbytes = 18 * (size_t)P.I.plane * store_bytes(p.storage);
+    const size_t bufbytes = 18 * np * store_bytes(p.storage);
     MCLBM_HIP(hipMemsetAsync(P.I.buf[0], 0, bufbytes, s));
     MCLBM_HIP(hipMemsetAsync(P.I.buf[1], 0, bufbytes, s));
+    MCLBM_HIP(hipMemsetAsync(word, 0, np * sizeof(uint16_t), s));
+    MCLBM_HIP(hipMemsetAsync(word0, 0, np * sizeof(uint16_t), s));
+    MCLBM_HIP(hipMemsetAsync(m25, 0, np * sizeof(uint32_t), s));
     MCLBM_HIP(hipMemsetAsync(P.dd, 0, sizeof(DiagDev), s));
     MCLBM_HIP(hipMemcpyAsync(dmask, mask, n, hipMemcpyHostToDevice, s));
     MCLBM_HIP(hipMemcpyAsync(drA, rA, n * sizeof(double), hipMemcpyHostToDevice, s));
     MCLBM_HIP(hipMemcpyAsync(drB, rB, n * sizeof(double), hipMemcpyHostToDevice, s));
-    const unsigned nb = (unsigned)((n + 255) / 256);
-    hipLaunchKernelGGL(k_classify, dim3(nb), dim3(256), 0, s, dmask, p.nx, p.ny, p.periodic, P.nbr, P.cls, node0);
-    hipLaunchKernelGGL(k_near, dim3(nb), dim3(256), 0, s, node0, p.nx, p.ny, p.periodic, node);
-    hipLaunchKernelGGL(k_tileflags, dim3(P.ntiles), dim3(256), 0, s, P.cls, p.nx, p.ny, ty, P.I.tiles_x, tflag);
-    if (p.storage == LBM_STORE_F16)
-        hipLaunchKernelGGL(k_init<__half>, dim3(nb), dim3(256), 0, s, P.I, drA, drB, (double)P.I.rrefA,
-                           (double)P.I.rrefB, 0);
-    else
-        hipLaunchKernelGGL(k_init<float>, dim3(nb), dim3(256), 0, s, P.I, drA, drB, (double)P.I.rrefA,
-                           (double)P.I.rrefB, 0);
-    MCLBM_HIP(hipGetLastError());
+    const Geometry g{P.nbr, P.cls, word, m25, tflag, word0};
+    int rc = enqueue_setup(P.I, p, ty, dmask, drA, drB, g, s);
+    if (rc) return rc;
     // drift threshold off in batched forms; step-0 mass recorded by the first fields pass
     launch_step(Launch{p.storage, ty, p.bc, MODE_FIELDS, true}, s, P.I, 0, Fields{}, P.partials, P.dd, 0);
     MCLBM_HIP(hipGetLastError());
@@ -228,25 +224,28 @@ int read_diag(Prepared &P, int parity, long long step, hipStream_t s, lbm_diag_t
 
 // Temporary upload buffers sized for the largest instance of a create/admit call.
 struct Staging {
-    uint8_t *mask = nullptr, *node0 = nullptr;
+    uint8_t *mask = nullptr;
+    uint16_t *word0 = nullptr;
     double *rA = nullptr, *rB = nullptr;
-    size_t cap = 0;
-    int ensure(size_t n) {
-        if (n <= cap) return LBM_OK;
+    size_t cap = 0, capw = 0;
+    int ensure(size_t n, size_t np) {
+        if (n <= cap && np <= capw) return LBM_OK;
         release();
         MCLBM_HIP(hipMalloc(&mask, n));
-        MCLBM_HIP(hipMalloc(&node0, n));
+        MCLBM_HIP(hipMalloc(&word0, np * sizeof(uint16_t)));
         MCLBM_HIP(hipMalloc(&rA, n * sizeof(double)));
         MCLBM_HIP(hipMalloc(&rB, n * sizeof(double)));
         cap = n;
+        capw = np;
         return LBM_OK;
     }
     void release() {
-        for (void *q : {(void *)mask, (void *)node0, (void *)rA, (void *)rB})
+        for (void *q : {(void *)mask, (void *)word0, (void *)rA, (void *)rB})
             if (q) (void)hipFree(q);
-        mask = node0 = nullptr;
+        mask = nullptr;
+        word0 = nullptr;
         rA = rB = nullptr;
-        cap = 0;
+        cap = capw = 0;
     }
 };
 
@@ -316,9 +315,12 @@ int lbm_batch_create(int32_t n, const lbm_params *params, const uint8_t *const *
         b->own_stream = true;
     }
     Staging st;
-    size_t maxn = 0;
-    for (int k = 0; k < n; ++k) maxn = std::max(maxn, (size_t)params[k].nx * params[k].ny);
-    int rc = st.ensure(maxn);
+    size_t maxn = 0, maxp = 0;
+    for (int k = 0; k < n; ++k) {
+        maxn = std::max(maxn, (size_t)params[k].nx * params[k].ny);
+        maxp = std::max(maxp, (size_t)params[k].ny * pitch_of(params[k].nx));
+    }
+    int rc = st.ensure(maxn, maxp);
     if (rc) {
         st.release();
         return bail(rc);
@@ -336,7 +338,7 @@ int lbm_batch_create(int32_t n, const lbm_params *params, const uint8_t *const *
             return bail(LBM_ENOMEM);
         }
         b->blocks.push_back(base);
-        rc = prepare(b->inst[k], p, b->ty, base, masks[k], rhoA0[k], rhoB0[k], b->stream, st.mask, st.node0, st.rA,
+        rc = prepare(b->inst[k], p, b->ty, base, masks[k], rhoA0[k], rhoB0[k], b->stream, st.mask, st.word0, st.rA,
                      st.rB);
         if (rc == LBM_OK && hipStreamSynchronize(b->stream) != hipSuccess) rc = LBM_EDEVICE;
         if (rc) {
@@ -635,12 +637,12 @@ int lbm_pool_admit(lbm_pool *P, const lbm_params *p, const uint8_t *mask, const 
     // set-up on the init stream overlaps the running batch
     const size_t n = (size_t)p->nx * p->ny;
     MCLBM_HIP(hipStreamSynchronize(P->init_stream));  // staging reuse
-    rc = P->st.ensure(n);
+    rc = P->st.ensure(n, (size_t)p->ny * pitch_of(p->nx));
     if (rc) {
         P->arena.release(off, m.bytes);
         return rc;
     }
-    rc = prepare(s.P, *p, P->ty, P->arena.base + off, mask, rhoA0, rhoB0, P->init_stream, P->st.mask, P->st.node0,
+    rc = prepare(s.P, *p, P->ty, P->arena.base + off, mask, rhoA0, rhoB0, P->init_stream, P->st.mask, P->st.word0,
                  P->st.rA, P->st.rB);
     if (rc) {
         P->arena.release(off, m.bytes);

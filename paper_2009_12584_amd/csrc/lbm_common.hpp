@@ -52,7 +52,7 @@ inline size_t footprint_bytes(const lbm_params &p) {
     const size_t plane = (size_t)p.ny * pitch_of(p.nx);
     const int ty = default_ty(p);
     const size_t tiles = (size_t)((p.nx + TX - 1) / TX) * ((p.ny + ty - 1) / ty);
-    return 2 * 18 * plane * store_bytes(p.storage) + 3 * n + tiles + tiles * 48 + sizeof(DiagDev) + 4096;
+    return 2 * 18 * plane * store_bytes(p.storage) + 2 * n + plane * 8 + tiles + tiles * 48 + sizeof(DiagDev) + 4096;
 }
 
 // Validation of everything that can be checked on the host before any device
@@ -66,9 +66,9 @@ inline int validate(const lbm_params *p, const uint8_t *mask, const double *rA, 
         set_err("grid %d x %d: both sizes must be >= 1", p->nx, p->ny);
         return LBM_EINVAL;
     }
-    // one component's 9 planes are addressed with 32-bit byte offsets
-    if ((double)p->ny * pitch_of(p->nx) * 9.0 * (double)store_bytes(p->storage) >= 4294967296.0) {
-        set_err("grid %d x %d: one component exceeds 4 GiB of populations", p->nx, p->ny);
+    // the 9 planes of (A, B) pairs are addressed with 32-bit byte offsets
+    if ((double)p->ny * pitch_of(p->nx) * 18.0 * (double)store_bytes(p->storage) >= 4294967296.0) {
+        set_err("grid %d x %d: a population buffer would exceed 4 GiB", p->nx, p->ny);
         return LBM_EINVAL;
     }
     if (!(p->tau > 0.5) || !std::isfinite(p->tau)) {
@@ -175,9 +175,11 @@ inline void fill_inst(Inst &I, const lbm_params &p, const double rref[2], int ty
 
 // ---------------------------------------------------------------- set-up kernels
 
-// Stair classification and node flags (Fig. 1A caption; Sections 3.1, 3.2).
-static __global__ void k_classify(const uint8_t *__restrict__ mask, int nx, int ny, uint32_t periodic,
-                           uint8_t *__restrict__ nbr, uint8_t *__restrict__ cls, uint8_t *__restrict__ node) {
+// Stair classification (Fig. 1A caption; Sections 3.1, 3.2) and the node
+// words: neighbour solid bits, solid, interface solid.  nbr and cls are the
+// ABI outputs (nx * ny); word0 has the row pitch of the population planes.
+static __global__ void k_classify(const uint8_t *__restrict__ mask, int nx, int ny, uint32_t periodic, int pitch,
+                                  uint8_t *__restrict__ nbr, uint8_t *__restrict__ cls, uint16_t *__restrict__ word0) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= (int64_t)nx * ny) return;
     const int x = (int)(k % nx), y = (int)(k / nx);
@@ -200,18 +202,18 @@ static __global__ void k_classify(const uint8_t *__restrict__ mask, int nx, int 
     const uint8_t c = solid ? (bits != 0xFFu ? 2 : 3) : (bits ? 1 : 0);
     nbr[k] = (uint8_t)bits;
     cls[k] = c;
-    node[k] = solid ? (uint8_t)(NF_SOLID | (c == 2 ? NF_IFACE : 0)) : (uint8_t)0;
+    word0[(int64_t)y * pitch + x] = (uint16_t)(bits | (solid ? NW_SOLID : 0u) | (c == 2 ? NW_IFACE : 0u));
 }
 
-// Fluid nodes within Chebyshev distance 2 of an interface solid: the only
-// fluid nodes whose density enters an Eq. 7 average.
-static __global__ void k_near(const uint8_t *__restrict__ node_in, int nx, int ny, uint32_t periodic,
-                       uint8_t *__restrict__ node_out) {
+// Near-wall bit: fluid nodes within Chebyshev distance 2 of an interface solid,
+// the only fluid nodes whose density enters an Eq. 7 average.
+static __global__ void k_near(const uint16_t *__restrict__ word0, int nx, int ny, uint32_t periodic, int pitch,
+                              uint16_t *__restrict__ word) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= (int64_t)nx * ny) return;
     const int x = (int)(k % nx), y = (int)(k / nx);
-    uint8_t f = node_in[k];
-    if (!(f & NF_SOLID)) {
+    uint32_t f = word0[(int64_t)y * pitch + x];
+    if (!(f & NW_SOLID)) {
         bool near = false;
         for (int dy = -2; dy <= 2 && !near; ++dy)
             for (int dx = -2; dx <= 2; ++dx) {
@@ -224,14 +226,44 @@ static __global__ void k_near(const uint8_t *__restrict__ node_in, int nx, int n
                     if (!(periodic & 2u)) continue;
                     yn = wrap(yn, ny, true);
                 }
-                if (node_in[(int64_t)yn * nx + xn] & NF_IFACE) {
+                if (word0[(int64_t)yn * pitch + xn] & NW_IFACE) {
                     near = true;
                     break;
                 }
             }
-        if (near) f |= NF_NEAR;
+        if (near) f |= NW_NEAR;
     }
-    node_out[k] = f;
+    word[(int64_t)y * pitch + x] = (uint16_t)f;
+}
+
+// For interface solids: bit j set when the j-th D2Q25 neighbour (rows dy = -2..2,
+// columns dx = -2..2, centre skipped) is fluid and inside the domain (Eq. 7).
+static __global__ void k_m25(const uint16_t *__restrict__ word, int nx, int ny, uint32_t periodic, int pitch,
+                             uint32_t *__restrict__ m25) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= (int64_t)nx * ny) return;
+    const int x = (int)(k % nx), y = (int)(k / nx);
+    uint32_t m = 0;
+    if (word[(int64_t)y * pitch + x] & NW_IFACE) {
+        int j = 0;
+        for (int dy = -2; dy <= 2; ++dy)
+            for (int dx = -2; dx <= 2; ++dx) {
+                if (dx == 0 && dy == 0) continue;
+                int xn = x + dx, yn = y + dy;
+                bool in = true;
+                if (xn < 0 || xn >= nx) {
+                    if (periodic & 1u) xn = wrap(xn, nx, true);
+                    else in = false;
+                }
+                if (yn < 0 || yn >= ny) {
+                    if (periodic & 2u) yn = wrap(yn, ny, true);
+                    else in = false;
+                }
+                if (in && !(word[(int64_t)yn * pitch + xn] & NW_SOLID)) m |= 1u << j;
+                ++j;
+            }
+    }
+    m25[(int64_t)y * pitch + x] = m;
 }
 
 // Per tile: does an owned fluid node touch a solid (then the improved scheme
@@ -258,18 +290,58 @@ __global__ void k_init(Inst I, const double *__restrict__ rA, const double *__re
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= (int64_t)I.nx * I.ny) return;
     const int x = (int)(k % I.nx), y = (int)(k / I.nx);
-    if (I.node[k] & NF_SOLID) return;
-    S *b = (S *)I.buf[which];
+    if (I.node[(int64_t)y * I.pitch + x] & NW_SOLID) return;
+    using P = typename Store<S>::P;
+    P *b = (P *)I.buf[which];
     const int64_t own = (int64_t)y * I.pitch + x;
     const double wd[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+    const double sc = (double)Store<S>::SC;
     for (int j = 0; j < 9; ++j) {
         const int xs = wrap(x + CX[j], I.nx, true), ys = wrap(y + CY[j], I.ny, true);
         int64_t src = (int64_t)ys * I.nx + xs;
-        if (I.node[src] & NF_SOLID) src = k;
-        const double sc = (double)Store<S>::SC;
-        Store<S>::put(b + (int64_t)j * I.plane + own, Store<S>::enc((float)(wd[j] * (rA[src] - rrefA) * sc)));
-        Store<S>::put(b + (int64_t)(9 + j) * I.plane + own, Store<S>::enc((float)(wd[j] * (rB[src] - rrefB) * sc)));
+        if (I.node[(int64_t)ys * I.pitch + xs] & NW_SOLID) src = k;
+        Store<S>::put2(b + (int64_t)j * I.plane + own, Store<S>::enc2((float)(wd[j] * (rA[src] - rrefA) * sc),
+                                                                      (float)(wd[j] * (rB[src] - rrefB) * sc)));
     }
+}
+
+// Device arrays of one simulation's geometry (all allocated by the caller).
+struct Geometry {
+    uint8_t *nbr, *cls;   // nx * ny, the classification returned by the ABI
+    uint16_t *word;       // ny * pitch node words
+    uint32_t *m25;        // ny * pitch D2Q25 fluid masks of interface solids
+    uint8_t *tflag;       // tiles
+    uint16_t *word0;      // ny * pitch scratch for the set-up
+};
+
+inline size_t geometry_bytes(int nx, int ny, int pitch, int ntiles) {
+    const size_t n = (size_t)nx * ny, np = (size_t)ny * pitch;
+    return 2 * n + 2 * np * sizeof(uint16_t) + np * sizeof(uint32_t) + (size_t)ntiles;
+}
+
+// Classification, node words, Eq. 7 masks, tile flags and the initial
+// populations of one simulation, enqueued on stream s (I.buf[0] is written).
+inline int enqueue_setup(Inst &I, const lbm_params &p, int ty, const uint8_t *dmask, const double *drA,
+                         const double *drB, const Geometry &g, hipStream_t s) {
+    const size_t n = (size_t)p.nx * p.ny;
+    const unsigned nb = (unsigned)((n + 255) / 256);
+    hipLaunchKernelGGL(k_classify, dim3(nb), dim3(256), 0, s, dmask, p.nx, p.ny, p.periodic, I.pitch, g.nbr, g.cls,
+                       g.word0);
+    hipLaunchKernelGGL(k_near, dim3(nb), dim3(256), 0, s, g.word0, p.nx, p.ny, p.periodic, I.pitch, g.word);
+    hipLaunchKernelGGL(k_m25, dim3(nb), dim3(256), 0, s, g.word, p.nx, p.ny, p.periodic, I.pitch, g.m25);
+    hipLaunchKernelGGL(k_tileflags, dim3((unsigned)(I.tiles_x * I.tiles_y)), dim3(256), 0, s, g.cls, p.nx, p.ny, ty,
+                       I.tiles_x, g.tflag);
+    I.node = g.word;
+    I.m25 = g.m25;
+    I.tflag = g.tflag;
+    if (p.storage == LBM_STORE_F16)
+        hipLaunchKernelGGL(k_init<__half>, dim3(nb), dim3(256), 0, s, I, drA, drB, (double)I.rrefA, (double)I.rrefB,
+                           0);
+    else
+        hipLaunchKernelGGL(k_init<float>, dim3(nb), dim3(256), 0, s, I, drA, drB, (double)I.rrefA, (double)I.rrefB,
+                           0);
+    MCLBM_HIP(hipGetLastError());
+    return LBM_OK;
 }
 
 // ---------------------------------------------------------------- step kernels

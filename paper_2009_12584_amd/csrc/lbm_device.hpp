@@ -3,7 +3,6 @@
 //
 // One workgroup of 256 threads (4 wavefronts) owns a tile of 64 x TY lattice
 // nodes and performs one whole time step for it:
-//   phase 0  node flags of the tile plus a halo of 4 into LDS
 //   phase 1  pull streaming with half-way bounce-back for the owned nodes
 //            (populations kept in registers) and for a ring of halo nodes
 //            (densities only); densities rho^A, rho^B into LDS  (Eqs. 1, 3)
@@ -19,12 +18,20 @@
 // node out), but only at fluid nodes within reach of an interface solid and
 // only in tiles that touch a wall; all other tiles use the 1-node halo.
 //
-// Populations are stored per (component, direction) plane, row pitch a
-// multiple of 64 elements, as deviations d_i = f_i - w_i rho_ref in FP32 or
-// scaled FP16.  The buffer read in a step holds the post-collision values of
-// the previous step at their node of origin (pull scheme).  Loads address a
-// component's 9 planes from one uniform base with 32-bit byte offsets (one
-// component stays below 4 GiB), stores a plane base plus the node offset.
+// Geometry comes from one 16-bit word per node, precomputed once: which of the
+// 8 neighbours are solid (bounce-back directions and the fluid/solid split of
+// Eqs. 5-6 without looking at neighbours), solid, interface solid, and fluid
+// within reach of an interface solid; interface solids also have a 24-bit
+// mask of their fluid D2Q25 neighbours for Eq. 7.
+//
+// Populations are stored as 9 direction planes, row pitch a multiple of 64
+// nodes, each element the pair (A, B) of one direction -- both components are
+// pulled from the same upstream node, so one load brings both -- as
+// deviations d_i = f_i - w_i rho_ref in FP32 (float2) or scaled FP16 (half2).
+// The buffer read in a step holds the post-collision values of the previous
+// step at their node of origin (pull scheme).  Loads address the 9 planes from
+// one uniform base with 32-bit byte offsets (a buffer stays below 4 GiB),
+// stores a plane base plus the node offset.
 #pragma once
 
 #include <hip/hip_fp16.h>
@@ -38,7 +45,11 @@ constexpr int NT = 256;       // threads per workgroup
 constexpr int HMAX = 3;       // widest density halo (improved scheme, D2Q25 average)
 constexpr int FH = HMAX + 1;  // flag halo: a halo node's pull needs its neighbours' phi
 
-enum : uint8_t { NF_SOLID = 1, NF_IFACE = 2, NF_NEAR = 4 };
+// Node word: bit (i-1), i = 1..8, set when neighbour x + c_i is solid or lies
+// beyond a closed border; then the flags below.
+enum : uint32_t { NW_SOLID = 1u << 8, NW_IFACE = 1u << 9, NW_NEAR = 1u << 10 };
+// LDS flags of the tile plus one ring
+enum : uint8_t { LF_SOLID = 1, LF_IFACE = 2 };
 enum : uint8_t { TF_NEEDS_RT = 1 };
 enum : int { BC_MC = 0, BC_LLKC = 1, BC_IMPROVED = 2 };
 enum : int { MODE_STEP = 0, MODE_FIELDS = 1 };
@@ -61,18 +72,20 @@ __device__ constexpr float W25_BY_R2[9] = {0.f,        4.f / 21.f, 4.f / 45.f, 0
 // momentum sums, so loads and stores are bare conversions.
 template <typename S> struct Store;
 template <> struct Store<float> {
+    using P = float2;  // one direction of components A and B
     static constexpr float SC = 1.f;
-    static __device__ __forceinline__ float ld(const float *p) { return *p; }
-    static __device__ __forceinline__ float enc(float v) { return v; }
-    static __device__ __forceinline__ float dec(float v) { return v; }
-    static __device__ __forceinline__ void put(float *p, float v) { *p = v; }
+    static __device__ __forceinline__ float2 ld2(const float2 *p) { return *p; }
+    static __device__ __forceinline__ float2 enc2(float a, float b) { return make_float2(a, b); }
+    static __device__ __forceinline__ float2 dec2(float2 v) { return v; }
+    static __device__ __forceinline__ void put2(float2 *p, float2 v) { *p = v; }
 };
 template <> struct Store<__half> {
+    using P = __half2;
     static constexpr float SC = 1024.f;
-    static __device__ __forceinline__ float ld(const __half *p) { return __half2float(*p); }
-    static __device__ __forceinline__ __half enc(float v) { return __float2half_rn(v); }
-    static __device__ __forceinline__ float dec(__half v) { return __half2float(v); }
-    static __device__ __forceinline__ void put(__half *p, __half v) { *p = v; }
+    static __device__ __forceinline__ float2 ld2(const __half2 *p) { return __half22float2(*p); }
+    static __device__ __forceinline__ __half2 enc2(float a, float b) { return __floats2half2_rn(a, b); }
+    static __device__ __forceinline__ float2 dec2(__half2 v) { return __half22float2(v); }
+    static __device__ __forceinline__ void put2(__half2 *p, __half2 v) { *p = v; }
 };
 
 template <typename S> __device__ __forceinline__ const S *at(const S *base, uint32_t byte_off) {
@@ -95,7 +108,8 @@ __device__ __forceinline__ double dsum9(const float d[9]) {
 // take it by value; the batched kernels read it from a table.
 struct Inst {
     void *buf[2];             // population buffers; parity selects the one read
-    const uint8_t *node;      // NF_* per node, row-major nx * ny
+    const uint16_t *node;     // node words, row pitch `pitch`
+    const uint32_t *m25;      // fluid D2Q25 neighbours of interface solids, row pitch `pitch`
     const uint8_t *tflag;     // TF_* per tile
     int nx, ny, pitch, tiles_x, tiles_y;
     int64_t plane;            // elements per population plane = ny * pitch
@@ -136,22 +150,17 @@ __device__ __forceinline__ int wrap(int g, int n, bool small) {
 }
 
 template <int TY> struct Smem {
-    static constexpr int FW = TX + 2 * FH;   // flag tile width
-    static constexpr int FHh = TY + 2 * FH;  // flag tile height
     static constexpr int RW = TX + 2 * HMAX; // density tile width
     static constexpr int RH = TY + 2 * HMAX;
-    static constexpr int VW = TX + 2;        // virtual density tile width
+    static constexpr int VW = TX + 2;        // tile + 1 ring
     static constexpr int VH = TY + 2;
-    uint8_t flag[FHh * FW];
     float rho[2][RH * RW];
     float rt[2][VH * VW];
+    uint8_t lf[VH * VW];
     double red[NT / 64][5];
     int redi[NT / 64];
 };
 
-template <int TY> __device__ __forceinline__ uint8_t flag_at(const Smem<TY> &sm, int lx, int ly) {
-    return sm.flag[(ly + FH) * Smem<TY>::FW + (lx + FH)];
-}
 template <int TY> __device__ __forceinline__ int rho_idx(int lx, int ly) {
     return (ly + HMAX) * Smem<TY>::RW + (lx + HMAX);
 }
@@ -159,43 +168,65 @@ template <int TY> __device__ __forceinline__ int rt_idx(int lx, int ly) {
     return (ly + 1) * Smem<TY>::VW + (lx + 1);
 }
 
-// Bit i set when the upstream node x - c_i of local node (lx, ly) is solid.
-template <int TY> __device__ __forceinline__ unsigned upstream_solid(const Smem<TY> &sm, int lx, int ly) {
-    unsigned m = 0;
-#pragma unroll
-    for (int i = 1; i < 9; ++i) m |= (unsigned)(flag_at<TY>(sm, lx - CX[i], ly - CY[i]) & NF_SOLID) << i;
-    return m;
+// Node word at global (gx, gy) near a tile: wrapped in periodic directions,
+// solid beyond a closed border.
+__device__ __forceinline__ uint32_t node_word(const Inst &I, int gx, int gy) {
+    if ((unsigned)gx >= (unsigned)I.nx) {
+        if (!(I.periodic & 1u)) return NW_SOLID;
+        gx = wrap(gx, I.nx, I.small != 0);
+    }
+    if ((unsigned)gy >= (unsigned)I.ny) {
+        if (!(I.periodic & 2u)) return NW_SOLID;
+        gy = wrap(gy, I.ny, I.small != 0);
+    }
+    return I.node[(size_t)gy * I.pitch + gx];
 }
 
-// Byte offsets, within one population plane, of the 3 x 3 block around a node.
+// Byte offsets, within one population plane, of the 3 x 3 block around a fluid
+// node.  Only tiles on a periodic border (edge) need the wrap: elsewhere a
+// fluid node's neighbours are inside the domain.
 struct Around {
     uint32_t row[3], col[3];
 };
 
-template <typename S> __device__ __forceinline__ Around around(const Inst &I, int gx, int gy) {
-    const bool small = I.small != 0;
+template <typename S> __device__ __forceinline__ Around around(const Inst &I, int gx, int gy, bool edge) {
     Around a;
+    if (!edge) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            a.col[j] = (uint32_t)(gx - 1 + j) * (uint32_t)sizeof(S) * 2u;
+            a.row[j] = (uint32_t)(gy - 1 + j) * (uint32_t)(I.pitch * sizeof(S) * 2);
+        }
+        return a;
+    }
+    const bool small = I.small != 0;
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-        a.col[j] = (uint32_t)wrap(gx - 1 + j, I.nx, small) * (uint32_t)sizeof(S);
-        a.row[j] = (uint32_t)wrap(gy - 1 + j, I.ny, small) * (uint32_t)(I.pitch * sizeof(S));
+        a.col[j] = (uint32_t)wrap(gx - 1 + j, I.nx, small) * (uint32_t)sizeof(S) * 2u;
+        a.row[j] = (uint32_t)wrap(gy - 1 + j, I.ny, small) * (uint32_t)(I.pitch * sizeof(S) * 2);
     }
     return a;
 }
 
-// Pull the 9 populations of one component at a fluid node (Eq. 1 streaming,
-// half-way bounce-back where the upstream node x - c_i is solid).  cbase is
-// the component's first plane, pb the plane size in bytes.
+// Pull the 9 populations of both components at a fluid node (Eq. 1 streaming,
+// half-way bounce-back where the upstream node x - c_i = x + c_opp(i) is solid,
+// read from the node word).  base is the first plane, pb the plane size in
+// bytes; dA, dB receive storage units.
 template <typename S>
-__device__ __forceinline__ void pull9(const S *__restrict__ cbase, uint32_t pb, const Around &a, unsigned solid_up,
-                                      float d[9]) {
+__device__ __forceinline__ void pull9(const typename Store<S>::P *__restrict__ base, uint32_t pb, const Around &a,
+                                      uint32_t w, float dA[9], float dB[9]) {
     const uint32_t own = a.row[1] + a.col[1];
+    float2 v = Store<S>::ld2(at(base, own));
+    dA[0] = v.x;
+    dB[0] = v.y;
 #pragma unroll
-    for (int i = 0; i < 9; ++i) {
+    for (int i = 1; i < 9; ++i) {
         const uint32_t up = a.row[1 - CY[i]] + a.col[1 - CX[i]];
-        const bool bb = (solid_up >> i) & 1u;
+        const bool bb = (w >> (OPP[i] - 1)) & 1u;
         const uint32_t off = bb ? (uint32_t)OPP[i] * pb + own : (uint32_t)i * pb + up;
-        d[i] = Store<S>::ld(at(cbase, off));
+        v = Store<S>::ld2(at(base, off));
+        dA[i] = v.x;
+        dB[i] = v.y;
     }
 }
 
@@ -258,15 +289,15 @@ template <int TY> __device__ void diag_partial(Smem<TY> &sm, const DiagAcc &a, d
 
 // Density pass over the halo frame of width HF (compile time): rows above and
 // below the tile, columns left and right of it.  Beyond the first ring only
-// fluid nodes within reach of an interface solid are needed (Eq. 7).
+// fluid nodes within reach of an interface solid are needed (Eq. 7).  First-ring
+// positions also record their solid / interface-solid flags in LDS.
 template <typename S, int TY, int HF>
-__device__ __forceinline__ void frame_pass(const Inst &I, Smem<TY> &sm, const S *__restrict__ fin, uint32_t pb,
-                                           int tx0, int ty0, const float rref[2]) {
+__device__ __forceinline__ void frame_pass(const Inst &I, Smem<TY> &sm, const typename Store<S>::P *__restrict__ fin,
+                                           uint32_t pb, int tx0, int ty0, bool edge, const float rref[2]) {
     constexpr int W = TX + 2 * HF;
     constexpr int NBAND = HF * W;
     constexpr int NSIDE = HF * TY;
     constexpr int TOTAL = 2 * NBAND + 2 * NSIDE;
-    const S *finB = fin + 9 * I.plane;
     for (int k = threadIdx.x; k < TOTAL; k += NT) {
         int hx, hy;
         if (k < NBAND) {
@@ -285,18 +316,19 @@ __device__ __forceinline__ void frame_pass(const Inst &I, Smem<TY> &sm, const S 
             hy = q / HF;
             hx = TX + q % HF;
         }
-        const uint8_t f = flag_at<TY>(sm, hx, hy);
+        const int gx = tx0 + hx, gy = ty0 + hy;
+        const uint32_t w = node_word(I, gx, gy);
         const int ring = max(max(-hx, hx - (TX - 1)), max(-hy, hy - (TY - 1)));
+        if (ring == 1)
+            sm.lf[rt_idx<TY>(hx, hy)] = (uint8_t)(((w & NW_SOLID) ? LF_SOLID : 0) | ((w & NW_IFACE) ? LF_IFACE : 0));
         float ra = 0.f, rb = 0.f;
-        const bool want = !(f & NF_SOLID) && (HF == 1 || ring <= 1 || (f & NF_NEAR));
+        const bool want = !(w & NW_SOLID) && (HF == 1 || ring <= 1 || (w & NW_NEAR));
         if (want) {
-            const Around a = around<S>(I, tx0 + hx, ty0 + hy);
-            const unsigned su = upstream_solid<TY>(sm, hx, hy);
-            float dd[9];
-            pull9<S>(fin, pb, a, su, dd);
-            ra = (float)((double)rref[0] + dsum9(dd) * (double)(1.f / Store<S>::SC));
-            pull9<S>(finB, pb, a, su, dd);
-            rb = (float)((double)rref[1] + dsum9(dd) * (double)(1.f / Store<S>::SC));
+            const Around a = around<S>(I, gx, gy, edge);
+            float dA[9], dB[9];
+            pull9<S>(fin, pb, a, w, dA, dB);
+            ra = (float)((double)rref[0] + dsum9(dA) * (double)(1.f / Store<S>::SC));
+            rb = (float)((double)rref[1] + dsum9(dB) * (double)(1.f / Store<S>::SC));
         }
         sm.rho[0][rho_idx<TY>(hx, hy)] = ra;
         sm.rho[1][rho_idx<TY>(hx, hy)] = rb;
@@ -309,62 +341,47 @@ template <typename S, int TY, int BC, int MODE, bool DIAG>
 __device__ void process_tile(const Inst &I, int tile_x, int tile_y, int parity, Smem<TY> &sm, DiagAcc &acc,
                              const Fields &fo) {
     constexpr int RPT = TY / 4;  // tile rows per thread
+    constexpr float SC = Store<S>::SC;
     const int tid = threadIdx.x;
     const int tx0 = tile_x * TX, ty0 = tile_y * TY;
-    const S *__restrict__ fin = (const S *)I.buf[parity];
-    S *__restrict__ fout = (S *)I.buf[parity ^ 1];
-    const uint32_t pb = (uint32_t)(I.plane * (int64_t)sizeof(S));
-    const S *finB = fin + 9 * I.plane;
-    const bool px = I.periodic & 1u, py = (I.periodic >> 1) & 1u;
-    const bool small = I.small != 0;
+    using P = typename Store<S>::P;
+    const P *__restrict__ fin = (const P *)I.buf[parity];
+    P *__restrict__ fout = (P *)I.buf[parity ^ 1];
+    const uint32_t pb = (uint32_t)(I.plane * (int64_t)sizeof(P));
     const float rref[2] = {I.rrefA, I.rrefB};
+    // tiles whose halo crosses a periodic border need coordinate wraps
+    const bool edge = I.small || ((I.periodic & 1u) && (tx0 - FH < 0 || tx0 + TX + FH > I.nx)) ||
+                      ((I.periodic & 2u) && (ty0 - FH < 0 || ty0 + TY + FH > I.ny));
 
     const bool need_rt = (BC == BC_IMPROVED) &&
                          (MODE == MODE_FIELDS || (I.tflag[tile_y * I.tiles_x + tile_x] & TF_NEEDS_RT));
-
-    // ---- phase 0: node flags with a halo of FH, wrapped or solid outside
-    for (int k = tid; k < Smem<TY>::FW * Smem<TY>::FHh; k += NT) {
-        const int lx = k % Smem<TY>::FW - FH, ly = k / Smem<TY>::FW - FH;
-        int gx = tx0 + lx, gy = ty0 + ly;
-        uint8_t f = NF_SOLID;
-        const bool inx = (gx >= 0 && gx < I.nx) || px;
-        const bool iny = (gy >= 0 && gy < I.ny) || py;
-        if (inx && iny) {
-            gx = wrap(gx, I.nx, small);
-            gy = wrap(gy, I.ny, small);
-            f = I.node[(size_t)gy * I.nx + gx];
-        }
-        sm.flag[k] = f;
-    }
-    __syncthreads();
 
     // ---- phase 1a: owned rectangle; populations stay in registers
     const int lx = tid & (TX - 1);
     const int lr = tid >> 6;
     float d[RPT][2][9];
-    double sd[RPT][2];  // exact incoming deviation sums
-    bool fluid[RPT];
+    double sd[RPT][2];  // exact incoming deviation sums, storage units
+    uint32_t w[RPT];    // node words
     uint32_t own[RPT];  // byte offset of the owned node in a plane
     bool owned[RPT];
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
         const int ly = lr + 4 * r;
         const int gx = tx0 + lx, gy = ty0 + ly;
-        const uint8_t f = flag_at<TY>(sm, lx, ly);
+        w[r] = node_word(I, gx, gy);
         owned[r] = gx < I.nx && gy < I.ny;
-        fluid[r] = !(f & NF_SOLID);
-        own[r] = (uint32_t)(gy * I.pitch + gx) * (uint32_t)sizeof(S);
+        own[r] = (uint32_t)(gy * I.pitch + gx) * (uint32_t)sizeof(P);
+        sm.lf[rt_idx<TY>(lx, ly)] =
+            (uint8_t)(((w[r] & NW_SOLID) ? LF_SOLID : 0) | ((w[r] & NW_IFACE) ? LF_IFACE : 0));
         float ra = 0.f, rb = 0.f;
         sd[r][0] = sd[r][1] = 0.0;
-        if (fluid[r]) {
-            const Around a = around<S>(I, gx, gy);
-            const unsigned su = upstream_solid<TY>(sm, lx, ly);
-            pull9<S>(fin, pb, a, su, d[r][0]);
-            pull9<S>(finB, pb, a, su, d[r][1]);
-            sd[r][0] = dsum9(d[r][0]);  // storage units
+        if (!(w[r] & NW_SOLID)) {
+            const Around a = around<S>(I, gx, gy, edge);
+            pull9<S>(fin, pb, a, w[r], d[r][0], d[r][1]);
+            sd[r][0] = dsum9(d[r][0]);
             sd[r][1] = dsum9(d[r][1]);
-            ra = (float)((double)rref[0] + sd[r][0] * (double)(1.f / Store<S>::SC));
-            rb = (float)((double)rref[1] + sd[r][1] * (double)(1.f / Store<S>::SC));
+            ra = (float)((double)rref[0] + sd[r][0] * (double)(1.f / SC));
+            rb = (float)((double)rref[1] + sd[r][1] * (double)(1.f / SC));
         }
         sm.rho[0][rho_idx<TY>(lx, ly)] = ra;
         sm.rho[1][rho_idx<TY>(lx, ly)] = rb;
@@ -372,9 +389,9 @@ __device__ void process_tile(const Inst &I, int tile_x, int tile_y, int parity, 
 
     // ---- phase 1b: halo frame
     if (need_rt)
-        frame_pass<S, TY, HMAX>(I, sm, fin, pb, tx0, ty0, rref);
+        frame_pass<S, TY, HMAX>(I, sm, fin, pb, tx0, ty0, edge, rref);
     else
-        frame_pass<S, TY, 1>(I, sm, fin, pb, tx0, ty0, rref);
+        frame_pass<S, TY, 1>(I, sm, fin, pb, tx0, ty0, edge, rref);
     __syncthreads();
 
     // ---- phase 2: virtual solid density of Eq. 7 on interface solids in tile + 1
@@ -383,31 +400,27 @@ __device__ void process_tile(const Inst &I, int tile_x, int tile_y, int parity, 
         for (int k = tid; k < Smem<TY>::VW * Smem<TY>::VH; k += NT) {
             const int vx = k % Smem<TY>::VW - 1, vy = k / Smem<TY>::VW - 1;
             float ta = 0.f, tb = 0.f;
-            if (flag_at<TY>(sm, vx, vy) & NF_IFACE) {
+            if (sm.lf[k] & LF_IFACE) {
+                // interface solids lie inside the domain or across a periodic border
+                const int gx = wrap(tx0 + vx, I.nx, true), gy = wrap(ty0 + vy, I.ny, true);
+                const uint32_t m = I.m25[(size_t)gy * I.pitch + gx];
                 float na = 0.f, nb = 0.f, den = 0.f;
-                if (I.avg == 0) {
+                int j = 0;
 #pragma unroll
-                    for (int ey = -2; ey <= 2; ++ey)
+                for (int ey = -2; ey <= 2; ++ey)
 #pragma unroll
-                        for (int ex = -2; ex <= 2; ++ex) {
-                            if (ex == 0 && ey == 0) continue;
-                            const float w = W25_BY_R2[ex * ex + ey * ey];
-                            if (!(flag_at<TY>(sm, vx + ex, vy + ey) & NF_SOLID)) {
-                                na += w * sm.rho[0][rho_idx<TY>(vx + ex, vy + ey)];
-                                nb += w * sm.rho[1][rho_idx<TY>(vx + ex, vy + ey)];
-                                den += w;
-                            }
+                    for (int ex = -2; ex <= 2; ++ex) {
+                        if (ex == 0 && ey == 0) continue;
+                        const int r2 = ex * ex + ey * ey;
+                        // D2Q25 weights, or the D2Q9 ones on the first belt
+                        const float wt = I.avg == 0 ? W25_BY_R2[r2] : (r2 == 1 ? 1.f / 9.f : (r2 == 2 ? 1.f / 36.f : 0.f));
+                        if (((m >> j) & 1u) && wt != 0.f) {
+                            na += wt * sm.rho[0][rho_idx<TY>(vx + ex, vy + ey)];
+                            nb += wt * sm.rho[1][rho_idx<TY>(vx + ex, vy + ey)];
+                            den += wt;
                         }
-                } else {
-#pragma unroll
-                    for (int i = 1; i < 9; ++i) {
-                        if (!(flag_at<TY>(sm, vx + CX[i], vy + CY[i]) & NF_SOLID)) {
-                            na += WF[i] * sm.rho[0][rho_idx<TY>(vx + CX[i], vy + CY[i])];
-                            nb += WF[i] * sm.rho[1][rho_idx<TY>(vx + CX[i], vy + CY[i])];
-                            den += WF[i];
-                        }
+                        ++j;
                     }
-                }
                 // den > 0: an interface solid has a fluid first-belt neighbour
                 ta = chi[0] * na / den;
                 tb = chi[1] * nb / den;
@@ -424,7 +437,7 @@ __device__ void process_tile(const Inst &I, int tile_x, int tile_y, int parity, 
         const int ly = lr + 4 * r;
         if (!owned[r]) continue;
         const size_t oidx = (size_t)(ty0 + ly) * I.nx + (tx0 + lx);
-        if (!fluid[r]) {
+        if (w[r] & NW_SOLID) {
             if (MODE == MODE_FIELDS) {
                 if (fo.rhoA) fo.rhoA[oidx] = 0.f;
                 if (fo.rhoB) fo.rhoB[oidx] = 0.f;
@@ -449,20 +462,20 @@ __device__ void process_tile(const Inst &I, int tile_x, int tile_y, int parity, 
 #pragma unroll
         for (int i = 1; i < 9; ++i) {
             const int qx = lx + CX[i], qy = ly + CY[i];
-            const float w = WF[i];
-            if (!(flag_at<TY>(sm, qx, qy) & NF_SOLID)) {
-                const float a = w * sm.rho[0][rho_idx<TY>(qx, qy)];
-                const float b = w * sm.rho[1][rho_idx<TY>(qx, qy)];
+            const float wi = WF[i];
+            if (!((w[r] >> (i - 1)) & 1u)) {
+                const float a = wi * sm.rho[0][rho_idx<TY>(qx, qy)];
+                const float b = wi * sm.rho[1][rho_idx<TY>(qx, qy)];
                 sax += a * CX[i];
                 say += a * CY[i];
                 sbx += b * CX[i];
                 sby += b * CY[i];
             } else {
-                nxs += w * CX[i];
-                nys += w * CY[i];
+                nxs += wi * CX[i];
+                nys += wi * CY[i];
                 if (BC == BC_IMPROVED) {
-                    const float a = w * sm.rt[0][rt_idx<TY>(qx, qy)];
-                    const float b = w * sm.rt[1][rt_idx<TY>(qx, qy)];
+                    const float a = wi * sm.rt[0][rt_idx<TY>(qx, qy)];
+                    const float b = wi * sm.rt[1][rt_idx<TY>(qx, qy)];
                     tax += a * CX[i];
                     tay += a * CY[i];
                     tbx += b * CX[i];
@@ -495,8 +508,8 @@ __device__ void process_tile(const Inst &I, int tile_x, int tile_y, int parity, 
             jx += (d[r][c][1] - d[r][c][3]) + (d[r][c][5] - d[r][c][6]) + (d[r][c][8] - d[r][c][7]);
             jy += (d[r][c][2] - d[r][c][4]) + (d[r][c][5] - d[r][c][8]) + (d[r][c][6] - d[r][c][7]);
         }
-        jx *= 1.f / Store<S>::SC;
-        jy *= 1.f / Store<S>::SC;
+        jx *= 1.f / SC;
+        jy *= 1.f / SC;
         const float rt = ra + rb;
         const float inv = 1.f / rt;
         const float ux = (jx + 0.5f * (FAx + FBx)) * inv;
@@ -504,8 +517,8 @@ __device__ void process_tile(const Inst &I, int tile_x, int tile_y, int parity, 
 
         if (DIAG) {
             // exact per-node mass: reference plus the exact deviation sum
-            acc.mA += (double)rref[0] + sd[r][0] * (double)(1.f / Store<S>::SC);
-            acc.mB += (double)rref[1] + sd[r][1] * (double)(1.f / Store<S>::SC);
+            acc.mA += (double)rref[0] + sd[r][0] * (double)(1.f / SC);
+            acc.mB += (double)rref[1] + sd[r][1] * (double)(1.f / SC);
             acc.px += (double)rt * (double)ux;
             acc.py += (double)rt * (double)uy;
             acc.u2max = fmaxf(acc.u2max, ux * ux + uy * uy);
@@ -529,32 +542,36 @@ __device__ void process_tile(const Inst &I, int tile_x, int tile_y, int parity, 
         // populations are computed and rounded to storage; the rest population
         // takes the exact remainder of the incoming deviation sum, so the stored
         // node mass equals the incoming one up to a single rounding (no
-        // systematic FP32 mass drift).
-        constexpr float SC = Store<S>::SC;
+        // systematic FP32 mass drift).  The velocity terms of the equilibrium
+        // are common to both components.
         const float uu = ux * ux + uy * uy;
-        const float rho_c[2] = {ra, rb};
-        const float Fx_c[2] = {FAx, FBx}, Fy_c[2] = {FAy, FBy};
+        float eq[9];
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            const float rc = rho_c[c], fx = Fx_c[c], fy = Fy_c[c];
-            const double s_in = sd[r][c];
-            const float drho = (float)s_in * (1.f / SC);
-            const float uF = ux * fx + uy * fy;
-            S *o = at(fout + (int64_t)c * 9 * I.plane, own[r]);
-            double s_out = 0.0;
-#pragma unroll
-            for (int i = 1; i < 9; ++i) {
-                const float cu = CX[i] * ux + CY[i] * uy;
-                const float cF = CX[i] * fx + CY[i] * fy;
-                const float deq = (WF[i] * SC) * (drho + rc * (3.f * cu + 4.5f * cu * cu - 1.5f * uu));
-                const float src = (WF[i] * SC) * I.guo * (3.f * (cF - uF) + 9.f * cu * cF);
-                const float di = d[r][c][i];
-                const auto q = Store<S>::enc(di + I.omega * (deq - di) + src);
-                s_out += (double)Store<S>::dec(q);
-                Store<S>::put(at(o, (uint32_t)i * pb), q);
-            }
-            Store<S>::put(o, Store<S>::enc((float)(s_in - s_out)));
+        for (int i = 1; i < 9; ++i) {
+            const float cu = CX[i] * ux + CY[i] * uy;
+            eq[i] = 3.f * cu + 4.5f * cu * cu - 1.5f * uu;
         }
+        const float uFA = ux * FAx + uy * FAy, uFB = ux * FBx + uy * FBy;
+        const float drA = (float)sd[r][0] * (1.f / SC), drB = (float)sd[r][1] * (1.f / SC);
+        P *o = at(fout, own[r]);
+        double soA = 0.0, soB = 0.0;
+#pragma unroll
+        for (int i = 1; i < 9; ++i) {
+            const float cu = CX[i] * ux + CY[i] * uy;
+            const float cFA = CX[i] * FAx + CY[i] * FAy;
+            const float cFB = CX[i] * FBx + CY[i] * FBy;
+            const float deqA = (WF[i] * SC) * (drA + ra * eq[i]);
+            const float deqB = (WF[i] * SC) * (drB + rb * eq[i]);
+            const float srcA = (WF[i] * SC) * I.guo * (3.f * (cFA - uFA) + 9.f * cu * cFA);
+            const float srcB = (WF[i] * SC) * I.guo * (3.f * (cFB - uFB) + 9.f * cu * cFB);
+            const float dA = d[r][0][i], dB = d[r][1][i];
+            const auto q = Store<S>::enc2(dA + I.omega * (deqA - dA) + srcA, dB + I.omega * (deqB - dB) + srcB);
+            const float2 qd = Store<S>::dec2(q);
+            soA += (double)qd.x;
+            soB += (double)qd.y;
+            Store<S>::put2(at(o, (uint32_t)i * pb), q);
+        }
+        Store<S>::put2(o, Store<S>::enc2((float)(sd[r][0] - soA), (float)(sd[r][1] - soB)));
     }
 }
 

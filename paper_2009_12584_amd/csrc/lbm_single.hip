@@ -11,7 +11,9 @@ struct lbm_handle {
     Inst I{};
     int ty = 8;
     int ntiles = 0;
-    uint8_t *node = nullptr, *tflag = nullptr, *nbr = nullptr, *cls = nullptr;
+    uint8_t *tflag = nullptr, *nbr = nullptr, *cls = nullptr;
+    uint16_t *word = nullptr;
+    uint32_t *m25 = nullptr;
     double *partials = nullptr;
     DiagDev *dd = nullptr;
     float *fields = nullptr;  // lazily allocated: 10 planes of nx*ny
@@ -35,8 +37,8 @@ void release(lbm_handle *h) {
     if (h->stream) (void)hipStreamSynchronize(h->stream);
     if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
     if (h->graph) (void)hipGraphDestroy(h->graph);
-    for (void *q : {(void *)h->I.buf[0], (void *)h->I.buf[1], (void *)h->node, (void *)h->tflag, (void *)h->nbr,
-                    (void *)h->cls, (void *)h->partials, (void *)h->dd, (void *)h->fields})
+    for (void *q : {(void *)h->I.buf[0], (void *)h->I.buf[1], (void *)h->word, (void *)h->m25, (void *)h->tflag,
+                    (void *)h->nbr, (void *)h->cls, (void *)h->partials, (void *)h->dd, (void *)h->fields})
         if (q) (void)hipFree(q);
     if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
     delete h;
@@ -126,54 +128,47 @@ int lbm_create(const lbm_params *p, const uint8_t *mask, const double *rhoA0, co
     h->ntiles = h->I.tiles_x * h->I.tiles_y;
     const size_t n = (size_t)p->nx * p->ny;
     const size_t bufbytes = 18 * (size_t)h->I.plane * store_bytes(p->storage);
-    uint8_t *dmask = nullptr, *node0 = nullptr;
+    uint8_t *dmask = nullptr;
+    uint16_t *word0 = nullptr;
     double *drA = nullptr, *drB = nullptr;
+    const size_t np = (size_t)h->I.plane;
     auto dev = [&]() -> int {
         MCLBM_HIP(hipMalloc(&h->I.buf[0], bufbytes));
         MCLBM_HIP(hipMalloc(&h->I.buf[1], bufbytes));
-        MCLBM_HIP(hipMalloc(&h->node, n));
+        MCLBM_HIP(hipMalloc(&h->word, np * sizeof(uint16_t)));
+        MCLBM_HIP(hipMalloc(&h->m25, np * sizeof(uint32_t)));
         MCLBM_HIP(hipMalloc(&h->nbr, n));
         MCLBM_HIP(hipMalloc(&h->cls, n));
         MCLBM_HIP(hipMalloc(&h->tflag, h->ntiles));
         MCLBM_HIP(hipMalloc(&h->partials, sizeof(double) * 6 * (size_t)h->ntiles));
         MCLBM_HIP(hipMalloc(&h->dd, sizeof(DiagDev)));
         MCLBM_HIP(hipMalloc(&dmask, n));
-        MCLBM_HIP(hipMalloc(&node0, n));
+        MCLBM_HIP(hipMalloc(&word0, np * sizeof(uint16_t)));
         MCLBM_HIP(hipMalloc(&drA, n * sizeof(double)));
         MCLBM_HIP(hipMalloc(&drB, n * sizeof(double)));
         hipStream_t s = h->stream;
         MCLBM_HIP(hipMemsetAsync(h->I.buf[0], 0, bufbytes, s));
         MCLBM_HIP(hipMemsetAsync(h->I.buf[1], 0, bufbytes, s));
+        MCLBM_HIP(hipMemsetAsync(h->word, 0, np * sizeof(uint16_t), s));
+        MCLBM_HIP(hipMemsetAsync(word0, 0, np * sizeof(uint16_t), s));
+        MCLBM_HIP(hipMemsetAsync(h->m25, 0, np * sizeof(uint32_t), s));
         DiagDev z{};
         z.drift_tol = p->drift_tol;
         MCLBM_HIP(hipMemcpyAsync(h->dd, &z, sizeof z, hipMemcpyHostToDevice, s));
         MCLBM_HIP(hipMemcpyAsync(dmask, mask, n, hipMemcpyHostToDevice, s));
         MCLBM_HIP(hipMemcpyAsync(drA, rhoA0, n * sizeof(double), hipMemcpyHostToDevice, s));
         MCLBM_HIP(hipMemcpyAsync(drB, rhoB0, n * sizeof(double), hipMemcpyHostToDevice, s));
-        const unsigned nb = (unsigned)((n + 255) / 256);
-        hipLaunchKernelGGL(k_classify, dim3(nb), dim3(256), 0, s, dmask, p->nx, p->ny, p->periodic, h->nbr, h->cls,
-                           node0);
-        hipLaunchKernelGGL(k_near, dim3(nb), dim3(256), 0, s, node0, p->nx, p->ny, p->periodic, h->node);
-        hipLaunchKernelGGL(k_tileflags, dim3(h->ntiles), dim3(256), 0, s, h->cls, p->nx, p->ny, h->ty,
-                           h->I.tiles_x, h->tflag);
-        MCLBM_HIP(hipGetLastError());
-        h->I.node = h->node;
-        h->I.tflag = h->tflag;
-        if (p->storage == LBM_STORE_F16)
-            hipLaunchKernelGGL(k_init<__half>, dim3(nb), dim3(256), 0, s, h->I, drA, drB, (double)h->I.rrefA,
-                               (double)h->I.rrefB, 0);
-        else
-            hipLaunchKernelGGL(k_init<float>, dim3(nb), dim3(256), 0, s, h->I, drA, drB, (double)h->I.rrefA,
-                               (double)h->I.rrefB, 0);
-        MCLBM_HIP(hipGetLastError());
+        const Geometry g{h->nbr, h->cls, h->word, h->m25, h->tflag, word0};
+        int r = enqueue_setup(h->I, *p, h->ty, dmask, drA, drB, g, s);
+        if (r) return r;
         // mass at step 0 for the drift check
-        int r = run_fields(h, Fields{});
+        r = run_fields(h, Fields{});
         if (r) return r;
         MCLBM_HIP(hipStreamSynchronize(s));
         return LBM_OK;
     };
     rc = dev();
-    for (void *q : {(void *)dmask, (void *)node0, (void *)drA, (void *)drB})
+    for (void *q : {(void *)dmask, (void *)word0, (void *)drA, (void *)drB})
         if (q) (void)hipFree(q);
     if (rc) return bail(rc);
     if (p->graph_steps > 0) {
