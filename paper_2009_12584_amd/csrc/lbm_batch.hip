@@ -33,7 +33,7 @@ __global__ __launch_bounds__(NT) void k_batch_step(const Inst *__restrict__ inst
     if (L >= I.t_end) return;  // this slot has finished; the whole block leaves together
     const int parity = (I.parity0 ^ launch_parity) & 1;
     int tx, ty;
-    tile_coords(e.y, I.tiles_x, I.tiles_y, tx, ty);
+    tile_coords(e.y, I.tiles_x, I.tiles_y, I.tg, tx, ty);
     DiagAcc acc;
     process_tile<S, TY, BC, MODE_STEP, false>(I, tx, ty, parity, sm, acc, Fields{});
 }

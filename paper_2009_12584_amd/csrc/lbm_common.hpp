@@ -169,6 +169,10 @@ inline void fill_inst(Inst &I, const lbm_params &p, const double rref[2], int ty
     I.chiB = (float)p.chi[1];
     I.rrefA = (float)rref[0];
     I.rrefB = (float)rref[1];
+    // tile walk in groups of 16 tile columns; streaming stores (the next step
+    // reads them from HBM anyway on grids larger than the caches)
+    I.tg = 16;
+    I.nt = 1;
     I.parity0 = 0;
     I.t_end = INT64_MAX;
 }
@@ -358,20 +362,19 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
 // columns (TG x 64 nodes = 4 KiB of FP32 per row, long contiguous HBM runs),
 // down each group row by row, so the tile below a tile runs TG tiles later on
 // the same XCD while the rows their density halos share are still in L2.
-constexpr int TG = 16;
-__device__ __forceinline__ void tile_coords(int t, int tiles_x, int tiles_y, int &tx, int &ty) {
-    const int per_group = TG * tiles_y;
+__device__ __forceinline__ void tile_coords(int t, int tiles_x, int tiles_y, int tg, int &tx, int &ty) {
+    const int per_group = tg * tiles_y;
     const int g = t / per_group, r = t - g * per_group;
-    const int gw = min(TG, tiles_x - g * TG);
+    const int gw = min(tg, tiles_x - g * tg);
     ty = r / gw;
-    tx = g * TG + (r - ty * gw);
+    tx = g * tg + (r - ty * gw);
 }
 
 template <typename S, int TY, int BC, int MODE, bool DIAG>
 __global__ __launch_bounds__(NT) void k_step(Inst I, int parity, Fields fo, double *partials) {
     __shared__ Smem<TY> sm;
     int tx, ty;
-    tile_coords(xcd_tile(blockIdx.x, gridDim.x), I.tiles_x, I.tiles_y, tx, ty);
+    tile_coords(xcd_tile(blockIdx.x, gridDim.x), I.tiles_x, I.tiles_y, I.tg, tx, ty);
     DiagAcc acc;
     process_tile<S, TY, BC, MODE, DIAG>(I, tx, ty, parity, sm, acc, fo);
     if (DIAG) diag_partial<TY>(sm, acc, partials, blockIdx.x);

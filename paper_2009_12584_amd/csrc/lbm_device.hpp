@@ -78,6 +78,11 @@ template <> struct Store<float> {
     static __device__ __forceinline__ float2 enc2(float a, float b) { return make_float2(a, b); }
     static __device__ __forceinline__ float2 dec2(float2 v) { return v; }
     static __device__ __forceinline__ void put2(float2 *p, float2 v) { *p = v; }
+    static __device__ __forceinline__ void put2nt(float2 *p, float2 v) {
+        typedef float f2v __attribute__((ext_vector_type(2)));
+        f2v t = {v.x, v.y};
+        __builtin_nontemporal_store(t, (f2v *)p);
+    }
 };
 template <> struct Store<__half> {
     using P = __half2;
@@ -86,6 +91,9 @@ template <> struct Store<__half> {
     static __device__ __forceinline__ __half2 enc2(float a, float b) { return __floats2half2_rn(a, b); }
     static __device__ __forceinline__ float2 dec2(__half2 v) { return __half22float2(v); }
     static __device__ __forceinline__ void put2(__half2 *p, __half2 v) { *p = v; }
+    static __device__ __forceinline__ void put2nt(__half2 *p, __half2 v) {
+        __builtin_nontemporal_store(__builtin_bit_cast(uint32_t, v), (uint32_t *)p);
+    }
 };
 
 template <typename S> __device__ __forceinline__ const S *at(const S *base, uint32_t byte_off) {
@@ -120,6 +128,8 @@ struct Inst {
     float G, GsA, GsB;        // Eq. 5 strength and the adhesion strengths of Eq. 6
     float chiA, chiB;         // Eq. 7
     float rrefA, rrefB;       // deviation references
+    int tg;                   // tile columns per group of the tile walk
+    int nt;                   // streaming (non-temporal) stores
     int parity0;              // pool: parity of the buffer read at launch counter 0
     int64_t t_end;            // pool: launch counter at which this instance stops
 };
@@ -356,7 +366,9 @@ __device__ void process_tile(const Inst &I, int tile_x, int tile_y, int parity, 
     const bool need_rt = (BC == BC_IMPROVED) &&
                          (MODE == MODE_FIELDS || (I.tflag[tile_y * I.tiles_x + tile_x] & TF_NEEDS_RT));
 
-    // ---- phase 1a: owned rectangle; populations stay in registers
+    // ---- phase 1a: owned rectangle; populations stay in registers.  The
+    // loads are issued here and consumed after the frame pass has issued its
+    // own, so the two memory latencies overlap.
     const int lx = tid & (TX - 1);
     const int lr = tid >> 6;
     float d[RPT][2][9];
@@ -373,18 +385,13 @@ __device__ void process_tile(const Inst &I, int tile_x, int tile_y, int parity, 
         own[r] = (uint32_t)(gy * I.pitch + gx) * (uint32_t)sizeof(P);
         sm.lf[rt_idx<TY>(lx, ly)] =
             (uint8_t)(((w[r] & NW_SOLID) ? LF_SOLID : 0) | ((w[r] & NW_IFACE) ? LF_IFACE : 0));
-        float ra = 0.f, rb = 0.f;
-        sd[r][0] = sd[r][1] = 0.0;
         if (!(w[r] & NW_SOLID)) {
             const Around a = around<S>(I, gx, gy, edge);
             pull9<S>(fin, pb, a, w[r], d[r][0], d[r][1]);
-            sd[r][0] = dsum9(d[r][0]);
-            sd[r][1] = dsum9(d[r][1]);
-            ra = (float)((double)rref[0] + sd[r][0] * (double)(1.f / SC));
-            rb = (float)((double)rref[1] + sd[r][1] * (double)(1.f / SC));
+        } else {
+#pragma unroll
+            for (int i = 0; i < 9; ++i) d[r][0][i] = d[r][1][i] = 0.f;
         }
-        sm.rho[0][rho_idx<TY>(lx, ly)] = ra;
-        sm.rho[1][rho_idx<TY>(lx, ly)] = rb;
     }
 
     // ---- phase 1b: halo frame
@@ -392,6 +399,17 @@ __device__ void process_tile(const Inst &I, int tile_x, int tile_y, int parity, 
         frame_pass<S, TY, HMAX>(I, sm, fin, pb, tx0, ty0, edge, rref);
     else
         frame_pass<S, TY, 1>(I, sm, fin, pb, tx0, ty0, edge, rref);
+
+    // ---- phase 1c: owned densities (solid nodes hold no fluid)
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+        const int ly = lr + 4 * r;
+        sd[r][0] = dsum9(d[r][0]);
+        sd[r][1] = dsum9(d[r][1]);
+        const bool fl = !(w[r] & NW_SOLID);
+        sm.rho[0][rho_idx<TY>(lx, ly)] = fl ? (float)((double)rref[0] + sd[r][0] * (double)(1.f / SC)) : 0.f;
+        sm.rho[1][rho_idx<TY>(lx, ly)] = fl ? (float)((double)rref[1] + sd[r][1] * (double)(1.f / SC)) : 0.f;
+    }
     __syncthreads();
 
     // ---- phase 2: virtual solid density of Eq. 7 on interface solids in tile + 1
@@ -569,9 +587,16 @@ __device__ void process_tile(const Inst &I, int tile_x, int tile_y, int parity, 
             const float2 qd = Store<S>::dec2(q);
             soA += (double)qd.x;
             soB += (double)qd.y;
-            Store<S>::put2(at(o, (uint32_t)i * pb), q);
+            if (I.nt)
+                Store<S>::put2nt(at(o, (uint32_t)i * pb), q);
+            else
+                Store<S>::put2(at(o, (uint32_t)i * pb), q);
         }
-        Store<S>::put2(o, Store<S>::enc2((float)(sd[r][0] - soA), (float)(sd[r][1] - soB)));
+        const auto q0 = Store<S>::enc2((float)(sd[r][0] - soA), (float)(sd[r][1] - soB));
+        if (I.nt)
+            Store<S>::put2nt(o, q0);
+        else
+            Store<S>::put2(o, q0);
     }
 }
 
