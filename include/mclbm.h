@@ -77,7 +77,7 @@ typedef struct {
     double drift_tol;    /* relative mass drift that flags LBM_ENUMERIC; <= 0 = off */
     int32_t graph_steps; /* > 0: lbm_step replays a captured HIP graph of this many
                             steps (rounded up to even); 0 = plain launches */
-    int32_t tile_y;      /* rows per tile: 0 = default, else one of 4, 8, 16 */
+    int32_t tile_y;      /* rows per tile: 0 = default (8), else 4, 8, 16 or 32 (512-thread workgroups) */
 } lbm_params;
 
 /* Diagnostics, reduced in FP64 over fluid nodes at the handle's current time. */

@@ -16,7 +16,7 @@ import time
 
 from .sim import Batch, Simulation
 
-CANDIDATES = (4, 8, 16)
+CANDIDATES = (4, 8, 16, 32)
 _CACHE_PATH = os.path.join(os.path.expanduser("~"), ".cache", "mclbm", "autotune.json")
 _cache = None
 

@@ -24,7 +24,7 @@ using namespace mclbm;
 namespace {
 
 template <typename S, int TY, int BC>
-__global__ __launch_bounds__(NT) void k_batch_step(const Inst *__restrict__ insts, const int2 *__restrict__ tiles,
+__global__ __launch_bounds__(threads_for(TY)) void k_batch_step(const Inst *__restrict__ insts, const int2 *__restrict__ tiles,
                                                    int launch_parity, long long L) {
     __shared__ Smem<TY> sm;
     const int t = xcd_tile(blockIdx.x, gridDim.x);
@@ -66,7 +66,7 @@ TileLists build_tiles(int n, InstOf inst_of, std::vector<int2> &out) {
 
 template <typename S, int TY>
 void launch_batch_ty(hipStream_t s, const TileLists &T, const Inst *insts, const int2 *tiles, int lp, long long L) {
-    const dim3 b(NT);
+    const dim3 b(threads_for(TY));
     if (T.cnt[0]) hipLaunchKernelGGL((k_batch_step<S, TY, BC_MC>), dim3(T.cnt[0]), b, 0, s, insts, tiles + T.off[0], lp, L);
     if (T.cnt[1]) hipLaunchKernelGGL((k_batch_step<S, TY, BC_LLKC>), dim3(T.cnt[1]), b, 0, s, insts, tiles + T.off[1], lp, L);
     if (T.cnt[2])
@@ -78,10 +78,12 @@ void launch_batch(int storage, int ty, hipStream_t s, const TileLists &T, const 
     if (storage == LBM_STORE_F16) {
         if (ty == 4) launch_batch_ty<__half, 4>(s, T, insts, tiles, lp, L);
         else if (ty == 16) launch_batch_ty<__half, 16>(s, T, insts, tiles, lp, L);
+        else if (ty == 32) launch_batch_ty<__half, 32>(s, T, insts, tiles, lp, L);
         else launch_batch_ty<__half, 8>(s, T, insts, tiles, lp, L);
     } else {
         if (ty == 4) launch_batch_ty<float, 4>(s, T, insts, tiles, lp, L);
         else if (ty == 16) launch_batch_ty<float, 16>(s, T, insts, tiles, lp, L);
+        else if (ty == 32) launch_batch_ty<float, 32>(s, T, insts, tiles, lp, L);
         else launch_batch_ty<float, 8>(s, T, insts, tiles, lp, L);
     }
 }

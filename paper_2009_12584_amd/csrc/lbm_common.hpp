@@ -88,8 +88,8 @@ inline int validate(const lbm_params *p, const uint8_t *mask, const double *rA, 
         set_err("periodic = %u: only bits 0 and 1 may be set", p->periodic);
         return LBM_EINVAL;
     }
-    if (p->tile_y != 0 && p->tile_y != 4 && p->tile_y != 8 && p->tile_y != 16) {
-        set_err("tile_y = %d: must be 0, 4, 8 or 16", p->tile_y);
+    if (p->tile_y != 0 && p->tile_y != 4 && p->tile_y != 8 && p->tile_y != 16 && p->tile_y != 32) {
+        set_err("tile_y = %d: must be 0, 4, 8, 16 or 32", p->tile_y);
         return LBM_EINVAL;
     }
     if (p->diag_every < 0 || p->graph_steps < 0) {
@@ -371,7 +371,7 @@ __device__ __forceinline__ void tile_coords(int t, int tiles_x, int tiles_y, int
 }
 
 template <typename S, int TY, int BC, int MODE, bool DIAG>
-__global__ __launch_bounds__(NT) void k_step(Inst I, int parity, Fields fo, double *partials) {
+__global__ __launch_bounds__(threads_for(TY)) void k_step(Inst I, int parity, Fields fo, double *partials) {
     __shared__ Smem<TY> sm;
     int tx, ty;
     tile_coords(xcd_tile(blockIdx.x, gridDim.x), I.tiles_x, I.tiles_y, I.tg, tx, ty);
@@ -438,11 +438,11 @@ template <typename S, int TY, int BC>
 inline void launch3(const Launch &L, dim3 g, hipStream_t s, const Inst &I, int parity, const Fields &fo,
                     double *partials) {
     if (L.mode == MODE_FIELDS)
-        hipLaunchKernelGGL((k_step<S, TY, BC, MODE_FIELDS, true>), g, dim3(NT), 0, s, I, parity, fo, partials);
+        hipLaunchKernelGGL((k_step<S, TY, BC, MODE_FIELDS, true>), g, dim3(threads_for(TY)), 0, s, I, parity, fo, partials);
     else if (L.diag)
-        hipLaunchKernelGGL((k_step<S, TY, BC, MODE_STEP, true>), g, dim3(NT), 0, s, I, parity, fo, partials);
+        hipLaunchKernelGGL((k_step<S, TY, BC, MODE_STEP, true>), g, dim3(threads_for(TY)), 0, s, I, parity, fo, partials);
     else
-        hipLaunchKernelGGL((k_step<S, TY, BC, MODE_STEP, false>), g, dim3(NT), 0, s, I, parity, fo, partials);
+        hipLaunchKernelGGL((k_step<S, TY, BC, MODE_STEP, false>), g, dim3(threads_for(TY)), 0, s, I, parity, fo, partials);
 }
 
 template <typename S, int TY>
@@ -461,6 +461,7 @@ inline void launch1(const Launch &L, dim3 g, hipStream_t s, const Inst &I, int p
     switch (L.ty) {
     case 4: launch2<S, 4>(L, g, s, I, parity, fo, partials); break;
     case 16: launch2<S, 16>(L, g, s, I, parity, fo, partials); break;
+    case 32: launch2<S, 32>(L, g, s, I, parity, fo, partials); break;
     default: launch2<S, 8>(L, g, s, I, parity, fo, partials); break;
     }
 }

@@ -41,7 +41,9 @@
 namespace mclbm {
 
 constexpr int TX = 64;        // tile width: one wavefront per tile row
-constexpr int NT = 256;       // threads per workgroup
+// Threads per workgroup for a tile of TY rows: 4 wavefronts, or 8 for the
+// 32-row tile (each thread then owns TY / (threads / 64) rows).
+constexpr int threads_for(int TY) { return TY == 32 ? 512 : 256; }
 constexpr int HMAX = 3;       // widest density halo (improved scheme, D2Q25 average)
 constexpr int FH = HMAX + 1;  // flag halo: a halo node's pull needs its neighbours' phi
 
@@ -167,8 +169,8 @@ template <int TY> struct Smem {
     float rho[2][RH * RW];
     float rt[2][VH * VW];
     uint8_t lf[VH * VW];
-    double red[NT / 64][5];
-    int redi[NT / 64];
+    double red[threads_for(TY) / 64][5];
+    int redi[threads_for(TY) / 64];
 };
 
 template <int TY> __device__ __forceinline__ int rho_idx(int lx, int ly) {
@@ -282,7 +284,7 @@ template <int TY> __device__ void diag_partial(Smem<TY> &sm, const DiagAcc &a, d
     if (threadIdx.x == 0) {
         double s[4] = {0, 0, 0, 0}, m = 0.0;
         int f = 0;
-        for (int w = 0; w < NT / 64; ++w) {
+        for (int w = 0; w < threads_for(TY) / 64; ++w) {
             for (int q = 0; q < 4; ++q) s[q] += sm.red[w][q];
             m = fmax(m, sm.red[w][4]);
             f |= sm.redi[w];
@@ -308,7 +310,7 @@ __device__ __forceinline__ void frame_pass(const Inst &I, Smem<TY> &sm, const ty
     constexpr int NBAND = HF * W;
     constexpr int NSIDE = HF * TY;
     constexpr int TOTAL = 2 * NBAND + 2 * NSIDE;
-    for (int k = threadIdx.x; k < TOTAL; k += NT) {
+    for (int k = threadIdx.x; k < TOTAL; k += threads_for(TY)) {
         int hx, hy;
         if (k < NBAND) {
             hy = -HF + k / W;
@@ -350,7 +352,8 @@ __device__ __forceinline__ void frame_pass(const Inst &I, Smem<TY> &sm, const ty
 template <typename S, int TY, int BC, int MODE, bool DIAG>
 __device__ void process_tile(const Inst &I, int tile_x, int tile_y, int parity, Smem<TY> &sm, DiagAcc &acc,
                              const Fields &fo) {
-    constexpr int RPT = TY / 4;  // tile rows per thread
+    constexpr int RPP = threads_for(TY) / 64;  // tile rows per pass of the workgroup
+    constexpr int RPT = TY / RPP;             // tile rows per thread
     constexpr float SC = Store<S>::SC;
     const int tid = threadIdx.x;
     const int tx0 = tile_x * TX, ty0 = tile_y * TY;
@@ -378,7 +381,7 @@ __device__ void process_tile(const Inst &I, int tile_x, int tile_y, int parity, 
     bool owned[RPT];
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
-        const int ly = lr + 4 * r;
+        const int ly = lr + RPP * r;
         const int gx = tx0 + lx, gy = ty0 + ly;
         w[r] = node_word(I, gx, gy);
         owned[r] = gx < I.nx && gy < I.ny;
@@ -403,7 +406,7 @@ __device__ void process_tile(const Inst &I, int tile_x, int tile_y, int parity, 
     // ---- phase 1c: owned densities (solid nodes hold no fluid)
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
-        const int ly = lr + 4 * r;
+        const int ly = lr + RPP * r;
         sd[r][0] = dsum9(d[r][0]);
         sd[r][1] = dsum9(d[r][1]);
         const bool fl = !(w[r] & NW_SOLID);
@@ -415,7 +418,7 @@ __device__ void process_tile(const Inst &I, int tile_x, int tile_y, int parity, 
     // ---- phase 2: virtual solid density of Eq. 7 on interface solids in tile + 1
     if (BC == BC_IMPROVED && need_rt) {
         const float chi[2] = {I.chiA, I.chiB};
-        for (int k = tid; k < Smem<TY>::VW * Smem<TY>::VH; k += NT) {
+        for (int k = tid; k < Smem<TY>::VW * Smem<TY>::VH; k += threads_for(TY)) {
             const int vx = k % Smem<TY>::VW - 1, vy = k / Smem<TY>::VW - 1;
             float ta = 0.f, tb = 0.f;
             if (sm.lf[k] & LF_IFACE) {
@@ -452,7 +455,7 @@ __device__ void process_tile(const Inst &I, int tile_x, int tile_y, int parity, 
     // ---- phase 3: forces, velocity, collision, store
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
-        const int ly = lr + 4 * r;
+        const int ly = lr + RPP * r;
         if (!owned[r]) continue;
         const size_t oidx = (size_t)(ty0 + ly) * I.nx + (tx0 + lx);
         if (w[r] & NW_SOLID) {
