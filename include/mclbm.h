@@ -165,6 +165,39 @@ int lbm_mask_plane(int32_t nx, int32_t ny, double beta, double R0, int32_t borde
 int lbm_mask_disk(int32_t nx, int32_t ny, double cx, double cy, double R, int32_t borders,
                   uint8_t *out);
 
+/* ---- drop-shape diagnostics (Section 3.2) ---- */
+
+/* Contact-angle measurement as in Section 3.2: a circle fitted to the
+ * interface rho^A = level of a static drop (the paper uses 0.5); the angle
+ * then follows from the circle and the wall line on the host.
+ * Interface points: on every lattice edge between two fluid nodes (right and
+ * up neighbours, both inside roi, no wrap) whose end values lie on different
+ * sides of the level, (a < level) != (b < level), the point a + t (b - a) with
+ * t = (level - a) / (b - a), computed in FP64 from the FP32 density field.
+ * Edges with a solid node within chessboard distance skip (0..32) of either
+ * end are left out.  roi = {x0, y0, x1, y1}, inclusive node indices inside the
+ * grid; {0, 0, 0, 0} means the whole grid. */
+typedef struct {
+    double level;
+    int32_t skip;
+    int32_t roi[4];
+} lbm_contour_req;
+
+/* Algebraic least-squares circle x^2 + y^2 + D x + E y + F = 0 through the n
+ * interface points, in node coordinates (x = column, y = row), with the rms
+ * and largest radial distance of the points from it.  xc, yc, R are NaN when
+ * fewer than 3 points were found or the points do not fix a circle. */
+typedef struct {
+    int64_t n;
+    double xc, yc, R;
+    double rms, max_dev;
+} lbm_circle_t;
+
+/* Interface circle of the handle's current state (FP64 moments reduced on the
+ * device in a fixed order; deterministic).  Synchronises.  LBM_EINVAL for a
+ * bad level, skip or roi. */
+int lbm_contour_fit(lbm_handle *h, const lbm_contour_req *req, lbm_circle_t *out);
+
 /* Measurement aid: a plain streaming copy of bytes (a multiple of 16) from
  * src to dst, both device pointers, enqueued on stream.  Its achieved
  * bandwidth is the practical HBM ceiling for a kernel that reads and writes
@@ -184,6 +217,8 @@ int lbm_batch_create(int32_t n, const lbm_params *params, const uint8_t *const *
 int lbm_batch_step(lbm_batch *b, int64_t nsteps);
 int lbm_batch_fields(lbm_batch *b, int32_t idx, double *rhoA, double *rhoB, double *ux, double *uy);
 int lbm_batch_diag(lbm_batch *b, int32_t idx, lbm_diag_t *out);
+/* lbm_contour_fit for instance idx of the batch. */
+int lbm_batch_contour_fit(lbm_batch *b, int32_t idx, const lbm_contour_req *req, lbm_circle_t *out);
 int64_t lbm_batch_fluid_nodes(const lbm_batch *b);
 int lbm_batch_destroy(lbm_batch *b);
 

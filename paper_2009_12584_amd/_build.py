@@ -7,7 +7,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmclbm.so")
-SOURCES = ["lbm_single.hip", "lbm_batch.hip"]
+SOURCES = ["lbm_single.hip", "lbm_batch.hip", "lbm_analysis.hip"]
 HEADERS = ["lbm_device.hpp", "lbm_common.hpp"]
 
 FLAGS = [

@@ -22,6 +22,7 @@ EXPORTS = [
     "lbm_params_default", "lbm_create", "lbm_step", "lbm_time", "lbm_fields", "lbm_fields_device",
     "lbm_forces", "lbm_diag", "lbm_classify", "lbm_state_bytes", "lbm_get_state", "lbm_set_state",
     "lbm_destroy", "lbm_strerror", "lbm_last_error", "lbm_mask_plane", "lbm_mask_disk", "lbm_copy_probe",
+    "lbm_contour_fit", "lbm_batch_contour_fit",
     "lbm_batch_create", "lbm_batch_step", "lbm_batch_fields", "lbm_batch_diag", "lbm_batch_fluid_nodes",
     "lbm_batch_destroy", "lbm_pool_create", "lbm_pool_footprint", "lbm_pool_admit", "lbm_pool_advance",
     "lbm_pool_poll", "lbm_pool_fields", "lbm_pool_release", "lbm_pool_stats", "lbm_pool_progress",
@@ -45,6 +46,15 @@ class LbmDiag(ctypes.Structure):
         ("max_speed", ctypes.c_double), ("step", ctypes.c_int64), ("flags", ctypes.c_int32),
         ("pad", ctypes.c_int32),
     ]
+
+
+class LbmContourReq(ctypes.Structure):
+    _fields_ = [("level", ctypes.c_double), ("skip", ctypes.c_int32), ("roi", ctypes.c_int32 * 4)]
+
+
+class LbmCircle(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("xc", ctypes.c_double), ("yc", ctypes.c_double), ("R", ctypes.c_double),
+                ("rms", ctypes.c_double), ("max_dev", ctypes.c_double)]
 
 
 class LbmError(RuntimeError):
@@ -84,6 +94,8 @@ def lib():
             "lbm_mask_plane": (I32, [I32, I32, D, D, I32, P]),
             "lbm_mask_disk": (I32, [I32, I32, D, D, D, I32, P]),
             "lbm_copy_probe": (I32, [P, P, SZ, P]),
+            "lbm_contour_fit": (I32, [P, ctypes.POINTER(LbmContourReq), ctypes.POINTER(LbmCircle)]),
+            "lbm_batch_contour_fit": (I32, [P, I32, ctypes.POINTER(LbmContourReq), ctypes.POINTER(LbmCircle)]),
             "lbm_batch_create": (I32, [I32, PP, P, P, P, P, I32, ctypes.POINTER(P)]),
             "lbm_batch_step": (I32, [P, I64]),
             "lbm_batch_fields": (I32, [P, I32, P, P, P, P]),
@@ -140,3 +152,12 @@ def make_params(nx, ny, *, tau=1.0, G=0.9, bc=BC_MARTYS_CHEN, Gw=0.0, chiA=1.0, 
     p.diag_every, p.drift_tol = int(diag_every), float(drift_tol)
     p.graph_steps, p.tile_y = int(graph_steps), int(tile_y)
     return p
+
+
+def make_contour_req(level=0.5, skip=3, roi=None) -> LbmContourReq:
+    """roi = (x0, y0, x1, y1) inclusive, or None for the whole grid."""
+    q = LbmContourReq()
+    q.level, q.skip = float(level), int(skip)
+    for k, v in enumerate(roi if roi is not None else (0, 0, 0, 0)):
+        q.roi[k] = int(v)
+    return q

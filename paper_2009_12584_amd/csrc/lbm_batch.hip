@@ -269,6 +269,7 @@ struct lbm_batch {
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     int glen = 0;
+    double *cwork = nullptr;  // lazily allocated: contour-fit work buffer
 };
 
 static void batch_release(lbm_batch *b) {
@@ -280,6 +281,7 @@ static void batch_release(lbm_batch *b) {
         if (q) (void)hipFree(q);
     if (b->d_inst) (void)hipFree(b->d_inst);
     if (b->d_tiles) (void)hipFree(b->d_tiles);
+    if (b->cwork) (void)hipFree(b->cwork);
     if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
     delete b;
 }
@@ -406,6 +408,18 @@ int lbm_batch_fields(lbm_batch *b, int32_t idx, double *rhoA, double *rhoB, doub
 int lbm_batch_diag(lbm_batch *b, int32_t idx, lbm_diag_t *out) {
     if (!b || !out || idx < 0 || idx >= (int)b->inst.size()) return LBM_EINVAL;
     return read_diag(b->inst[idx], (int)(b->t & 1), b->t, b->stream, out);
+}
+
+int lbm_batch_contour_fit(lbm_batch *b, int32_t idx, const lbm_contour_req *req, lbm_circle_t *out) {
+    if (!b || idx < 0 || idx >= (int)b->inst.size()) return LBM_EINVAL;
+    if (!b->cwork) MCLBM_HIP(hipMalloc(&b->cwork, sizeof(double) * CONTOUR_WORK_DOUBLES));
+    Prepared &P = b->inst[idx];
+    Fields fo{};
+    fo.rhoA = P.fields;
+    launch_step(Launch{P.p.storage, P.ty, P.p.bc, MODE_FIELDS, true}, b->stream, P.I, (int)(b->t & 1), fo,
+                P.partials, P.dd, b->t);
+    MCLBM_HIP(hipGetLastError());
+    return contour_fit(P.fields, P.cls, P.p.nx, P.p.ny, req, b->cwork, b->stream, out);
 }
 
 int64_t lbm_batch_fluid_nodes(const lbm_batch *b) { return b ? b->fluid : -1; }

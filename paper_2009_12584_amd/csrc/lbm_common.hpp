@@ -41,6 +41,14 @@ inline void set_err(const char *fmt, ...) {
     tls_err() = b;
 }
 
+// Contour circle fit (lbm_analysis.hip): workgroups of the moment pass, the
+// largest wall-distance cut, and the device work buffer it needs in doubles.
+constexpr int CONTOUR_BLOCKS = 1024;
+constexpr int CONTOUR_MAX_SKIP = 32;
+constexpr size_t CONTOUR_WORK_DOUBLES = (size_t)CONTOUR_BLOCKS * 10 + 8;
+int contour_fit(const float *rhoA, const uint8_t *cls, int nx, int ny, const lbm_contour_req *q, double *work,
+                hipStream_t s, lbm_circle_t *out);
+
 inline int pitch_of(int nx) { return (nx + 63) / 64 * 64; }
 inline int default_ty(const lbm_params &p) { return p.tile_y > 0 ? p.tile_y : 8; }
 inline size_t store_bytes(int storage) { return storage == LBM_STORE_F16 ? 2 : 4; }

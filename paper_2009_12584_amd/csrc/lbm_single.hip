@@ -17,6 +17,7 @@ struct lbm_handle {
     double *partials = nullptr;
     DiagDev *dd = nullptr;
     float *fields = nullptr;  // lazily allocated: 10 planes of nx*ny
+    double *cwork = nullptr;  // lazily allocated: contour-fit work buffer
     int64_t t = 0;
     int sticky = LBM_OK;
     std::string err;
@@ -38,7 +39,8 @@ void release(lbm_handle *h) {
     if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
     if (h->graph) (void)hipGraphDestroy(h->graph);
     for (void *q : {(void *)h->I.buf[0], (void *)h->I.buf[1], (void *)h->word, (void *)h->m25, (void *)h->tflag,
-                    (void *)h->nbr, (void *)h->cls, (void *)h->partials, (void *)h->dd, (void *)h->fields})
+                    (void *)h->nbr, (void *)h->cls, (void *)h->partials, (void *)h->dd, (void *)h->fields,
+                    (void *)h->cwork})
         if (q) (void)hipFree(q);
     if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
     delete h;
@@ -286,6 +288,25 @@ int lbm_diag(lbm_handle *h, lbm_diag_t *out) {
         return fail(h, LBM_ENUMERIC);
     }
     return LBM_OK;
+}
+
+int lbm_contour_fit(lbm_handle *h, const lbm_contour_req *req, lbm_circle_t *out) {
+    if (!h) return LBM_EINVAL;
+    int rc = ensure_fields(h);
+    if (rc) return fail(h, rc);
+    if (!h->cwork) {
+        if (hipMalloc(&h->cwork, sizeof(double) * CONTOUR_WORK_DOUBLES) != hipSuccess) {
+            h->cwork = nullptr;
+            set_err("contour fit: work buffer allocation failed");
+            return fail(h, LBM_ENOMEM);
+        }
+    }
+    Fields fo{};
+    fo.rhoA = h->fields;
+    rc = run_fields(h, fo);
+    if (rc) return fail(h, rc);
+    rc = contour_fit(h->fields, h->cls, h->p.nx, h->p.ny, req, h->cwork, h->stream, out);
+    return rc ? fail(h, rc) : LBM_OK;
 }
 
 int lbm_classify(lbm_handle *h, uint8_t *nbr, uint8_t *cls) {

@@ -24,6 +24,10 @@ def _host(a, dtype, shape):
     return a
 
 
+def _circle(c) -> dict:
+    return dict(n=int(c.n), xc=c.xc, yc=c.yc, R=c.R, rms=c.rms, max_dev=c.max_dev)
+
+
 def _stream_handle(stream):
     if stream is None:
         return None
@@ -117,6 +121,13 @@ class Simulation:
         return dict(mass=(d.mass[0], d.mass[1]), mass0=(d.mass0[0], d.mass0[1]),
                     momentum=(d.momentum[0], d.momentum[1]), max_speed=d.max_speed, step=d.step, flags=d.flags)
 
+    def contour_fit(self, level=0.5, skip=3, roi=None) -> dict:
+        """Circle through the interface rho^A = level (lbm_contour_fit)."""
+        c = capi.LbmCircle()
+        q = capi.make_contour_req(level, skip, roi)
+        check(lib().lbm_contour_fit(self._h, ctypes.byref(q), ctypes.byref(c)), self._h)
+        return _circle(c)
+
     def classify(self):
         nbr = np.zeros((self.ny, self.nx), np.uint8)
         cls = np.zeros((self.ny, self.nx), np.uint8)
@@ -181,6 +192,12 @@ class Batch:
         d = capi.LbmDiag()
         check(lib().lbm_batch_diag(self._h, int(idx), ctypes.byref(d)))
         return dict(mass=(d.mass[0], d.mass[1]), mass0=(d.mass0[0], d.mass0[1]), step=d.step, flags=d.flags)
+
+    def contour_fit(self, idx, level=0.5, skip=3, roi=None) -> dict:
+        c = capi.LbmCircle()
+        q = capi.make_contour_req(level, skip, roi)
+        check(lib().lbm_batch_contour_fit(self._h, int(idx), ctypes.byref(q), ctypes.byref(c)))
+        return _circle(c)
 
     def close(self):
         h = getattr(self, "_h", None)
