@@ -53,7 +53,19 @@ extern "C" {
 #define LBM_ENOTFOUND (-6) /* pool: slot not active */
 
 /* ---- enums ---- */
-typedef enum { LBM_BC_MARTYS_CHEN = 0, LBM_BC_LLKC = 1, LBM_BC_VIRTUAL_IMPROVED = 2 } lbm_bc;
+/* solid pseudopotential S of Eq. 6 (Section 2):
+ *   MARTYS_CHEN      S = phi, G_As = G_w, G_Bs = -G_w
+ *   LLKC             S(x + c_i) = phi(x + c_i) rho(x), G_As = G_w, G_Bs = -G_w
+ *   VIRTUAL_IMPROVED S = phi rho~ of Eq. 7 with chi^A, chi^B; G_{sigma s} = G
+ *   FIXED_VIRTUAL    S^sigma = phi rho_s^sigma with the constant solid densities
+ *                    rho_s^A = chi[0], rho_s^B = chi[1] (Chen et al.'s virtual
+ *                    solid density, same section); G_{sigma s} = G */
+typedef enum {
+    LBM_BC_MARTYS_CHEN = 0,
+    LBM_BC_LLKC = 1,
+    LBM_BC_VIRTUAL_IMPROVED = 2,
+    LBM_BC_FIXED_VIRTUAL = 3
+} lbm_bc;
 /* averaging lattice of the virtual solid density, Eq. 7 and the text after it */
 typedef enum { LBM_AVG_D2Q25 = 0, LBM_AVG_D2Q9 = 1 } lbm_avg;
 /* storage of the populations as deviations d_i = f_i - w_i rho_ref */
@@ -68,7 +80,8 @@ typedef struct {
     double G;            /* G_AB = G_BA of Eq. 5 (D2Q9 weights inside the sum) */
     int32_t bc;          /* lbm_bc */
     double G_w;          /* Martys-Chen, LLKC: G_As = G_w, G_Bs = -G_w; G_w < 0 wets A */
-    double chi[2];       /* improved scheme: chi^A, chi^B of Eq. 7 (G_{sigma s} = G) */
+    double chi[2];       /* improved scheme: chi^A, chi^B of Eq. 7 (G_{sigma s} = G);
+                            fixed virtual density: rho_s^A, rho_s^B */
     int32_t avg;         /* lbm_avg */
     int32_t storage;     /* lbm_storage */
     double rho_ref[2];   /* deviation reference per component; NaN = the smallest
@@ -197,6 +210,22 @@ typedef struct {
  * device in a fixed order; deterministic).  Synchronises.  LBM_EINVAL for a
  * bad level, skip or roi. */
 int lbm_contour_fit(lbm_handle *h, const lbm_contour_req *req, lbm_circle_t *out);
+
+/* Interface position along a lattice line, for the bridge radius of two
+ * coalescing drops (Section 4: the distance between the surface and the
+ * bridge interface).  From the fluid node (x0, y0), stepping by (dx, dy)
+ * (each -1, 0 or 1, not both 0) over len nodes that must all lie inside the
+ * grid, finds the first node k that is solid or has rho^A below level, and
+ * writes to the DEVICE double *out the crossing position in node steps from
+ * the start: k - 1 + (r_{k-1} - level) / (r_{k-1} - r_k) (densities in FP32,
+ * interpolation in FP64); -0.5 when the start node is already below the
+ * level (a half-way wall just before it); NaN when a solid node or the end of
+ * the line comes first.  Runs one fields pass and one small kernel on the
+ * handle's stream, no synchronisation, so a time series costs no host round
+ * trip.  LBM_EINVAL for a null out, a non-finite level or a line leaving the
+ * grid (checked before anything is enqueued). */
+int lbm_line_probe(lbm_handle *h, int32_t x0, int32_t y0, int32_t dx, int32_t dy, int32_t len, double level,
+                   double *out);
 
 /* Measurement aid: a plain streaming copy of bytes (a multiple of 16) from
  * src to dst, both device pointers, enqueued on stream.  Its achieved

@@ -20,7 +20,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "lbm_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-BC_MARTYS_CHEN, BC_LLKC, BC_IMPROVED = 0, 1, 2
+BC_MARTYS_CHEN, BC_LLKC, BC_IMPROVED, BC_FIXED_VIRTUAL = 0, 1, 2, 3
 AVG_D2Q25, AVG_D2Q9 = 0, 1
 
 

@@ -217,7 +217,7 @@ int ora_create(const ora_params *p, const unsigned char *mask, const double *rho
     if (!p || !mask || !rhoA0 || !rhoB0) return ORA_EINVAL;
     if (p->nx <= 0 || p->ny <= 0) return ORA_EINVAL;
     if (!(p->tau > 0.5)) return ORA_EINVAL;
-    if (p->bc < 0 || p->bc > 2 || p->avg < 0 || p->avg > 1) return ORA_EINVAL;
+    if (p->bc < 0 || p->bc > 3 || p->avg < 0 || p->avg > 1) return ORA_EINVAL;
     d2q25_init();
     const int nx = p->nx, ny = p->ny;
     const long n = (long)nx * ny;
@@ -341,7 +341,7 @@ static void macroscopic(ora_state *s) {
     /* S3 + S4 */
     const double G = p->G;
     double Gs[2];
-    if (p->bc == ORA_BC_IMPROVED) {
+    if (p->bc == ORA_BC_IMPROVED || p->bc == ORA_BC_FIXED_VIRTUAL) { /* virtual-density schemes */
         Gs[0] = G;
         Gs[1] = G;
     } else {
@@ -375,6 +375,8 @@ static void macroscopic(ora_state *s) {
                         double S;
                         if (p->bc == ORA_BC_MARTYS_CHEN) S = 1.0;             /* S = phi */
                         else if (p->bc == ORA_BC_LLKC) S = s->rho[cb][k];     /* S = phi rho^sbar(x) */
+                        else if (p->bc == ORA_BC_FIXED_VIRTUAL)               /* S = phi rho_s^sbar */
+                            S = cb == 0 ? p->chiA : p->chiB;
                         else S = s->rt[cb][kn];                               /* S = phi rho-tilde^sbar */
                         adx += W9[i] * S * CX[i];
                         ady += W9[i] * S * CY[i];

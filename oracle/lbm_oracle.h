@@ -14,7 +14,7 @@ extern "C" {
 #endif
 
 enum { ORA_OK = 0, ORA_EINVAL = -1, ORA_ENOMEM = -2 };
-enum { ORA_BC_MARTYS_CHEN = 0, ORA_BC_LLKC = 1, ORA_BC_IMPROVED = 2 };
+enum { ORA_BC_MARTYS_CHEN = 0, ORA_BC_LLKC = 1, ORA_BC_IMPROVED = 2, ORA_BC_FIXED_VIRTUAL = 3 };
 enum { ORA_AVG_D2Q25 = 0, ORA_AVG_D2Q9 = 1 };
 
 typedef struct {
@@ -24,7 +24,8 @@ typedef struct {
     double G;          /* G_AB = G_BA of Eq. 5 */
     int bc;            /* ORA_BC_* */
     double Gw;         /* Martys-Chen / LLKC: G_As = -G_Bs = Gw (Section 3.1) */
-    double chiA, chiB; /* improved scheme: chi^A, chi^B of Eq. 7 */
+    double chiA, chiB; /* improved scheme: chi^A, chi^B of Eq. 7; fixed virtual
+                          density: the solid densities rho_s^A, rho_s^B (Section 2) */
     int avg;           /* averaging lattice of Eq. 7: ORA_AVG_D2Q25 or ORA_AVG_D2Q9 */
 } ora_params;
 

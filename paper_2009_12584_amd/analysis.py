@@ -1,4 +1,6 @@
-"""Contact angle of a static drop (Section 3.2) and the theta(xi, beta) sweep.
+"""Drop-shape measurements: the contact angle of a static drop with the
+theta(xi, beta) sweep (Section 3.2), and the bridge radius of two coalescing
+drops with its growth exponent (Section 4).
 
 The paper fits a circle to the interface rho^A = 0.5 of the static drop and
 takes the angle between the circle's tangent at the contact line and the
@@ -117,7 +119,117 @@ def sweep(xis, betas, avgs=(0,), *, n=1000, R0=100.0, tau=1.88, G=3.0, rho_out=0
     return rows
 
 
+def surface_start(mask, x0, y_surface):
+    """First fluid node above the surface point (x0, y_surface) in column x0."""
+    m = np.asarray(mask)
+    y = int(y_surface)
+    while y < m.shape[0] and m[y, x0]:
+        y += 1
+    if y >= m.shape[0] - 1:
+        raise ValueError("no fluid above the surface in column %d" % x0)
+    return y
+
+
+def bridge_history(case, mask, *, every, steps=None, level=0.5, storage="f32", tile_y=0):
+    """Bridge radius b(t) of two drops coalescing on a surface (Section 4).
+
+    The probe runs up the column x = L_X / 2 from the first fluid node above
+    the surface point (L_X / 2, L_Y / 2); b is the distance from the half-way
+    wall below that node to the rho^A = level crossing (0 before the bridge
+    forms).  Samples are written on the device, one per `every` steps, and
+    read back once.  Returns (t, b) arrays."""
+    import torch
+
+    from .sim import Simulation
+
+    steps = case.steps if steps is None else steps
+    x0 = case.nx // 2
+    y0 = surface_start(mask, x0, case.ny // 2)
+    length = case.ny - 1 - y0
+    n = steps // every
+    stream = torch.cuda.current_stream()
+    buf = torch.empty(max(1, n), dtype=torch.float64, device="cuda")
+    sim = Simulation(mask, case.rhoA0, case.rhoB0, stream=stream, storage=storage, tile_y=tile_y, **case.params())
+    try:
+        for k in range(n):
+            sim.step(every)
+            sim.line_probe(x0, y0, 0, 1, length, level, buf.data_ptr() + 8 * k)
+        stream.synchronize()
+    finally:
+        sim.close()
+    pos = buf[:n].cpu().numpy()
+    t = every * np.arange(1, n + 1, dtype=np.float64)
+    return t, pos + 0.5
+
+
+def fit_exponent(t, b, lo, hi):
+    """Least-squares slope of log b against log t over samples with lo <= b <= hi."""
+    t = np.asarray(t, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    sel = (t > 0) & np.isfinite(b) & (b >= lo) & (b <= hi)
+    if sel.sum() < 3:
+        return math.nan
+    return float(np.polyfit(np.log(t[sel]), np.log(b[sel]), 1)[0])
+
+
+def coalescence_study(R0s, Rs=None, *, samples=400, t_end=4.0, b_lo=3.0, storage="f32", log=None):
+    """Bridge growth for each initial radius at the paper's Ohnesorge number:
+    alpha fitted over b_lo <= b <= R0 / 3 (the viscous regime, which ends as
+    b passes R0 / 3), time in units of tau_nu = nu R0 / sigma."""
+    import workloads as W
+
+    from .sim import mask_disk, mask_plane
+
+    out = []
+    for R0 in R0s:
+        c = W.coalescence(R0, Rs)
+        steps = int(round(t_end * c.t_nu))
+        every = max(1, steps // samples)
+        g = c.geometry
+        mask = mask_plane(c.nx, c.ny, g[1], g[2]) if g[0] == "plane" else mask_disk(c.nx, c.ny, g[1], g[2], g[3])
+        t0 = time.perf_counter()
+        t, b = bridge_history(c, mask, every=every, steps=steps, storage=storage)
+        wall = time.perf_counter() - t0
+        alpha = fit_exponent(t, b, b_lo, R0 / 3.0)
+        row = dict(R0=R0, Rs=Rs, nx=c.nx, ny=c.ny, tau=c.tau, t_nu=c.t_nu, steps=steps, every=every, alpha=alpha,
+                   t=t.tolist(), b=b.tolist(), seconds=wall)
+        out.append(row)
+        if log:
+            log("coalescence R0=%g %dx%d tau=%.4f steps=%d alpha=%.3f (%.1f s)" % (R0, c.nx, c.ny, c.tau, steps,
+                                                                                 alpha, wall))
+    return out
+
+
+def main_coalescence(argv):
+    ap = argparse.ArgumentParser(description="Bridge growth of coalescing drops versus resolution (Section 4).")
+    ap.add_argument("--R0", default="12.5,25,50,100,200,400")
+    ap.add_argument("--Rs", type=float, default=None, help="surface radius; flat when omitted")
+    ap.add_argument("--t-end", type=float, default=4.0, help="in viscous times")
+    ap.add_argument("--samples", type=int, default=400)
+    ap.add_argument("--out", default=None)
+    a = ap.parse_args(argv)
+    rows = coalescence_study([float(v) for v in a.R0.split(",")], a.Rs, samples=a.samples, t_end=a.t_end,
+                             log=lambda m: print(m, flush=True))
+    if a.out:
+        with open(a.out, "w") as f:
+            json.dump(dict(args=vars(a), rows=rows), f)
+    print("| R0 | grid | tau | steps | alpha | b/R0 at t/tau_nu = 0.5, 1, 2, 4 |")
+    print("|---|---|---|---|---|---|")
+    for r in rows:
+        tt = np.array(r["t"]) / r["t_nu"]
+        bb = np.array(r["b"]) / r["R0"]
+        pts = ", ".join("%.3f" % np.interp(x, tt, bb) for x in (0.5, 1.0, 2.0, 4.0))
+        print("| %g | %dx%d | %.4f | %d | %.3f | %s |" % (r["R0"], r["nx"], r["ny"], r["tau"], r["steps"], r["alpha"],
+                                                       pts))
+    return 0
+
+
 def main(argv=None):
+    argv = sys.argv[1:] if argv is None else list(argv)
+    if argv and argv[0] == "coalescence":
+        return main_coalescence(argv[1:])
+    if argv and argv[0] == "angles":
+        argv = argv[1:]
     ap = argparse.ArgumentParser(description="Contact angle versus xi and plane inclination (improved scheme).")
     ap.add_argument("--xi", default="-0.4,-0.2,0,0.2,0.4")
     ap.add_argument("--beta", default="0,10,30,45,60")

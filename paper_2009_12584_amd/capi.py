@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmclbm.so")
 
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EAGAIN, LBM_EDEVICE, LBM_ENUMERIC, LBM_ENOTFOUND = 0, -1, -2, -3, -4, -5, -6
-BC_MARTYS_CHEN, BC_LLKC, BC_VIRTUAL_IMPROVED = 0, 1, 2
+BC_MARTYS_CHEN, BC_LLKC, BC_VIRTUAL_IMPROVED, BC_FIXED_VIRTUAL = 0, 1, 2, 3
 AVG_D2Q25, AVG_D2Q9 = 0, 1
 STORE_F32, STORE_F16 = 0, 1
 
@@ -22,7 +22,7 @@ EXPORTS = [
     "lbm_params_default", "lbm_create", "lbm_step", "lbm_time", "lbm_fields", "lbm_fields_device",
     "lbm_forces", "lbm_diag", "lbm_classify", "lbm_state_bytes", "lbm_get_state", "lbm_set_state",
     "lbm_destroy", "lbm_strerror", "lbm_last_error", "lbm_mask_plane", "lbm_mask_disk", "lbm_copy_probe",
-    "lbm_contour_fit", "lbm_batch_contour_fit",
+    "lbm_contour_fit", "lbm_batch_contour_fit", "lbm_line_probe",
     "lbm_batch_create", "lbm_batch_step", "lbm_batch_fields", "lbm_batch_diag", "lbm_batch_fluid_nodes",
     "lbm_batch_destroy", "lbm_pool_create", "lbm_pool_footprint", "lbm_pool_admit", "lbm_pool_advance",
     "lbm_pool_poll", "lbm_pool_fields", "lbm_pool_release", "lbm_pool_stats", "lbm_pool_progress",
@@ -72,6 +72,11 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise ImportError("libmclbm.so is not built: run __graft_entry__.build() "
                               "(or python -m paper_2009_12584_amd._build)")
+        # torch ships its own HIP and HSA runtimes: loading them first makes this
+        # library bind to the same ones (one runtime per process); the other
+        # order leaves torch without devices.
+        import torch  # noqa: F401
+
         L = ctypes.CDLL(LIB_PATH)
         P, I32, I64, D, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
         PP = ctypes.POINTER(LbmParams)
@@ -96,6 +101,7 @@ def lib():
             "lbm_copy_probe": (I32, [P, P, SZ, P]),
             "lbm_contour_fit": (I32, [P, ctypes.POINTER(LbmContourReq), ctypes.POINTER(LbmCircle)]),
             "lbm_batch_contour_fit": (I32, [P, I32, ctypes.POINTER(LbmContourReq), ctypes.POINTER(LbmCircle)]),
+            "lbm_line_probe": (I32, [P, I32, I32, I32, I32, I32, D, P]),
             "lbm_batch_create": (I32, [I32, PP, P, P, P, P, I32, ctypes.POINTER(P)]),
             "lbm_batch_step": (I32, [P, I64]),
             "lbm_batch_fields": (I32, [P, I32, P, P, P, P]),

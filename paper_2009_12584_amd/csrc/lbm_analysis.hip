@@ -10,7 +10,11 @@
 // partials in order and solves the 3x3 normal equations of the algebraic fit
 // x^2 + y^2 + D x + E y + F = 0; pass 2 sums the radial residuals about the
 // fitted circle.  Everything stays on the device until the final 64-byte copy.
-#include "lbm_common.hpp"
+//
+// The line probe gives the interface position along one lattice line (the
+// bridge radius of two coalescing drops, Section 4) straight into a device
+// double, so that a time series costs no host round trip.
+#include "lbm_analysis.hpp"
 
 namespace mclbm {
 namespace {
@@ -180,7 +184,71 @@ __global__ __launch_bounds__(CF_THREADS) void k_contour_finish(const double *__r
     fit[3] = n;
 }
 
+// First node along the line that is solid or below the level (a min-reduction
+// over 256 lanes), then the interpolated crossing in node steps from the start:
+// -0.5 when the start node is already below the level, NaN when a solid node
+// or the end of the line comes first.
+__global__ __launch_bounds__(CF_THREADS) void k_line_probe(const float *__restrict__ rhoA,
+                                                           const uint8_t *__restrict__ cls, int nx, int x0, int y0,
+                                                           int dx, int dy, int len, float level, double *out) {
+    __shared__ int kmin[CF_THREADS];
+    int best = len;
+    for (int k = threadIdx.x; k < len; k += CF_THREADS) {
+        const size_t i = (size_t)(y0 + k * dy) * nx + (x0 + k * dx);
+        if (cls[i] >= 2 || rhoA[i] < level) {
+            best = k;  // this lane's indices increase, so its first hit is its smallest
+            break;
+        }
+    }
+    kmin[threadIdx.x] = best;
+    __syncthreads();
+    for (int w = CF_THREADS / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) kmin[threadIdx.x] = min(kmin[threadIdx.x], kmin[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    const int k = kmin[0];
+    double r = NAN;
+    if (k < len) {
+        const size_t i = (size_t)(y0 + k * dy) * nx + (x0 + k * dx);
+        if (cls[i] < 2) {
+            if (k == 0) {
+                r = -0.5;
+            } else {
+                const double a = rhoA[i - (ptrdiff_t)dy * nx - dx], b = rhoA[i];
+                r = (double)(k - 1) + (a - (double)level) / (a - b);
+            }
+        }
+    }
+    *out = r;
+}
+
 }  // namespace
+
+int line_probe_check(int nx, int ny, int x0, int y0, int dx, int dy, int len, double level, const double *out) {
+    if (!out || !std::isfinite(level) || len < 1 || dx < -1 || dx > 1 || dy < -1 || dy > 1 || (dx == 0 && dy == 0)) {
+        set_err("line probe: need a device output, a finite level, steps dx, dy in {-1, 0, 1} not both zero, "
+                "and len >= 1");
+        return LBM_EINVAL;
+    }
+    const int64_t x1 = x0 + (int64_t)dx * (len - 1), y1 = y0 + (int64_t)dy * (len - 1);
+    if (x0 < 0 || x0 >= nx || y0 < 0 || y0 >= ny || x1 < 0 || x1 >= nx || y1 < 0 || y1 >= ny) {
+        set_err("line probe: the line (%d,%d) + k (%d,%d), k < %d, leaves the %d x %d grid", x0, y0, dx, dy, len, nx,
+                ny);
+        return LBM_EINVAL;
+    }
+    return LBM_OK;
+}
+
+int line_probe(const float *rhoA, const uint8_t *cls, int nx, int ny, int x0, int y0, int dx, int dy, int len,
+               double level, double *out, hipStream_t s) {
+    const int rc = line_probe_check(nx, ny, x0, y0, dx, dy, len, level, out);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_line_probe, dim3(1), dim3(CF_THREADS), 0, s, rhoA, cls, nx, x0, y0, dx, dy, len,
+                       (float)level, out);
+    MCLBM_HIP(hipGetLastError());
+    return LBM_OK;
+}
 
 int contour_fit(const float *rhoA, const uint8_t *cls, int nx, int ny, const lbm_contour_req *q, double *work,
                 hipStream_t s, lbm_circle_t *out) {

@@ -17,7 +17,7 @@
 #include <deque>
 #include <map>
 
-#include "lbm_common.hpp"
+#include "lbm_analysis.hpp"
 
 using namespace mclbm;
 
@@ -178,7 +178,7 @@ int prepare(Prepared &P, const lbm_params &p, int ty, char *base, const uint8_t 
     int rc = enqueue_setup(P.I, p, ty, dmask, drA, drB, g, s);
     if (rc) return rc;
     // drift threshold off in batched forms; step-0 mass recorded by the first fields pass
-    launch_step(Launch{p.storage, ty, p.bc, MODE_FIELDS, true}, s, P.I, 0, Fields{}, P.partials, P.dd, 0);
+    launch_step(Launch{p.storage, ty, kernel_bc(p), MODE_FIELDS, true}, s, P.I, 0, Fields{}, P.partials, P.dd, 0);
     MCLBM_HIP(hipGetLastError());
     return LBM_OK;
 }
@@ -191,7 +191,8 @@ int read_fields(Prepared &P, int parity, long long step, hipStream_t s, double *
     fo.rhoB = P.fields + n;
     fo.ux = P.fields + 2 * n;
     fo.uy = P.fields + 3 * n;
-    launch_step(Launch{P.p.storage, P.ty, P.p.bc, MODE_FIELDS, true}, s, P.I, parity, fo, P.partials, P.dd, step);
+    launch_step(Launch{P.p.storage, P.ty, kernel_bc(P.p), MODE_FIELDS, true}, s, P.I, parity, fo, P.partials, P.dd,
+                step);
     MCLBM_HIP(hipGetLastError());
     std::vector<float> tmp(n);
     for (int q = 0; q < 4; ++q) {
@@ -205,7 +206,7 @@ int read_fields(Prepared &P, int parity, long long step, hipStream_t s, double *
 }
 
 int read_diag(Prepared &P, int parity, long long step, hipStream_t s, lbm_diag_t *out) {
-    launch_step(Launch{P.p.storage, P.ty, P.p.bc, MODE_FIELDS, true}, s, P.I, parity, Fields{}, P.partials, P.dd,
+    launch_step(Launch{P.p.storage, P.ty, kernel_bc(P.p), MODE_FIELDS, true}, s, P.I, parity, Fields{}, P.partials, P.dd,
                 step);
     MCLBM_HIP(hipGetLastError());
     DiagDev d;
@@ -416,7 +417,7 @@ int lbm_batch_contour_fit(lbm_batch *b, int32_t idx, const lbm_contour_req *req,
     Prepared &P = b->inst[idx];
     Fields fo{};
     fo.rhoA = P.fields;
-    launch_step(Launch{P.p.storage, P.ty, P.p.bc, MODE_FIELDS, true}, b->stream, P.I, (int)(b->t & 1), fo,
+    launch_step(Launch{P.p.storage, P.ty, kernel_bc(P.p), MODE_FIELDS, true}, b->stream, P.I, (int)(b->t & 1), fo,
                 P.partials, P.dd, b->t);
     MCLBM_HIP(hipGetLastError());
     return contour_fit(P.fields, P.cls, P.p.nx, P.p.ny, req, b->cwork, b->stream, out);

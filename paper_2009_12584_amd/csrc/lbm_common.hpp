@@ -41,14 +41,6 @@ inline void set_err(const char *fmt, ...) {
     tls_err() = b;
 }
 
-// Contour circle fit (lbm_analysis.hip): workgroups of the moment pass, the
-// largest wall-distance cut, and the device work buffer it needs in doubles.
-constexpr int CONTOUR_BLOCKS = 1024;
-constexpr int CONTOUR_MAX_SKIP = 32;
-constexpr size_t CONTOUR_WORK_DOUBLES = (size_t)CONTOUR_BLOCKS * 10 + 8;
-int contour_fit(const float *rhoA, const uint8_t *cls, int nx, int ny, const lbm_contour_req *q, double *work,
-                hipStream_t s, lbm_circle_t *out);
-
 inline int pitch_of(int nx) { return (nx + 63) / 64 * 64; }
 inline int default_ty(const lbm_params &p) { return p.tile_y > 0 ? p.tile_y : 8; }
 inline size_t store_bytes(int storage) { return storage == LBM_STORE_F16 ? 2 : 4; }
@@ -88,7 +80,7 @@ inline int validate(const lbm_params *p, const uint8_t *mask, const double *rA, 
         set_err("non-finite G, G_w or chi");
         return LBM_EINVAL;
     }
-    if (p->bc < 0 || p->bc > 2 || p->avg < 0 || p->avg > 1 || p->storage < 0 || p->storage > 1) {
+    if (p->bc < 0 || p->bc > 3 || p->avg < 0 || p->avg > 1 || p->storage < 0 || p->storage > 1) {
         set_err("bc %d / avg %d / storage %d out of range", p->bc, p->avg, p->storage);
         return LBM_EINVAL;
     }
@@ -149,6 +141,12 @@ inline void resolve_rref(const lbm_params &p, const uint8_t *mask, const double 
     }
 }
 
+// Kernel rule for a BC: a fixed virtual solid density S^sigma = phi rho_s^sigma
+// is the Martys-Chen force with G_{sigma s} = G rho_s^{sigma-bar} (Eq. 6).
+inline int kernel_bc(const lbm_params &p) {
+    return p.bc == LBM_BC_FIXED_VIRTUAL ? (int)LBM_BC_MARTYS_CHEN : p.bc;
+}
+
 inline void fill_inst(Inst &I, const lbm_params &p, const double rref[2], int ty) {
     I.nx = p.nx;
     I.ny = p.ny;
@@ -160,7 +158,7 @@ inline void fill_inst(Inst &I, const lbm_params &p, const double rref[2], int ty
     // the compare-and-add wrap covers excursions of a tile plus halo; shorter
     // periodic sizes wrap by modulo
     I.small = (((p.periodic & 1u) && p.nx < TX + 2 * FH + 8) || ((p.periodic & 2u) && p.ny < 16 + 2 * FH + 8)) ? 1 : 0;
-    I.bc = p.bc;
+    I.bc = kernel_bc(p);
     I.avg = p.avg;
     I.omega = (float)(1.0 / p.tau);
     I.guo = (float)(1.0 - 1.0 / (2.0 * p.tau));
@@ -169,6 +167,9 @@ inline void fill_inst(Inst &I, const lbm_params &p, const double rref[2], int ty
         // virtual-density schemes use G_{sigma s} = G_{sigma sigma-bar} (Section 2)
         I.GsA = (float)p.G;
         I.GsB = (float)p.G;
+    } else if (p.bc == LBM_BC_FIXED_VIRTUAL) {
+        I.GsA = (float)(p.G * p.chi[1]);
+        I.GsB = (float)(p.G * p.chi[0]);
     } else {
         I.GsA = (float)p.G_w;
         I.GsB = (float)(-p.G_w);

@@ -1,6 +1,6 @@
 // Single-simulation C ABI of libmclbm.so: create / step / fields / diag /
 // classify / state / destroy, and the geometry rasters.
-#include "lbm_common.hpp"
+#include "lbm_analysis.hpp"
 
 using namespace mclbm;
 
@@ -18,6 +18,7 @@ struct lbm_handle {
     DiagDev *dd = nullptr;
     float *fields = nullptr;  // lazily allocated: 10 planes of nx*ny
     double *cwork = nullptr;  // lazily allocated: contour-fit work buffer
+    float *rho1 = nullptr;    // lazily allocated: one density plane for the line probe
     int64_t t = 0;
     int sticky = LBM_OK;
     std::string err;
@@ -40,14 +41,14 @@ void release(lbm_handle *h) {
     if (h->graph) (void)hipGraphDestroy(h->graph);
     for (void *q : {(void *)h->I.buf[0], (void *)h->I.buf[1], (void *)h->word, (void *)h->m25, (void *)h->tflag,
                     (void *)h->nbr, (void *)h->cls, (void *)h->partials, (void *)h->dd, (void *)h->fields,
-                    (void *)h->cwork})
+                    (void *)h->cwork, (void *)h->rho1})
         if (q) (void)hipFree(q);
     if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
     delete h;
 }
 
 Launch launch_of(const lbm_handle *h, int mode, bool diag) {
-    return Launch{h->p.storage, h->ty, h->p.bc, mode, diag};
+    return Launch{h->p.storage, h->ty, kernel_bc(h->p), mode, diag};
 }
 
 int run_fields(lbm_handle *h, const Fields &fo) {
@@ -306,6 +307,27 @@ int lbm_contour_fit(lbm_handle *h, const lbm_contour_req *req, lbm_circle_t *out
     rc = run_fields(h, fo);
     if (rc) return fail(h, rc);
     rc = contour_fit(h->fields, h->cls, h->p.nx, h->p.ny, req, h->cwork, h->stream, out);
+    return rc ? fail(h, rc) : LBM_OK;
+}
+
+int lbm_line_probe(lbm_handle *h, int32_t x0, int32_t y0, int32_t dx, int32_t dy, int32_t len, double level,
+                   double *out) {
+    if (!h) return LBM_EINVAL;
+    const int nx = h->p.nx, ny = h->p.ny;
+    int rc = line_probe_check(nx, ny, x0, y0, dx, dy, len, level, out);  // before any device work
+    if (rc) return fail(h, rc);
+    if (!h->rho1) {
+        if (hipMalloc(&h->rho1, sizeof(float) * (size_t)nx * ny) != hipSuccess) {
+            h->rho1 = nullptr;
+            set_err("line probe: density plane allocation failed");
+            return fail(h, LBM_ENOMEM);
+        }
+    }
+    Fields fo{};
+    fo.rhoA = h->rho1;
+    rc = run_fields(h, fo);
+    if (rc) return fail(h, rc);
+    rc = line_probe(h->rho1, h->cls, nx, ny, x0, y0, dx, dy, len, level, out, h->stream);
     return rc ? fail(h, rc) : LBM_OK;
 }
 

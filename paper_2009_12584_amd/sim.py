@@ -128,6 +128,12 @@ class Simulation:
         check(lib().lbm_contour_fit(self._h, ctypes.byref(q), ctypes.byref(c)), self._h)
         return _circle(c)
 
+    def line_probe(self, x0, y0, dx, dy, length, level, out):
+        """Enqueues the interface crossing along a lattice line into the device
+        double at `out` (an integer address, e.g. tensor.data_ptr() + 8 k)."""
+        check(lib().lbm_line_probe(self._h, int(x0), int(y0), int(dx), int(dy), int(length), float(level),
+                                   ctypes.c_void_p(int(out))), self._h)
+
     def classify(self):
         nbr = np.zeros((self.ny, self.nx), np.uint8)
         cls = np.zeros((self.ny, self.nx), np.uint8)

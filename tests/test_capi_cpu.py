@@ -44,7 +44,7 @@ def _sim(**kw):
 @pytest.mark.parametrize("kw,needle", [
     (dict(tau=0.5), "tau"),
     (dict(tau=float("nan")), "tau"),
-    (dict(bc=3), "bc"),
+    (dict(bc=4), "bc"),
     (dict(avg=2), "avg"),
     (dict(storage=7, tile_y=3), "tile_y"),
     (dict(periodic=4), "periodic"),

@@ -108,6 +108,9 @@ CASES = {
     "imp1": (W.IMPROVED, dict(chi=(1.0, 1.0))),
     "imp-xi": (W.IMPROVED, dict(chi=(1.2, 0.8))),   # xi = -0.2 with chi^A = 1 - xi
     "imp-lit": (W.IMPROVED, dict(chi=(0.8, 1.2))),  # xi = -0.2 with chi^A = 1 + xi
+    "fix=": (W.FIXED, dict(chi=(0.5, 0.5))),        # rho_s^A = rho_s^B
+    "fixA": (W.FIXED, dict(chi=(0.7, 0.3))),        # solid looks A-rich
+    "fixB": (W.FIXED, dict(chi=(0.3, 0.7))),
 }
 
 
@@ -155,6 +158,19 @@ def test_martys_chen_and_llkc_angles_near_the_printed_ones(angles):
     assert angles["mc-"]["theta"] == pytest.approx(mc, abs=10.0)
     assert angles["llkc-"]["theta"] == pytest.approx(llkc, abs=10.0)
     assert angles["mc-"]["theta"] < angles["llkc-"]["theta"] < 90.0
+
+
+def test_fixed_virtual_density_wets_the_component_it_mimics(angles):
+    """Chen et al.'s constant solid densities (Section 2): equal densities are
+    neutral by the A/B swap; an A-rich solid attracts A, and swapping the two
+    densities mirrors the angle."""
+    a = angles
+    # the depletion layer both components form at a repelling wall moves the
+    # extrapolated circle by ~2 degrees at R ~ 22 (equal rho_s of 0.2 and 1.0
+    # give 91.7 and 92.3 degrees); the bias falls as 1/R
+    assert a["fix="]["theta"] == pytest.approx(90.0, abs=2.5)
+    assert a["fixA"]["theta"] < 80.0 < 100.0 < a["fixB"]["theta"]
+    assert a["fixA"]["theta"] + a["fixB"]["theta"] == pytest.approx(2 * a["fix="]["theta"], abs=1.0)
 
 
 def test_xi_sign_matches_the_paper_with_chi_a_one_minus_xi(angles):

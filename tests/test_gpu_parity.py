@@ -121,7 +121,7 @@ def test_classification_bit_exact(gpu, ora, which):
 
 # ------------------------------------------------------ step-0 quantities
 
-@pytest.mark.parametrize("bc", [W.MC, W.LLKC, W.IMPROVED])
+@pytest.mark.parametrize("bc", [W.MC, W.LLKC, W.IMPROVED, W.FIXED])
 @pytest.mark.parametrize("avg", [0, 1])
 def test_forces_and_virtual_density_at_step0(gpu, ora, bc, avg):
     if bc != W.IMPROVED and avg == 1:
@@ -144,10 +144,13 @@ def test_forces_and_virtual_density_at_step0(gpu, ora, bc, avg):
 
 # ------------------------------------------------------------ dynamics
 
-@pytest.mark.parametrize("bc", [W.MC, W.LLKC, W.IMPROVED])
-def test_parity_ragged_tiles_all_bcs(gpu, ora, bc):
-    """Several tiles with ragged right/bottom edges, G = 3 demixing, all three rules."""
-    c = W.plane_drop(203, 97, 25.0, 15.0, bc, G=3.0, rho_out=0.055)
+@pytest.mark.parametrize("bc,avg,chi", [(W.MC, 0, (1.0, 1.0)), (W.LLKC, 0, (1.0, 1.0)), (W.IMPROVED, 0, (1.0, 1.0)),
+                                        (W.IMPROVED, 1, (1.15, 0.85)), (W.FIXED, 0, (0.7, 0.3))],
+                         ids=["martys-chen", "llkc", "improved-d2q25", "improved-d2q9", "fixed-virtual"])
+def test_parity_ragged_tiles_all_bcs(gpu, ora, bc, avg, chi):
+    """Several tiles with ragged right/bottom edges, G = 3 demixing, every rule."""
+    c = W.plane_drop(203, 97, 25.0, 15.0, bc, G=3.0, rho_out=0.055, chi=chi)
+    c.avg = avg
     for T, er, eu in compare_run(gpu, ora, c, [1, 10, 100, 300]):
         assert er <= RHO_TOL and eu <= U_TOL, (T, er, eu)
 

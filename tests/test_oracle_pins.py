@@ -253,6 +253,24 @@ def test_virtual_density_uniform_field_is_chi_rho(ora, avg):
     assert np.all(tA[~iface] == 0)
 
 
+def test_fixed_virtual_density_equals_improved_on_a_uniform_field(ora):
+    """Chen et al.'s constant solid density S^s = phi rho_s^s (Section 2) and the
+    improved rule S^s = phi rho~^s (Eq. 7) coincide when rho_s = chi rho for a
+    uniform fluid; with chi^A != chi^B a component swap in either rule shows."""
+    c = W.plane_drop(120, 90, 30.0, 15.0, W.IMPROVED)
+    m = ora.mask_plane(c.nx, c.ny, c.geometry[1], c.geometry[2])
+    rA = np.full(m.shape, 0.8)
+    rB = np.full(m.shape, 0.25)
+    imp = ora.Oracle(m, rA, rB, tau=1.0, G=3.0, bc=W.IMPROVED, chiA=1.3, chiB=0.6)
+    fix = ora.Oracle(m, rA, rB, tau=1.0, G=3.0, bc=W.FIXED, chiA=1.3 * 0.8, chiB=0.6 * 0.25)
+    fi, ff = imp.forces(), fix.forces()
+    scale = max(np.abs(x).max() for x in fi)
+    assert scale > 0.01
+    for a, b in zip(fi, ff):
+        np.testing.assert_allclose(b, a, rtol=0, atol=1e-14 * scale)
+    assert np.all(fix.virtual_density()[0] == 0)
+
+
 def test_virtual_density_linear_response_reveals_stencil(ora):
     """Perturb one fluid node by d: rho~ at an interface solid s changes by
     chi W(|e|^2) d / sum_fluid W, exactly for the D2Q25 offsets e = node - s

@@ -17,8 +17,8 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-MC, LLKC, IMPROVED = 0, 1, 2
-BC_NAMES = {MC: "martys-chen", LLKC: "llkc", IMPROVED: "improved"}
+MC, LLKC, IMPROVED, FIXED = 0, 1, 2, 3
+BC_NAMES = {MC: "martys-chen", LLKC: "llkc", IMPROVED: "improved", FIXED: "fixed-virtual"}
 
 
 @dataclass
@@ -101,7 +101,7 @@ def plane_drop(nx, ny, beta_deg, R0, bc, *, G=0.9, tau=1.0, rho_out=0.03, Gw=Non
     beta = math.radians(beta_deg)
     rA, rB = sharp_drop(nx, ny, nx / 2.0, ny / 2.0, R0, 1.0, rho_out)
     if Gw is None:
-        Gw = {MC: -0.2, LLKC: -0.5, IMPROVED: 0.0}[bc]
+        Gw = {MC: -0.2, LLKC: -0.5, IMPROVED: 0.0, FIXED: 0.0}[bc]
     return Case(name or "plane-%dx%d-b%g-%s" % (nx, ny, beta_deg, BC_NAMES[bc]), nx, ny, periodic=0,
                 tau=tau, G=G, bc=bc, Gw=Gw, chiA=chi[0], chiB=chi[1], steps=steps,
                 geometry=("plane", beta, float(R0)), rhoA0=rA, rhoB0=rB)
@@ -128,6 +128,41 @@ def config3(seed: int = 0) -> Case:
     return Case("c3-disk-1024-improved-seed%d" % seed, nx, ny, periodic=0, tau=1.0, G=0.9,
                 bc=IMPROVED, chiA=2.0 * s, chiB=2.0 - 2.0 * s, steps=50000,
                 geometry=("disk", cx, cy, Rs), rhoA0=rA, rhoB0=rB)
+
+
+def coalescence(R0: float, Rs: float | None = None, *, Oh=0.286, sigma=0.026, theta_deg=71.0, xi=-0.2,
+                rho1=1.0, rho2=0.055, delta=8.0, G=3.0, steps=None, aspect=(14.0, 10.0)) -> Case:
+    """Two drops coalescing on a flat (Rs None) or circular surface (Section 4).
+
+    Box L_X x L_Y = 14 R0 x 10 R0; the surface passes through (L_X/2, L_Y/2)
+    (flat: solid on or below y = L_Y/2; curved: the disk of radius Rs centred
+    at (L_X/2, L_Y/2 - Rs)); tanh drops of radius R0 placed at contact angle
+    theta against it, 2 nodes apart at the surface.  The viscosity follows
+    from the Ohnesorge number, nu = Oh sqrt(sigma R0) with rho = 1 and the
+    surface tension sigma of the Laplace test at G = 3; tau = 3 nu + 1/2.
+    Improved scheme with the wetting parameter xi read as chi^A = 1 - xi,
+    chi^B = 1 + xi (the reading under which xi = -0.2 gives the paper's
+    71 degrees and xi < 0 wets the drop fluid).  steps defaults to four
+    viscous times tau_nu = nu R0 / sigma."""
+    nx, ny = int(round(aspect[0] * R0)), int(round(aspect[1] * R0))
+    th = math.radians(theta_deg)
+    xc1 = nx / 2.0 - R0 * math.sin(th) - 1.0
+    xc2 = nx / 2.0 + R0 * math.sin(th) + 1.0
+    yc = ny / 2.0 - R0 * math.cos(th)
+    rA, rB = tanh_two_drops(nx, ny, xc1, xc2, yc, R0, rho1, rho2, delta)
+    nu = Oh * math.sqrt(sigma * R0)
+    tau = 3.0 * nu + 0.5
+    t_nu = nu * R0 / sigma
+    if Rs is None:
+        geom = ("plane", 0.0, 0.0)
+    else:
+        geom = ("disk", nx / 2.0, ny / 2.0 - Rs, float(Rs))
+    name = "coalescence-R0%g-%s-%dx%d" % (R0, "flat" if Rs is None else "Rs%g" % Rs, nx, ny)
+    c = Case(name, nx, ny, periodic=0, tau=tau, G=G, bc=IMPROVED, chiA=1.0 - xi, chiB=1.0 + xi,
+             steps=int(steps if steps is not None else round(4 * t_nu)), geometry=geom, rhoA0=rA, rhoB0=rB)
+    c.t_nu = t_nu
+    c.R0 = float(R0)
+    return c
 
 
 def config4_instances(n: int = 64, seed0: int = 0):
