@@ -425,6 +425,10 @@ __device__ void process_tile(const Inst &I, int tile_x, int tile_y, int parity, 
                 // interface solids lie inside the domain or across a periodic border
                 const int gx = wrap(tx0 + vx, I.nx, true), gy = wrap(ty0 + vy, I.ny, true);
                 const uint32_t m = I.m25[(size_t)gy * I.pitch + gx];
+                // every position of the 5 x 5 block is in LDS, solids and
+                // out-of-domain positions as 0, so the numerator needs no mask:
+                // all 48 reads issue back to back; the mask enters only the
+                // denominator
                 float na = 0.f, nb = 0.f, den = 0.f;
                 int j = 0;
 #pragma unroll
@@ -435,11 +439,9 @@ __device__ void process_tile(const Inst &I, int tile_x, int tile_y, int parity, 
                         const int r2 = ex * ex + ey * ey;
                         // D2Q25 weights, or the D2Q9 ones on the first belt
                         const float wt = I.avg == 0 ? W25_BY_R2[r2] : (r2 == 1 ? 1.f / 9.f : (r2 == 2 ? 1.f / 36.f : 0.f));
-                        if (((m >> j) & 1u) && wt != 0.f) {
-                            na += wt * sm.rho[0][rho_idx<TY>(vx + ex, vy + ey)];
-                            nb += wt * sm.rho[1][rho_idx<TY>(vx + ex, vy + ey)];
-                            den += wt;
-                        }
+                        na += wt * sm.rho[0][rho_idx<TY>(vx + ex, vy + ey)];
+                        nb += wt * sm.rho[1][rho_idx<TY>(vx + ex, vy + ey)];
+                        den += ((m >> j) & 1u) ? wt : 0.f;
                         ++j;
                     }
                 // den > 0: an interface solid has a fluid first-belt neighbour
