@@ -68,6 +68,14 @@ typedef enum {
 } lbm_bc;
 /* averaging lattice of the virtual solid density, Eq. 7 and the text after it */
 typedef enum { LBM_AVG_D2Q25 = 0, LBM_AVG_D2Q9 = 1 } lbm_avg;
+/* the paper's two-component model, or the single-component multiphase
+ * Shan-Chen model in which the paper also observed the sliding (Sections 3.1
+ * and 5): one population set, psi = psi_rho0 (1 - exp(-rho / psi_rho0)),
+ * F = -G psi(x) sum_i w_i psi(x + c_i) c_i over fluid neighbours (G < 0
+ * separates liquid and vapour), adhesion -G_w psi(x) S sum_i w_i phi(x + c_i) c_i
+ * with S = 1 (Martys-Chen) or psi(x) (LLKC).  rhoB0 is ignored (may be NULL),
+ * rhoB, FBx, FBy read back as 0; single simulations only (not batch or pool). */
+typedef enum { LBM_MODEL_TWO = 0, LBM_MODEL_SC1 = 1 } lbm_model;
 /* storage of the populations as deviations d_i = f_i - w_i rho_ref */
 typedef enum { LBM_STORE_F32 = 0, LBM_STORE_F16 = 1 } lbm_storage;
 
@@ -91,6 +99,8 @@ typedef struct {
     int32_t graph_steps; /* > 0: lbm_step replays a captured HIP graph of this many
                             steps (rounded up to even); 0 = plain launches */
     int32_t tile_y;      /* rows per tile: 0 = default (8), else 4, 8, 16 or 32 (512-thread workgroups) */
+    int32_t model;       /* lbm_model */
+    double psi_rho0;     /* single-component model: the density scale of psi */
 } lbm_params;
 
 /* Diagnostics, reduced in FP64 over fluid nodes at the handle's current time. */
@@ -107,7 +117,8 @@ typedef struct {
 typedef struct lbm_handle lbm_handle;
 
 /* Fills *p with defaults: tau 1, G 0.9, Martys-Chen with G_w 0, chi 1, D2Q25,
- * FP32 storage, rho_ref NaN, diag_every 0, drift_tol 0, graph_steps 0. */
+ * FP32 storage, rho_ref NaN, diag_every 0, drift_tol 0, graph_steps 0,
+ * two-component model, psi_rho0 1. */
 void lbm_params_default(lbm_params *p);
 
 /* Creates one simulation.  mask: nx*ny bytes, non-zero = solid (phi of

@@ -22,6 +22,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 BC_MARTYS_CHEN, BC_LLKC, BC_IMPROVED, BC_FIXED_VIRTUAL = 0, 1, 2, 3
 AVG_D2Q25, AVG_D2Q9 = 0, 1
+MODEL_TWO, MODEL_SC1 = 0, 1
 
 
 def build(force: bool = False) -> str:
@@ -42,7 +43,7 @@ class _Params(ctypes.Structure):
         ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("periodic", ctypes.c_uint),
         ("tau", ctypes.c_double), ("G", ctypes.c_double), ("bc", ctypes.c_int),
         ("Gw", ctypes.c_double), ("chiA", ctypes.c_double), ("chiB", ctypes.c_double),
-        ("avg", ctypes.c_int),
+        ("avg", ctypes.c_int), ("model", ctypes.c_int), ("rho0", ctypes.c_double),
     ]
 
 
@@ -139,14 +140,15 @@ class Oracle:
     """One simulation held by the C oracle (populations in FP64)."""
 
     def __init__(self, mask, rhoA0, rhoB0, *, tau, G, bc, Gw=0.0, chiA=1.0, chiB=1.0,
-                 avg=AVG_D2Q25, periodic=0):
+                 avg=AVG_D2Q25, periodic=0, model=MODEL_TWO, rho0=1.0):
+        """rhoB0 may be None for the single-component model (model=MODEL_SC1)."""
         mask = np.ascontiguousarray(mask, np.uint8)
         self.ny, self.nx = mask.shape
         self.mask = mask
         rA = np.ascontiguousarray(rhoA0, np.float64).reshape(self.ny, self.nx)
-        rB = np.ascontiguousarray(rhoB0, np.float64).reshape(self.ny, self.nx)
+        rB = np.zeros_like(rA) if rhoB0 is None else np.ascontiguousarray(rhoB0, np.float64).reshape(self.ny, self.nx)
         p = _Params(self.nx, self.ny, int(periodic), float(tau), float(G), int(bc), float(Gw),
-                    float(chiA), float(chiB), int(avg))
+                    float(chiA), float(chiB), int(avg), int(model), float(rho0))
         h = ctypes.c_void_p()
         rc = lib().ora_create(ctypes.byref(p), _ptr(mask), _ptr(rA), _ptr(rB), ctypes.byref(h))
         if rc != 0:

@@ -29,6 +29,14 @@
  *   - Initial populations are the rest equilibrium w_i rho_0.
  *   - In virtual-density schemes G_{sigma s} = G_{sigma sigma-bar} = G; for
  *     Martys-Chen and LLKC G_{As} = -G_{Bs} = G_w (Section 3.1).
+ *
+ * The single-component multiphase model (ORA_MODEL_SC1) is the standard
+ * Shan-Chen model the paper also ran (Sections 3.1 and 5), in the same
+ * convention: F = -G psi(x) sum_i w_i psi(x + c_i) c_i over fluid neighbours,
+ * psi = rho0 (1 - exp(-rho / rho0)), plus the adhesion force with the fluid
+ * node's pseudopotential in place of rho: Martys-Chen -G_w psi(x) sum_i w_i
+ * phi(x + c_i) c_i, LLKC (the solid takes the fluid node's psi)
+ * -G_w psi(x)^2 sum_i w_i phi(x + c_i) c_i.  Component B stays empty.
  */
 #include <math.h>
 #include <stdint.h>
@@ -214,7 +222,10 @@ static void free_state(ora_state *s) {
 int ora_create(const ora_params *p, const unsigned char *mask, const double *rhoA0, const double *rhoB0,
                ora_state **out) {
     *out = NULL;
-    if (!p || !mask || !rhoA0 || !rhoB0) return ORA_EINVAL;
+    if (!p || !mask || !rhoA0) return ORA_EINVAL;
+    if (p->model != ORA_MODEL_TWO && p->model != ORA_MODEL_SC1) return ORA_EINVAL;
+    if (p->model == ORA_MODEL_TWO && !rhoB0) return ORA_EINVAL;
+    if (p->model == ORA_MODEL_SC1 && (p->bc > ORA_BC_LLKC || !(p->rho0 > 0.0))) return ORA_EINVAL;
     if (p->nx <= 0 || p->ny <= 0) return ORA_EINVAL;
     if (!(p->tau > 0.5)) return ORA_EINVAL;
     if (p->bc < 0 || p->bc > 3 || p->avg < 0 || p->avg > 1) return ORA_EINVAL;
@@ -228,8 +239,9 @@ int ora_create(const ora_params *p, const unsigned char *mask, const double *rho
             /* fluid may not sit on a non-periodic border: its neighbours would leave the domain */
             if (!(p->periodic & 1) && (x == 0 || x == nx - 1)) return ORA_EINVAL;
             if (!(p->periodic & 2) && (y == 0 || y == ny - 1)) return ORA_EINVAL;
-            if (!(rhoA0[k] >= 0.0) || !(rhoB0[k] >= 0.0) || !(rhoA0[k] + rhoB0[k] > 0.0)) return ORA_EINVAL;
-            if (!isfinite(rhoA0[k]) || !isfinite(rhoB0[k])) return ORA_EINVAL;
+            const double rb = p->model == ORA_MODEL_SC1 ? 0.0 : rhoB0[k];
+            if (!(rhoA0[k] >= 0.0) || !(rb >= 0.0) || !(rhoA0[k] + rb > 0.0)) return ORA_EINVAL;
+            if (!isfinite(rhoA0[k]) || !isfinite(rb)) return ORA_EINVAL;
         }
     ora_state *s = (ora_state *)calloc(1, sizeof(ora_state));
     if (!s) return ORA_ENOMEM;
@@ -276,7 +288,7 @@ int ora_create(const ora_params *p, const unsigned char *mask, const double *rho
         if (s->phi[k]) continue;
         for (int i = 0; i < 9; ++i) {
             s->f[0][i][k] = W9[i] * rhoA0[k];
-            s->f[1][i][k] = W9[i] * rhoB0[k];
+            s->f[1][i][k] = p->model == ORA_MODEL_SC1 ? 0.0 : W9[i] * rhoB0[k];
         }
     }
     s->t = 0;
@@ -361,6 +373,29 @@ static void macroscopic(ora_state *s) {
                 s->u[1][k] = 0.0;
                 continue;
             }
+            if (p->model == ORA_MODEL_SC1) {
+                /* single component: self-interaction through psi, adhesion with psi(x) */
+                const double r0 = p->rho0;
+                const double psi = r0 * (1.0 - exp(-s->rho[0][k] / r0));
+                double scx = 0.0, scy = 0.0, adx = 0.0, ady = 0.0;
+                for (int i = 1; i < 9; ++i) {
+                    long kn;
+                    neighbour(s, x, y, CX[i], CY[i], &kn);
+                    if (!s->phi[kn]) {
+                        const double pn = r0 * (1.0 - exp(-s->rho[0][kn] / r0));
+                        scx += W9[i] * pn * CX[i];
+                        scy += W9[i] * pn * CY[i];
+                    } else {
+                        const double S = p->bc == ORA_BC_MARTYS_CHEN ? 1.0 : psi; /* phi, or phi psi(x) */
+                        adx += W9[i] * S * CX[i];
+                        ady += W9[i] * S * CY[i];
+                    }
+                }
+                s->F[0][0][k] = -G * psi * scx - p->Gw * psi * adx;
+                s->F[0][1][k] = -G * psi * scy - p->Gw * psi * ady;
+                s->F[1][0][k] = 0.0;
+                s->F[1][1][k] = 0.0;
+            } else
             for (int c = 0; c < 2; ++c) {
                 const int cb = 1 - c; /* sigma-bar */
                 double scx = 0.0, scy = 0.0; /* sum_i w_i psi^sbar(x+c_i) c_i over fluid neighbours */
@@ -416,7 +451,8 @@ static void collide_stream(ora_state *s) {
             const long k = (long)y * nx + x;
             if (s->phi[k]) continue;
             const double ux = s->u[0][k], uy = s->u[1][k];
-            for (int c = 0; c < 2; ++c) {
+            const int ncomp = s->p.model == ORA_MODEL_SC1 ? 1 : 2;
+            for (int c = 0; c < ncomp; ++c) {
                 double feq[9], S[9];
                 equilibrium(s->rho[c][k], ux, uy, feq);
                 guo_source(tau, ux, uy, s->F[c][0][k], s->F[c][1][k], S);

@@ -16,6 +16,11 @@ extern "C" {
 enum { ORA_OK = 0, ORA_EINVAL = -1, ORA_ENOMEM = -2 };
 enum { ORA_BC_MARTYS_CHEN = 0, ORA_BC_LLKC = 1, ORA_BC_IMPROVED = 2, ORA_BC_FIXED_VIRTUAL = 3 };
 enum { ORA_AVG_D2Q25 = 0, ORA_AVG_D2Q9 = 1 };
+/* two components (the paper's model), or the single-component multiphase
+ * Shan-Chen model the paper compares against (Section 3.1, Section 5):
+ * one population set, psi = rho0 (1 - exp(-rho / rho0)), self-interaction
+ * strength G (< 0 separates phases), Martys-Chen or LLKC adhesion with G_w. */
+enum { ORA_MODEL_TWO = 0, ORA_MODEL_SC1 = 1 };
 
 typedef struct {
     int nx, ny;
@@ -27,6 +32,8 @@ typedef struct {
     double chiA, chiB; /* improved scheme: chi^A, chi^B of Eq. 7; fixed virtual
                           density: the solid densities rho_s^A, rho_s^B (Section 2) */
     int avg;           /* averaging lattice of Eq. 7: ORA_AVG_D2Q25 or ORA_AVG_D2Q9 */
+    int model;         /* ORA_MODEL_* */
+    double rho0;       /* single-component model: psi = rho0 (1 - exp(-rho / rho0)) */
 } ora_params;
 
 typedef struct ora_state ora_state;

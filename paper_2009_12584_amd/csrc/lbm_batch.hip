@@ -299,6 +299,10 @@ int lbm_batch_create(int32_t n, const lbm_params *params, const uint8_t *const *
     for (int k = 0; k < n; ++k) {
         int rc = validate(&params[k], masks[k], rhoA0[k], rhoB0[k]);
         if (rc) return rc;
+        if (params[k].model != LBM_MODEL_TWO) {
+            set_err("instance %d: batches run the two-component model only", k);
+            return LBM_EINVAL;
+        }
         if (params[k].storage != params[0].storage || default_ty(params[k]) != default_ty(params[0])) {
             set_err("instance %d: every instance of a batch uses the same storage and tile rows", k);
             return LBM_EINVAL;
@@ -626,6 +630,10 @@ int lbm_pool_admit(lbm_pool *P, const lbm_params *p, const uint8_t *mask, const 
     if (!P || !slot || nsteps < 0) return LBM_EINVAL;
     int rc = validate(p, mask, rhoA0, rhoB0);
     if (rc) return rc;
+    if (p->model != LBM_MODEL_TWO) {
+        set_err("the pool runs the two-component model only");
+        return LBM_EINVAL;
+    }
     if (p->storage != P->storage) {
         set_err("pool storage is %d, request asks for %d", P->storage, p->storage);
         return LBM_EINVAL;

@@ -15,6 +15,7 @@
 
 #include "../../include/mclbm.h"
 #include "lbm_device.hpp"
+#include "lbm_sc1.hpp"
 
 namespace mclbm {
 
@@ -44,6 +45,12 @@ inline void set_err(const char *fmt, ...) {
 inline int pitch_of(int nx) { return (nx + 63) / 64 * 64; }
 inline int default_ty(const lbm_params &p) { return p.tile_y > 0 ? p.tile_y : 8; }
 inline size_t store_bytes(int storage) { return storage == LBM_STORE_F16 ? 2 : 4; }
+// populations stored per node: 9 directions of both components, or of one
+inline int pops_per_node(const lbm_params &p) { return p.model == LBM_MODEL_SC1 ? 9 : 18; }
+// bytes of one population buffer
+inline size_t pop_buffer_bytes(const lbm_params &p) {
+    return (size_t)pops_per_node(p) * (size_t)p.ny * pitch_of(p.nx) * store_bytes(p.storage);
+}
 
 // Bytes of device memory one simulation holds (two population buffers, node
 // flags, classification, tile flags, diagnostic partials and targets).
@@ -52,22 +59,35 @@ inline size_t footprint_bytes(const lbm_params &p) {
     const size_t plane = (size_t)p.ny * pitch_of(p.nx);
     const int ty = default_ty(p);
     const size_t tiles = (size_t)((p.nx + TX - 1) / TX) * ((p.ny + ty - 1) / ty);
-    return 2 * 18 * plane * store_bytes(p.storage) + 2 * n + plane * 8 + tiles + tiles * 48 + sizeof(DiagDev) + 4096;
+    return 2 * pop_buffer_bytes(p) + 2 * n + plane * 8 + tiles + tiles * 48 + sizeof(DiagDev) + 4096;
 }
 
 // Validation of everything that can be checked on the host before any device
 // call (Section 2: tau > 1/2; Section 3.1: closed borders are solid walls).
 inline int validate(const lbm_params *p, const uint8_t *mask, const double *rA, const double *rB) {
-    if (!p || !mask || !rA || !rB) {
+    if (!p || !mask || !rA) {
         set_err("null argument");
+        return LBM_EINVAL;
+    }
+    if (p->model != LBM_MODEL_TWO && p->model != LBM_MODEL_SC1) {
+        set_err("model %d out of range", p->model);
+        return LBM_EINVAL;
+    }
+    const bool sc1 = p->model == LBM_MODEL_SC1;
+    if (!sc1 && !rB) {
+        set_err("null rhoB0 for the two-component model");
+        return LBM_EINVAL;
+    }
+    if (sc1 && (p->bc > LBM_BC_LLKC || !(p->psi_rho0 > 0.0) || !std::isfinite(p->psi_rho0))) {
+        set_err("single-component model: bc must be Martys-Chen or LLKC and psi_rho0 finite and > 0");
         return LBM_EINVAL;
     }
     if (p->nx < 1 || p->ny < 1) {
         set_err("grid %d x %d: both sizes must be >= 1", p->nx, p->ny);
         return LBM_EINVAL;
     }
-    // the 9 planes of (A, B) pairs are addressed with 32-bit byte offsets
-    if ((double)p->ny * pitch_of(p->nx) * 18.0 * (double)store_bytes(p->storage) >= 4294967296.0) {
+    // the 9 population planes are addressed with 32-bit byte offsets
+    if ((double)p->ny * pitch_of(p->nx) * pops_per_node(*p) * (double)store_bytes(p->storage) >= 4294967296.0) {
         set_err("grid %d x %d: a population buffer would exceed 4 GiB", p->nx, p->ny);
         return LBM_EINVAL;
     }
@@ -111,7 +131,7 @@ inline int validate(const lbm_params *p, const uint8_t *mask, const double *rA, 
                 set_err("fluid node (%d,%d) on a non-periodic y border", x, y);
                 return LBM_EINVAL;
             }
-            const double a = rA[k], b = rB[k];
+            const double a = rA[k], b = sc1 ? 0.0 : rB[k];
             if (!std::isfinite(a) || !std::isfinite(b) || a < 0.0 || b < 0.0 || !(a + b > 0.0)) {
                 set_err("initial densities at (%d,%d) = (%g, %g): need finite, >= 0, sum > 0", x, y, a, b);
                 return LBM_EINVAL;
@@ -133,7 +153,7 @@ inline void resolve_rref(const lbm_params &p, const uint8_t *mask, const double 
     for (size_t k = 0; k < N; ++k)
         if (!mask[k]) {
             lo[0] = std::min(lo[0], rA[k]);
-            lo[1] = std::min(lo[1], rB[k]);
+            lo[1] = std::min(lo[1], rB ? rB[k] : 0.0);
         }
     for (int c = 0; c < 2; ++c) {
         if (!std::isfinite(lo[c])) lo[c] = 0.0;
@@ -167,6 +187,9 @@ inline void fill_inst(Inst &I, const lbm_params &p, const double rref[2], int ty
         // virtual-density schemes use G_{sigma s} = G_{sigma sigma-bar} (Section 2)
         I.GsA = (float)p.G;
         I.GsB = (float)p.G;
+    } else if (p.model == LBM_MODEL_SC1) {
+        I.GsA = (float)p.G_w;  // one adhesion strength
+        I.GsB = 0.f;
     } else if (p.bc == LBM_BC_FIXED_VIRTUAL) {
         I.GsA = (float)(p.G * p.chi[1]);
         I.GsB = (float)(p.G * p.chi[0]);
@@ -178,6 +201,7 @@ inline void fill_inst(Inst &I, const lbm_params &p, const double rref[2], int ty
     I.chiB = (float)p.chi[1];
     I.rrefA = (float)rref[0];
     I.rrefB = (float)rref[1];
+    I.psi0 = (float)p.psi_rho0;
     // tile walk in groups of 16 tile columns; streaming stores (the next step
     // reads them from HBM anyway on grids larger than the caches)
     I.tg = 16;
@@ -318,6 +342,26 @@ __global__ void k_init(Inst I, const double *__restrict__ rA, const double *__re
     }
 }
 
+// The same initial buffer for the single-component model (one plane set).
+template <typename S>
+__global__ void k_init_sc1(Inst I, const double *__restrict__ rA, double rref, int which) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= (int64_t)I.nx * I.ny) return;
+    const int x = (int)(k % I.nx), y = (int)(k / I.nx);
+    if (I.node[(int64_t)y * I.pitch + x] & NW_SOLID) return;
+    using P = typename Store1<S>::P;
+    P *b = (P *)I.buf[which];
+    const int64_t own = (int64_t)y * I.pitch + x;
+    const double wd[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+    const double sc = (double)Store1<S>::SC;
+    for (int j = 0; j < 9; ++j) {
+        const int xs = wrap(x + CX[j], I.nx, true), ys = wrap(y + CY[j], I.ny, true);
+        int64_t src = (int64_t)ys * I.nx + xs;
+        if (I.node[(int64_t)ys * I.pitch + xs] & NW_SOLID) src = k;
+        Store1<S>::put(b + (int64_t)j * I.plane + own, Store1<S>::enc((float)(wd[j] * (rA[src] - rref) * sc)));
+    }
+}
+
 // Device arrays of one simulation's geometry (all allocated by the caller).
 struct Geometry {
     uint8_t *nbr, *cls;   // nx * ny, the classification returned by the ABI
@@ -347,12 +391,18 @@ inline int enqueue_setup(Inst &I, const lbm_params &p, int ty, const uint8_t *dm
     I.node = g.word;
     I.m25 = g.m25;
     I.tflag = g.tflag;
-    if (p.storage == LBM_STORE_F16)
+    if (p.model == LBM_MODEL_SC1) {
+        if (p.storage == LBM_STORE_F16)
+            hipLaunchKernelGGL(k_init_sc1<__half>, dim3(nb), dim3(256), 0, s, I, drA, (double)I.rrefA, 0);
+        else
+            hipLaunchKernelGGL(k_init_sc1<float>, dim3(nb), dim3(256), 0, s, I, drA, (double)I.rrefA, 0);
+    } else if (p.storage == LBM_STORE_F16) {
         hipLaunchKernelGGL(k_init<__half>, dim3(nb), dim3(256), 0, s, I, drA, drB, (double)I.rrefA, (double)I.rrefB,
                            0);
-    else
+    } else {
         hipLaunchKernelGGL(k_init<float>, dim3(nb), dim3(256), 0, s, I, drA, drB, (double)I.rrefA, (double)I.rrefB,
                            0);
+    }
     MCLBM_HIP(hipGetLastError());
     return LBM_OK;
 }
@@ -386,6 +436,16 @@ __global__ __launch_bounds__(threads_for(TY)) void k_step(Inst I, int parity, Fi
     tile_coords(xcd_tile(blockIdx.x, gridDim.x), I.tiles_x, I.tiles_y, I.tg, tx, ty);
     DiagAcc acc;
     process_tile<S, TY, BC, MODE, DIAG>(I, tx, ty, parity, sm, acc, fo);
+    if (DIAG) diag_partial<TY>(sm, acc, partials, blockIdx.x);
+}
+
+template <typename S, int TY, int BC, int MODE, bool DIAG>
+__global__ __launch_bounds__(threads_for(TY)) void k_step_sc1(Inst I, int parity, Fields fo, double *partials) {
+    __shared__ Smem<TY> sm;
+    int tx, ty;
+    tile_coords(xcd_tile(blockIdx.x, gridDim.x), I.tiles_x, I.tiles_y, I.tg, tx, ty);
+    DiagAcc acc;
+    process_tile_sc1<S, TY, BC, MODE, DIAG>(I, tx, ty, parity, sm, acc, fo);
     if (DIAG) diag_partial<TY>(sm, acc, partials, blockIdx.x);
 }
 
@@ -437,15 +497,30 @@ static __global__ __launch_bounds__(256) void k_diag_reduce(const double *__rest
     }
 }
 
-// Runtime dispatch over (storage, tile rows, BC, mode, diag).
+// Runtime dispatch over (storage, tile rows, BC, mode, diag, model).
 struct Launch {
     int storage, ty, bc, mode;
     bool diag;
+    int model = LBM_MODEL_TWO;
 };
 
 template <typename S, int TY, int BC>
 inline void launch3(const Launch &L, dim3 g, hipStream_t s, const Inst &I, int parity, const Fields &fo,
                     double *partials) {
+    if (L.model == LBM_MODEL_SC1) {
+        if constexpr (BC == BC_MC || BC == BC_LLKC) {
+            if (L.mode == MODE_FIELDS)
+                hipLaunchKernelGGL((k_step_sc1<S, TY, BC, MODE_FIELDS, true>), g, dim3(threads_for(TY)), 0, s, I,
+                                   parity, fo, partials);
+            else if (L.diag)
+                hipLaunchKernelGGL((k_step_sc1<S, TY, BC, MODE_STEP, true>), g, dim3(threads_for(TY)), 0, s, I,
+                                   parity, fo, partials);
+            else
+                hipLaunchKernelGGL((k_step_sc1<S, TY, BC, MODE_STEP, false>), g, dim3(threads_for(TY)), 0, s, I,
+                                   parity, fo, partials);
+        }
+        return;
+    }
     if (L.mode == MODE_FIELDS)
         hipLaunchKernelGGL((k_step<S, TY, BC, MODE_FIELDS, true>), g, dim3(threads_for(TY)), 0, s, I, parity, fo, partials);
     else if (L.diag)

@@ -130,6 +130,7 @@ struct Inst {
     float G, GsA, GsB;        // Eq. 5 strength and the adhesion strengths of Eq. 6
     float chiA, chiB;         // Eq. 7
     float rrefA, rrefB;       // deviation references
+    float psi0;               // single-component model: psi = psi0 (1 - exp(-rho / psi0))
     int tg;                   // tile columns per group of the tile walk
     int nt;                   // streaming (non-temporal) stores
     int parity0;              // pool: parity of the buffer read at launch counter 0
@@ -195,27 +196,30 @@ __device__ __forceinline__ uint32_t node_word(const Inst &I, int gx, int gy) {
 }
 
 // Byte offsets, within one population plane, of the 3 x 3 block around a fluid
-// node.  Only tiles on a periodic border (edge) need the wrap: elsewhere a
-// fluid node's neighbours are inside the domain.
+// node, for plane elements of NC components of type S.  Only tiles on a
+// periodic border (edge) need the wrap: elsewhere a fluid node's neighbours
+// are inside the domain.
 struct Around {
     uint32_t row[3], col[3];
 };
 
-template <typename S> __device__ __forceinline__ Around around(const Inst &I, int gx, int gy, bool edge) {
+template <typename S, int NC = 2>
+__device__ __forceinline__ Around around(const Inst &I, int gx, int gy, bool edge) {
+    constexpr uint32_t EB = (uint32_t)sizeof(S) * NC;
     Around a;
     if (!edge) {
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
-            a.col[j] = (uint32_t)(gx - 1 + j) * (uint32_t)sizeof(S) * 2u;
-            a.row[j] = (uint32_t)(gy - 1 + j) * (uint32_t)(I.pitch * sizeof(S) * 2);
+            a.col[j] = (uint32_t)(gx - 1 + j) * EB;
+            a.row[j] = (uint32_t)(gy - 1 + j) * (uint32_t)I.pitch * EB;
         }
         return a;
     }
     const bool small = I.small != 0;
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-        a.col[j] = (uint32_t)wrap(gx - 1 + j, I.nx, small) * (uint32_t)sizeof(S) * 2u;
-        a.row[j] = (uint32_t)wrap(gy - 1 + j, I.ny, small) * (uint32_t)(I.pitch * sizeof(S) * 2);
+        a.col[j] = (uint32_t)wrap(gx - 1 + j, I.nx, small) * EB;
+        a.row[j] = (uint32_t)wrap(gy - 1 + j, I.ny, small) * (uint32_t)I.pitch * EB;
     }
     return a;
 }

@@ -1,0 +1,229 @@
+// Single-component multiphase Shan-Chen model on the same tiles, geometry
+// and storage scheme as the two-component step.  The paper reports that its
+// wetting problem (a drop sliding on an off-grid wall under Martys-Chen and
+// LLKC adhesion) appears in this standard model as well (Sections 3.1, 5).
+//
+// One population set, stored as 9 planes of single deviations
+// d_i = f_i - w_i rho_ref (FP32, or FP16 x 2^10).  Per step and node:
+//   rho = sum_i f_i (pull streaming with half-way bounce-back),
+//   psi = psi0 (1 - exp(-rho / psi0)),
+//   F = -G psi(x) sum_i w_i psi(x + c_i) c_i over fluid neighbours
+//       - G_w psi(x) S sum_i w_i phi(x + c_i) c_i,  S = 1 (Martys-Chen) or
+//       psi(x) (LLKC: the solid takes the fluid node's pseudopotential),
+//   u = (sum_i f_i c_i + F / 2) / rho, BGK collision with the Guo source
+//   (Eqs. 1-4 of the paper with a single component).
+// The halo is one node: psi of the tile plus one ring goes to LDS, computed
+// from the pulled densities exactly as the owning tile computes it, so every
+// tile sees the same psi for a node.
+#pragma once
+
+#include "lbm_device.hpp"
+
+namespace mclbm {
+
+template <typename S> struct Store1;
+template <> struct Store1<float> {
+    using P = float;
+    static constexpr float SC = 1.f;
+    static __device__ __forceinline__ float ld(const float *p) { return *p; }
+    static __device__ __forceinline__ float enc(float a) { return a; }
+    static __device__ __forceinline__ float dec(float v) { return v; }
+    static __device__ __forceinline__ void put(float *p, float v) { *p = v; }
+    static __device__ __forceinline__ void putnt(float *p, float v) { __builtin_nontemporal_store(v, p); }
+};
+template <> struct Store1<__half> {
+    using P = __half;
+    static constexpr float SC = 1024.f;
+    static __device__ __forceinline__ float ld(const __half *p) { return __half2float(*p); }
+    static __device__ __forceinline__ __half enc(float a) { return __float2half_rn(a); }
+    static __device__ __forceinline__ float dec(__half v) { return __half2float(v); }
+    static __device__ __forceinline__ void put(__half *p, __half v) { *p = v; }
+    static __device__ __forceinline__ void putnt(__half *p, __half v) {
+        __builtin_nontemporal_store(__builtin_bit_cast(uint16_t, v), (uint16_t *)p);
+    }
+};
+
+// Pull of the 9 populations at a fluid node (bounce-back from the node word).
+template <typename S>
+__device__ __forceinline__ void pull9_1(const typename Store1<S>::P *__restrict__ base, uint32_t pb, const Around &a,
+                                        uint32_t w, float d[9]) {
+    const uint32_t own = a.row[1] + a.col[1];
+    d[0] = Store1<S>::ld(at(base, own));
+#pragma unroll
+    for (int i = 1; i < 9; ++i) {
+        const uint32_t up = a.row[1 - CY[i]] + a.col[1 - CX[i]];
+        const bool bb = (w >> (OPP[i] - 1)) & 1u;
+        const uint32_t off = bb ? (uint32_t)OPP[i] * pb + own : (uint32_t)i * pb + up;
+        d[i] = Store1<S>::ld(at(base, off));
+    }
+}
+
+__device__ __forceinline__ float psi_of(float rho, float psi0) { return psi0 * (1.f - expf(-rho / psi0)); }
+
+template <typename S, int TY, int BC, int MODE, bool DIAG>
+__device__ void process_tile_sc1(const Inst &I, int tile_x, int tile_y, int parity, Smem<TY> &sm, DiagAcc &acc,
+                                 const Fields &fo) {
+    constexpr int RPP = threads_for(TY) / 64;
+    constexpr int RPT = TY / RPP;
+    constexpr float SC = Store1<S>::SC;
+    using P = typename Store1<S>::P;
+    const int tid = threadIdx.x;
+    const int tx0 = tile_x * TX, ty0 = tile_y * TY;
+    const P *__restrict__ fin = (const P *)I.buf[parity];
+    P *__restrict__ fout = (P *)I.buf[parity ^ 1];
+    const uint32_t pb = (uint32_t)(I.plane * (int64_t)sizeof(P));
+    const double rref = (double)I.rrefA;
+    const bool edge = I.small || ((I.periodic & 1u) && (tx0 - FH < 0 || tx0 + TX + FH > I.nx)) ||
+                      ((I.periodic & 2u) && (ty0 - FH < 0 || ty0 + TY + FH > I.ny));
+
+    // ---- owned rectangle: populations in registers
+    const int lx = tid & (TX - 1);
+    const int lr = tid >> 6;
+    float d[RPT][9];
+    double sd[RPT];
+    uint32_t w[RPT], own[RPT];
+    bool owned[RPT];
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+        const int ly = lr + RPP * r;
+        const int gx = tx0 + lx, gy = ty0 + ly;
+        w[r] = node_word(I, gx, gy);
+        owned[r] = gx < I.nx && gy < I.ny;
+        own[r] = (uint32_t)(gy * I.pitch + gx) * (uint32_t)sizeof(P);
+        if (!(w[r] & NW_SOLID)) {
+            pull9_1<S>(fin, pb, around<S, 1>(I, gx, gy, edge), w[r], d[r]);
+        } else {
+#pragma unroll
+            for (int i = 0; i < 9; ++i) d[r][i] = 0.f;
+        }
+    }
+
+    // ---- one-node frame: psi of the neighbours (0 at solids, never read there):
+    // the rows above and below (TX + 2 each), then the columns left and right
+    constexpr int FW = TX + 2, TOTAL = 2 * FW + 2 * TY;
+    for (int k = tid; k < TOTAL; k += threads_for(TY)) {
+        int hx, hy;
+        if (k < 2 * FW) {
+            hy = k < FW ? -1 : TY;
+            hx = (k < FW ? k : k - FW) - 1;
+        } else {
+            const int q = k - 2 * FW;
+            hy = q % TY;
+            hx = q < TY ? -1 : TX;
+        }
+        const int gx = tx0 + hx, gy = ty0 + hy;
+        const uint32_t wf = node_word(I, gx, gy);
+        float ps = 0.f;
+        if (!(wf & NW_SOLID)) {
+            float df[9];
+            pull9_1<S>(fin, pb, around<S, 1>(I, gx, gy, edge), wf, df);
+            ps = psi_of((float)(rref + dsum9(df) * (double)(1.f / SC)), I.psi0);
+        }
+        sm.rho[0][rho_idx<TY>(hx, hy)] = ps;
+    }
+
+    // ---- owned densities and pseudopotentials
+    float rho[RPT];
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+        const int ly = lr + RPP * r;
+        sd[r] = dsum9(d[r]);
+        rho[r] = (float)(rref + sd[r] * (double)(1.f / SC));
+        sm.rho[0][rho_idx<TY>(lx, ly)] = (w[r] & NW_SOLID) ? 0.f : psi_of(rho[r], I.psi0);
+    }
+    __syncthreads();
+
+    // ---- forces, velocity, collision, store
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+        const int ly = lr + RPP * r;
+        if (!owned[r]) continue;
+        const size_t oidx = (size_t)(ty0 + ly) * I.nx + (tx0 + lx);
+        if (w[r] & NW_SOLID) {
+            if (MODE == MODE_FIELDS) {
+                float *outs[10] = {fo.rhoA, fo.rhoB, fo.ux, fo.uy, fo.FAx, fo.FAy, fo.FBx, fo.FBy, fo.rtA, fo.rtB};
+#pragma unroll
+                for (int q = 0; q < 10; ++q)
+                    if (outs[q]) outs[q][oidx] = 0.f;
+            }
+            continue;
+        }
+        const float ra = rho[r];
+        const float px = sm.rho[0][rho_idx<TY>(lx, ly)];
+        float sx = 0.f, sy = 0.f;  // sum w psi c over fluid neighbours
+        float nxs = 0.f, nys = 0.f;  // sum w phi c
+#pragma unroll
+        for (int i = 1; i < 9; ++i) {
+            const float wi = WF[i];
+            if (!((w[r] >> (i - 1)) & 1u)) {
+                const float a = wi * sm.rho[0][rho_idx<TY>(lx + CX[i], ly + CY[i])];
+                sx += a * CX[i];
+                sy += a * CY[i];
+            } else {
+                nxs += wi * CX[i];
+                nys += wi * CY[i];
+            }
+        }
+        const float Sw = BC == BC_MC ? 1.f : px;  // the solid's pseudopotential
+        const float Fx = -I.G * px * sx - I.GsA * px * Sw * nxs;
+        const float Fy = -I.G * px * sy - I.GsA * px * Sw * nys;
+        float jx = (d[r][1] - d[r][3]) + (d[r][5] - d[r][6]) + (d[r][8] - d[r][7]);
+        float jy = (d[r][2] - d[r][4]) + (d[r][5] - d[r][8]) + (d[r][6] - d[r][7]);
+        jx *= 1.f / SC;
+        jy *= 1.f / SC;
+        const float inv = 1.f / ra;
+        const float ux = (jx + 0.5f * Fx) * inv;
+        const float uy = (jy + 0.5f * Fy) * inv;
+
+        if (DIAG) {
+            acc.mA += rref + sd[r] * (double)(1.f / SC);
+            acc.px += (double)ra * (double)ux;
+            acc.py += (double)ra * (double)uy;
+            acc.u2max = fmaxf(acc.u2max, ux * ux + uy * uy);
+            if (!isfinite(ra + ux + uy)) acc.flags |= 1;
+            if (ra < 0.f) acc.flags |= 2;
+        }
+        if (MODE == MODE_FIELDS) {
+            if (fo.rhoA) fo.rhoA[oidx] = ra;
+            if (fo.rhoB) fo.rhoB[oidx] = 0.f;
+            if (fo.ux) fo.ux[oidx] = ux;
+            if (fo.uy) fo.uy[oidx] = uy;
+            if (fo.FAx) fo.FAx[oidx] = Fx;
+            if (fo.FAy) fo.FAy[oidx] = Fy;
+            if (fo.FBx) fo.FBx[oidx] = 0.f;
+            if (fo.FBy) fo.FBy[oidx] = 0.f;
+            if (fo.rtA) fo.rtA[oidx] = 0.f;
+            if (fo.rtB) fo.rtB[oidx] = 0.f;
+            continue;
+        }
+        // Eqs. 1, 2, 4 in deviation form and storage units; the rest
+        // population takes the exact remainder of the incoming sum
+        const float uu = ux * ux + uy * uy;
+        const float uF = ux * Fx + uy * Fy;
+        const float dr = (float)sd[r] * (1.f / SC);
+        P *o = at(fout, own[r]);
+        double so = 0.0;
+#pragma unroll
+        for (int i = 1; i < 9; ++i) {
+            const float cu = CX[i] * ux + CY[i] * uy;
+            const float cF = CX[i] * Fx + CY[i] * Fy;
+            const float eq = 3.f * cu + 4.5f * cu * cu - 1.5f * uu;
+            const float deq = (WF[i] * SC) * (dr + ra * eq);
+            const float src = (WF[i] * SC) * I.guo * (3.f * (cF - uF) + 9.f * cu * cF);
+            const float di = d[r][i];
+            const P q = Store1<S>::enc(di + I.omega * (deq - di) + src);
+            so += (double)Store1<S>::dec(q);
+            if (I.nt)
+                Store1<S>::putnt(at(o, (uint32_t)i * pb), q);
+            else
+                Store1<S>::put(at(o, (uint32_t)i * pb), q);
+        }
+        const P q0 = Store1<S>::enc((float)(sd[r] - so));
+        if (I.nt)
+            Store1<S>::putnt(o, q0);
+        else
+            Store1<S>::put(o, q0);
+    }
+}
+
+}  // namespace mclbm

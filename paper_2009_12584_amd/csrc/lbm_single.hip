@@ -48,7 +48,7 @@ void release(lbm_handle *h) {
 }
 
 Launch launch_of(const lbm_handle *h, int mode, bool diag) {
-    return Launch{h->p.storage, h->ty, kernel_bc(h->p), mode, diag};
+    return Launch{h->p.storage, h->ty, kernel_bc(h->p), mode, diag, h->p.model};
 }
 
 int run_fields(lbm_handle *h, const Fields &fo) {
@@ -99,6 +99,8 @@ void lbm_params_default(lbm_params *p) {
     p->avg = LBM_AVG_D2Q25;
     p->storage = LBM_STORE_F32;
     p->rho_ref[0] = p->rho_ref[1] = NAN;
+    p->model = LBM_MODEL_TWO;
+    p->psi_rho0 = 1.0;
 }
 
 int lbm_create(const lbm_params *p, const uint8_t *mask, const double *rhoA0, const double *rhoB0, void *stream,
@@ -130,7 +132,8 @@ int lbm_create(const lbm_params *p, const uint8_t *mask, const double *rhoA0, co
     fill_inst(h->I, *p, rref, h->ty);
     h->ntiles = h->I.tiles_x * h->I.tiles_y;
     const size_t n = (size_t)p->nx * p->ny;
-    const size_t bufbytes = 18 * (size_t)h->I.plane * store_bytes(p->storage);
+    const size_t bufbytes = pop_buffer_bytes(*p);
+    const bool two = p->model == LBM_MODEL_TWO;
     uint8_t *dmask = nullptr;
     uint16_t *word0 = nullptr;
     double *drA = nullptr, *drB = nullptr;
@@ -148,7 +151,7 @@ int lbm_create(const lbm_params *p, const uint8_t *mask, const double *rhoA0, co
         MCLBM_HIP(hipMalloc(&dmask, n));
         MCLBM_HIP(hipMalloc(&word0, np * sizeof(uint16_t)));
         MCLBM_HIP(hipMalloc(&drA, n * sizeof(double)));
-        MCLBM_HIP(hipMalloc(&drB, n * sizeof(double)));
+        if (two) MCLBM_HIP(hipMalloc(&drB, n * sizeof(double)));
         hipStream_t s = h->stream;
         MCLBM_HIP(hipMemsetAsync(h->I.buf[0], 0, bufbytes, s));
         MCLBM_HIP(hipMemsetAsync(h->I.buf[1], 0, bufbytes, s));
@@ -160,7 +163,7 @@ int lbm_create(const lbm_params *p, const uint8_t *mask, const double *rhoA0, co
         MCLBM_HIP(hipMemcpyAsync(h->dd, &z, sizeof z, hipMemcpyHostToDevice, s));
         MCLBM_HIP(hipMemcpyAsync(dmask, mask, n, hipMemcpyHostToDevice, s));
         MCLBM_HIP(hipMemcpyAsync(drA, rhoA0, n * sizeof(double), hipMemcpyHostToDevice, s));
-        MCLBM_HIP(hipMemcpyAsync(drB, rhoB0, n * sizeof(double), hipMemcpyHostToDevice, s));
+        if (two) MCLBM_HIP(hipMemcpyAsync(drB, rhoB0, n * sizeof(double), hipMemcpyHostToDevice, s));
         const Geometry g{h->nbr, h->cls, h->word, h->m25, h->tflag, word0};
         int r = enqueue_setup(h->I, *p, h->ty, dmask, drA, drB, g, s);
         if (r) return r;
@@ -341,7 +344,7 @@ int lbm_classify(lbm_handle *h, uint8_t *nbr, uint8_t *cls) {
 }
 
 size_t lbm_state_bytes(const lbm_handle *h) {
-    return h ? 18 * (size_t)h->I.plane * store_bytes(h->p.storage) : 0;
+    return h ? pop_buffer_bytes(h->p) : 0;
 }
 
 int lbm_get_state(lbm_handle *h, void *host, int64_t *step) {

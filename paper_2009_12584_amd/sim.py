@@ -58,10 +58,11 @@ class Simulation:
         self.ny, self.nx = mask.shape
         self.params = capi.make_params(self.nx, self.ny, **params)
         rA = _host(rhoA0, np.float64, mask.shape)
-        rB = _host(rhoB0, np.float64, mask.shape)
+        # the single-component model reads no rhoB0
+        rB = None if rhoB0 is None else _host(rhoB0, np.float64, mask.shape)
         h = ctypes.c_void_p()
-        code = lib().lbm_create(ctypes.byref(self.params), _p(mask), _p(rA), _p(rB), _stream_handle(stream),
-                                ctypes.byref(h))
+        code = lib().lbm_create(ctypes.byref(self.params), _p(mask), _p(rA), None if rB is None else _p(rB),
+                                _stream_handle(stream), ctypes.byref(h))
         check(code)
         self._h = h
 

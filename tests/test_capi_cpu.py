@@ -53,6 +53,10 @@ def _sim(**kw):
     (dict(rA=np.full((8, 8), -0.1)), "densities"),
     (dict(rB=np.full((8, 8), np.nan)), "densities"),
     (dict(diag_every=-1), "diag_every"),
+    (dict(model=2), "model"),
+    (dict(model=1, bc=2), "single-component"),
+    (dict(model=1, rho0=0.0), "single-component"),
+    (dict(model=0, rB=None), "rhoB0"),
 ])
 def test_invalid_problems_rejected_on_host(kw, needle):
     import paper_2009_12584_amd as M

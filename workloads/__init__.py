@@ -42,10 +42,15 @@ class Case:
     rhoA0: np.ndarray | None = field(default=None, repr=False)
     rhoB0: np.ndarray | None = field(default=None, repr=False)
     mask_user: np.ndarray | None = field(default=None, repr=False)
+    model: int = 0              # 0 = two components, 1 = single-component multiphase
+    rho0: float = 1.0           # single-component pseudopotential density scale
 
     def params(self) -> dict:
-        return dict(tau=self.tau, G=self.G, bc=self.bc, Gw=self.Gw, chiA=self.chiA,
-                    chiB=self.chiB, avg=self.avg, periodic=self.periodic)
+        d = dict(tau=self.tau, G=self.G, bc=self.bc, Gw=self.Gw, chiA=self.chiA,
+                 chiB=self.chiB, avg=self.avg, periodic=self.periodic)
+        if self.model:
+            d.update(model=self.model, rho0=self.rho0)
+        return d
 
 
 def rows_mask(nx: int, ny: int, rows) -> np.ndarray:
@@ -105,6 +110,25 @@ def plane_drop(nx, ny, beta_deg, R0, bc, *, G=0.9, tau=1.0, rho_out=0.03, Gw=Non
     return Case(name or "plane-%dx%d-b%g-%s" % (nx, ny, beta_deg, BC_NAMES[bc]), nx, ny, periodic=0,
                 tau=tau, G=G, bc=bc, Gw=Gw, chiA=chi[0], chiB=chi[1], steps=steps,
                 geometry=("plane", beta, float(R0)), rhoA0=rA, rhoB0=rB)
+
+
+# Single-component multiphase Shan-Chen (psi = 1 - exp(-rho)) at G = -5: the
+# flat-interface coexistence densities of that model (vapour, liquid).
+SC1_G = -5.0
+SC1_RHO_V, SC1_RHO_L = 0.1194, 1.8884
+
+
+def sc1_plane_drop(nx, ny, beta_deg, R0, bc, *, Gw=None, G=SC1_G, tau=1.0, steps=100, name=None) -> Case:
+    """Liquid drop in its vapour, tangent to a plane inclined by beta (Section 3.1
+    set-up) in the single-component model; Martys-Chen G_w = -3 and LLKC
+    G_w = -5 give contact angles near 70 degrees on a flat wall."""
+    beta = math.radians(beta_deg)
+    rA, _ = sharp_drop(nx, ny, nx / 2.0, ny / 2.0, R0, SC1_RHO_L, SC1_RHO_V)
+    if Gw is None:
+        Gw = {MC: -3.0, LLKC: -5.0}[bc]
+    return Case(name or "sc1-plane-%dx%d-b%g-%s" % (nx, ny, beta_deg, BC_NAMES[bc]), nx, ny, periodic=0,
+                tau=tau, G=G, bc=bc, Gw=Gw, steps=steps, geometry=("plane", beta, float(R0)), rhoA0=rA,
+                rhoB0=None, model=1)
 
 
 def config2() -> Case:
