@@ -200,6 +200,108 @@ def coalescence_study(R0s, Rs=None, *, samples=400, t_end=4.0, b_lo=3.0, storage
     return out
 
 
+def plane_position(rho, mask, beta, level):
+    """Centre of the drop fluid (rho above level, fluid nodes) projected on the
+    plane direction (cos beta, sin beta)."""
+    ny, nx = rho.shape
+    yy, xx = np.mgrid[0:ny, 0:nx]
+    w = np.where((np.asarray(mask) == 0) & (rho > level), rho, 0.0)
+    s = w.sum()
+    return float(((w * xx).sum() * math.cos(beta) + (w * yy).sum() * math.sin(beta)) / s)
+
+
+def sliding_study(betas, rules, *, n=400, R0=18.0, steps=6000, every=250, fit_from=2000, log=None):
+    """Drop velocity along off-grid planes (Section 3.1, Fig. 2): drops of
+    radius R0 in an n x n box at G = 3, rho 1.0/0.055, for each wetting rule
+    and inclination, run as one batch; u_d is the least-squares slope of the
+    along-plane drop position over fit_from <= t <= steps.  rules: list of
+    (name, bc, params dict) for the two-component model; the single-component
+    model runs as separate simulations, rules named 'sc1-...'."""
+    import workloads as W
+
+    from .sim import Simulation
+
+    rows = []
+    two = [(nm, bc, kw) for nm, bc, kw in rules if not nm.startswith("sc1")]
+    one = [(nm, bc, kw) for nm, bc, kw in rules if nm.startswith("sc1")]
+    t_s = np.arange(every, steps + 1, every, dtype=np.float64)
+    sel = t_s >= fit_from
+    if two:
+        keys, cases = [], []
+        for nm, bc, kw in two:
+            for beta in betas:
+                c = W.plane_drop(n, n, beta, R0, bc, G=3.0, rho_out=0.055, **kw)
+                m = mask_plane(n, n, c.geometry[1], c.geometry[2])
+                keys.append((nm, beta, c.geometry[1], m))
+                cases.append((m, c.rhoA0, c.rhoB0, c.params()))
+        b = Batch(cases)
+        pos = np.zeros((len(keys), len(t_s)))
+        try:
+            for k in range(len(t_s)):
+                b.step(every)
+                for i, (nm, beta, brad, m) in enumerate(keys):
+                    pos[i, k] = plane_position(b.fields(i, (True, False, False, False))[0], m, brad, 0.5)
+                if log and (k + 1) % 8 == 0:
+                    log("sliding: two-component step %d of %d" % ((k + 1) * every, steps))
+        finally:
+            b.close()
+        for i, (nm, beta, brad, m) in enumerate(keys):
+            ud = float(np.polyfit(t_s[sel], pos[i, sel], 1)[0])
+            rows.append(dict(rule=nm, beta=beta, u_d=ud, pos=pos[i].tolist()))
+    for nm, bc, kw in one:
+        for beta in betas:
+            c = W.sc1_plane_drop(n, n, beta, R0, bc, **kw)
+            m = mask_plane(n, n, c.geometry[1], c.geometry[2])
+            s = Simulation(m, c.rhoA0, None, **c.params())
+            p = []
+            try:
+                for k in range(len(t_s)):
+                    s.step(every)
+                    p.append(plane_position(s.fields()[0], m, c.geometry[1], 0.5 * (W.SC1_RHO_L + W.SC1_RHO_V)))
+            finally:
+                s.close()
+            p = np.array(p)
+            rows.append(dict(rule=nm, beta=beta, u_d=float(np.polyfit(t_s[sel], p[sel], 1)[0]), pos=p.tolist()))
+        if log:
+            log("sliding: %s done" % nm)
+    return rows
+
+
+def main_sliding(argv):
+    ap = argparse.ArgumentParser(description="Drop velocity along off-grid planes (Section 3.1).")
+    ap.add_argument("--beta", default="0,10,20,30,40,45,50,60,70,80")
+    ap.add_argument("--n", type=int, default=400)
+    ap.add_argument("--R0", type=float, default=18.0)
+    ap.add_argument("--steps", type=int, default=6000)
+    ap.add_argument("--every", type=int, default=250)
+    ap.add_argument("--fit-from", type=int, default=2000)
+    ap.add_argument("--rules", default="", help="comma list of rule-name prefixes to run (default: all)")
+    ap.add_argument("--out", default=None)
+    a = ap.parse_args(argv)
+    import workloads as W
+
+    rules = [("martys-chen Gw=-0.2", W.MC, dict(Gw=-0.2)), ("martys-chen Gw=0", W.MC, dict(Gw=0.0)),
+             ("llkc Gw=-0.5", W.LLKC, dict(Gw=-0.5)),
+             ("improved xi=-0.2", W.IMPROVED, dict(chi=xi_to_chi(-0.2))),
+             ("sc1-martys-chen Gw=-3", W.MC, dict(Gw=-3.0)), ("sc1-llkc Gw=-5", W.LLKC, dict(Gw=-5.0))]
+    if a.rules:
+        pre = [v.strip() for v in a.rules.split(",")]
+        rules = [r for r in rules if any(r[0].startswith(p) for p in pre)]
+    betas = [float(v) for v in a.beta.split(",")]
+    rows = sliding_study(betas, rules, n=a.n, R0=a.R0, steps=a.steps, every=a.every, fit_from=a.fit_from,
+                         log=lambda m: print(m, flush=True))
+    if a.out:
+        with open(a.out, "w") as f:
+            json.dump(dict(args=vars(a), rows=rows), f)
+    names = [r[0] for r in rules]
+    print("| rule | " + " | ".join("beta=%g" % b for b in betas) + " |")
+    print("|---|" + "---|" * len(betas))
+    for nm in names:
+        v = {r["beta"]: r["u_d"] for r in rows if r["rule"] == nm}
+        print("| %s | " % nm + " | ".join("%.1e" % v[b] for b in betas) + " |")
+    return 0
+
+
 def main_coalescence(argv):
     ap = argparse.ArgumentParser(description="Bridge growth of coalescing drops versus resolution (Section 4).")
     ap.add_argument("--R0", default="12.5,25,50,100,200,400")
@@ -228,6 +330,8 @@ def main(argv=None):
     argv = sys.argv[1:] if argv is None else list(argv)
     if argv and argv[0] == "coalescence":
         return main_coalescence(argv[1:])
+    if argv and argv[0] == "sliding":
+        return main_sliding(argv[1:])
     if argv and argv[0] == "angles":
         argv = argv[1:]
     ap = argparse.ArgumentParser(description="Contact angle versus xi and plane inclination (improved scheme).")

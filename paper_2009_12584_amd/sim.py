@@ -189,10 +189,11 @@ class Batch:
     def step(self, n=1):
         check(lib().lbm_batch_step(self._h, int(n)))
 
-    def fields(self, idx):
+    def fields(self, idx, which=(True, True, True, True)):
+        """(rhoA, rhoB, ux, uy) of instance idx; entries not in `which` are None."""
         ny, nx = self.shapes[idx]
-        a = [np.zeros((ny, nx)) for _ in range(4)]
-        check(lib().lbm_batch_fields(self._h, int(idx), *[_p(x) for x in a]))
+        a = [np.zeros((ny, nx)) if w else None for w in which]
+        check(lib().lbm_batch_fields(self._h, int(idx), *[_p(x) if x is not None else None for x in a]))
         return tuple(a)
 
     def diag(self, idx):
