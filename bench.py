@@ -17,6 +17,8 @@ Also reported (same JSON line):
   served                  Poisson request stream through the resident pool
                           with continuous batching: p50/p99 latency, MLUPS,
                           against running the same requests one by one
+  single_component        the single-component multiphase model on the same
+                          5600 x 4000 grid (9 populations per node)
   cpu_baseline            the FP64 oracle on the host cores, bounded sample
 
 Prints ONE JSON line.
@@ -35,8 +37,9 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_FLUID = {"f32": 144, "f16": 72}   # 18 populations read + written per fluid node
+BYTES_PER_FLUID_SC1 = {"f32": 72, "f16": 36}  # 9 populations read + written, single-component model
 BYTES_PER_NODE_FLAGS = 2                     # one 16-bit node word per node
-KERNEL_SOURCES = ["lbm_device.hpp", "lbm_common.hpp", "lbm_single.hip", "lbm_batch.hip"]
+KERNEL_SOURCES = ["lbm_device.hpp", "lbm_sc1.hpp", "lbm_common.hpp", "lbm_single.hip", "lbm_batch.hip"]
 
 
 def alg_bytes(fluid, nodes, storage="f32"):
@@ -240,7 +243,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20000)
     ap.add_argument("--warmup", type=int, default=500)
     ap.add_argument("--large-steps", type=int, default=200)
-    ap.add_argument("--rows", default="headline,large,batched,served,cpu",
+    ap.add_argument("--rows", default="headline,large,sc1,batched,served,cpu",
                     help="comma list of rows to run (profiling runs select one)")
     ap.add_argument("--served-requests", type=int, default=40)
     args = ap.parse_args()
@@ -295,6 +298,24 @@ def main():
         out["roofline_out_of_cache"] = dict(
             workload="5600x4000 fully periodic G=3 mixture (Martys-Chen path), 3.2 GB ping-pong in FP32",
             bound="hbm", peak=HBM_PEAK_GBS, unit="GB/s", **lrows["f32"], f16=lrows["f16"])
+
+    if "sc1" in rows:
+        sc = W.sc1_roofline_case()
+        sfl = sc.nx * sc.ny
+        srows = {}
+        for storage in ("f32", "f16"):
+            rs = run_single(M, torch, sc, sc.mask_user, args.large_steps, 10, storage=storage, tile_y=8,
+                            graph_steps=20, diag_every=20)
+            sms = rs["ms"] / rs["steps"]
+            sb = BYTES_PER_FLUID_SC1[storage] * sfl + BYTES_PER_NODE_FLAGS * sfl
+            kn = "k_step_sc1<%s, 8, 0, 0, false>" % ("float" if storage == "f32" else "__half")
+            srows[storage] = {"achieved": round(sb / (sms * 1e-3) / 1e9, 1),
+                              "frac": round(sb / (sms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "ms_per_step": round(sms, 4),
+                              "fluid_mlups": round(sfl * rs["steps"] / (rs["ms"] * 1e-3) / 1e6, 1), "kernel": kn,
+                              "bytes_per_launch": sb, "traffic": measured_traffic(kn, "k_step_sc1_periodic_5600x4000.md")}
+        out["single_component"] = dict(
+            workload="5600x4000 fully periodic single-component Shan-Chen at G=-5 (liquid-vapour separation), "
+                     "Martys-Chen path", bound="hbm", peak=HBM_PEAK_GBS, unit="GB/s", **srows["f32"], f16=srows["f16"])
 
     if "batched" in rows:
         out["batched"] = batched_rows(M, torch, W)

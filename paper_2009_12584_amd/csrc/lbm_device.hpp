@@ -107,6 +107,12 @@ template <typename S> __device__ __forceinline__ S *at(S *base, uint32_t byte_of
 
 // Exact sum of the 9 deviations of one component (a double holds the sum of
 // nine floats of this range without rounding), in a fixed order.
+__device__ __forceinline__ float fsum9(const float d[9]) {
+    float s = 0.f;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) s += d[i];
+    return s;
+}
 __device__ __forceinline__ double dsum9(const float d[9]) {
     double s = 0.0;
 #pragma unroll
@@ -343,8 +349,8 @@ __device__ __forceinline__ void frame_pass(const Inst &I, Smem<TY> &sm, const ty
             const Around a = around<S>(I, gx, gy, edge);
             float dA[9], dB[9];
             pull9<S>(fin, pb, a, w, dA, dB);
-            ra = (float)((double)rref[0] + dsum9(dA) * (double)(1.f / Store<S>::SC));
-            rb = (float)((double)rref[1] + dsum9(dB) * (double)(1.f / Store<S>::SC));
+            ra = rref[0] + fsum9(dA) * (1.f / Store<S>::SC);
+            rb = rref[1] + fsum9(dB) * (1.f / Store<S>::SC);
         }
         sm.rho[0][rho_idx<TY>(hx, hy)] = ra;
         sm.rho[1][rho_idx<TY>(hx, hy)] = rb;
@@ -414,8 +420,8 @@ __device__ void process_tile(const Inst &I, int tile_x, int tile_y, int parity, 
         sd[r][0] = dsum9(d[r][0]);
         sd[r][1] = dsum9(d[r][1]);
         const bool fl = !(w[r] & NW_SOLID);
-        sm.rho[0][rho_idx<TY>(lx, ly)] = fl ? (float)((double)rref[0] + sd[r][0] * (double)(1.f / SC)) : 0.f;
-        sm.rho[1][rho_idx<TY>(lx, ly)] = fl ? (float)((double)rref[1] + sd[r][1] * (double)(1.f / SC)) : 0.f;
+        sm.rho[0][rho_idx<TY>(lx, ly)] = fl ? rref[0] + fsum9(d[r][0]) * (1.f / SC) : 0.f;
+        sm.rho[1][rho_idx<TY>(lx, ly)] = fl ? rref[1] + fsum9(d[r][1]) * (1.f / SC) : 0.f;
     }
     __syncthreads();
 

@@ -223,6 +223,17 @@ def config5_requests(n: int = 400, seed: int = 12345, rate: float = 200.0):
     return reqs
 
 
+def sc1_roofline_case(nx=5600, ny=4000, seed=7) -> Case:
+    """The same grid for the single-component model: a seeded near-uniform
+    density inside the spinodal region at G = -5 (it separates into liquid
+    and vapour), fully periodic."""
+    rng = np.random.default_rng(seed)
+    rA = 0.7 + 0.02 * (2.0 * rng.random((ny, nx)) - 1.0)
+    return Case("r-sc1-periodic-%dx%d" % (nx, ny), nx, ny, periodic=3, tau=1.0, G=SC1_G, bc=MC, Gw=0.0,
+                steps=1000, geometry=("none",), rhoA0=rA, rhoB0=None, model=1,
+                mask_user=np.zeros((ny, nx), np.uint8))
+
+
 def roofline_case(nx=5600, ny=4000, seed=7, G=3.0) -> Case:
     """The paper's largest grid (Section 4 convergence study) as a fully periodic mixture."""
     rA, rB = random_mixture(nx, ny, seed)
