@@ -407,6 +407,21 @@ __device__ void process_tile(const Inst &I, int tile_x, int tile_y, int parity, 
         }
     }
 
+    // fluid D2Q25 masks of the tile + 1 positions this thread treats in Eq. 7,
+    // in flight with the pulls (indices wrap into the grid; a value is used
+    // only at an interface solid)
+    constexpr int NV = (Smem<TY>::VW * Smem<TY>::VH + threads_for(TY) - 1) / threads_for(TY);
+    uint32_t m25v[NV];
+    if (BC == BC_IMPROVED && need_rt) {
+#pragma unroll
+        for (int s = 0; s < NV; ++s) {
+            const int k = tid + s * threads_for(TY);
+            const int vx = k % Smem<TY>::VW - 1, vy = k / Smem<TY>::VW - 1;
+            const int gx = wrap(tx0 + vx, I.nx, true), gy = wrap(ty0 + vy, I.ny, true);
+            m25v[s] = k < Smem<TY>::VW * Smem<TY>::VH ? I.m25[(size_t)gy * I.pitch + gx] : 0u;
+        }
+    }
+
     // ---- phase 1b: halo frame
     if (need_rt)
         frame_pass<S, TY, HMAX>(I, sm, fin, pb, tx0, ty0, edge, rref);
@@ -428,13 +443,15 @@ __device__ void process_tile(const Inst &I, int tile_x, int tile_y, int parity, 
     // ---- phase 2: virtual solid density of Eq. 7 on interface solids in tile + 1
     if (BC == BC_IMPROVED && need_rt) {
         const float chi[2] = {I.chiA, I.chiB};
-        for (int k = tid; k < Smem<TY>::VW * Smem<TY>::VH; k += threads_for(TY)) {
+#pragma unroll
+        for (int s = 0; s < NV; ++s) {
+            const int k = tid + s * threads_for(TY);
+            if (k >= Smem<TY>::VW * Smem<TY>::VH) continue;
             const int vx = k % Smem<TY>::VW - 1, vy = k / Smem<TY>::VW - 1;
             float ta = 0.f, tb = 0.f;
             if (sm.lf[k] & LF_IFACE) {
                 // interface solids lie inside the domain or across a periodic border
-                const int gx = wrap(tx0 + vx, I.nx, true), gy = wrap(ty0 + vy, I.ny, true);
-                const uint32_t m = I.m25[(size_t)gy * I.pitch + gx];
+                const uint32_t m = m25v[s];
                 // every position of the 5 x 5 block is in LDS, solids and
                 // out-of-domain positions as 0, so the numerator needs no mask:
                 // all 48 reads issue back to back; the mask enters only the
