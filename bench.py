@@ -39,7 +39,8 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_FLUID = {"f32": 144, "f16": 72}   # 18 populations read + written per fluid node
 BYTES_PER_FLUID_SC1 = {"f32": 72, "f16": 36}  # 9 populations read + written, single-component model
 BYTES_PER_NODE_FLAGS = 2                     # one 16-bit node word per node
-KERNEL_SOURCES = ["lbm_device.hpp", "lbm_sc1.hpp", "lbm_common.hpp", "lbm_single.hip", "lbm_batch.hip"]
+KERNEL_SOURCES = ["lbm_device.hpp", "lbm_pair.hpp", "lbm_sc1.hpp", "lbm_common.hpp", "lbm_single.hip",
+                  "lbm_batch.hip"]
 
 
 def alg_bytes(fluid, nodes, storage="f32"):
@@ -110,10 +111,11 @@ def copy_probe(torch, nbytes=1 << 31, reps=5):
             "frac_of_peak": round(2 * nbytes / ms / 1e6 / HBM_PEAK_GBS, 4)}
 
 
-def run_single(M, torch, case, mask, steps, warmup, *, storage="f32", tile_y=0, graph_steps=100, diag_every=100):
+def run_single(M, torch, case, mask, steps, warmup, *, storage="f32", tile_y=0, lanes=0, graph_steps=100,
+               diag_every=100):
     stream = torch.cuda.Stream()
     sim = M.Simulation(mask, case.rhoA0, case.rhoB0, stream=stream, storage=storage, graph_steps=graph_steps,
-                       diag_every=diag_every, drift_tol=1e-3, tile_y=tile_y, **case.params())
+                       diag_every=diag_every, drift_tol=1e-3, tile_y=tile_y, lanes=lanes, **case.params())
     sim.step(warmup)
     if graph_steps:
         steps = max(graph_steps, steps // graph_steps * graph_steps)  # whole graph replays only
@@ -125,7 +127,7 @@ def run_single(M, torch, case, mask, steps, warmup, *, storage="f32", tile_y=0, 
 
 
 def batched_rows(M, torch, W, steps=1000):
-    from paper_2009_12584_amd.autotune import tile_y_for_batch
+    from paper_2009_12584_amd.autotune import launch_config_for_batch
 
     cases = W.config4_instances(64)
     masks = [M.mask_plane(c.nx, c.ny, c.geometry[1], c.geometry[2]) for c in cases]
@@ -148,13 +150,14 @@ def batched_rows(M, torch, W, steps=1000):
         s.close()
     out["plain_loop_fluid_mlups"] = round(fluid * steps / (plain_ms * 1e-3) / 1e6, 1)
     for storage in ("f32", "f16"):
-        ty = tile_y_for_batch(items, storage=storage, stream=stream)
-        b = M.Batch(items, storage=storage, graph_steps=100, tile_y=ty, stream=stream)
+        cfg = launch_config_for_batch(items, storage=storage, stream=stream)
+        ty = cfg["tile_y"]
+        b = M.Batch(items, storage=storage, graph_steps=100, tile_y=ty, lanes=cfg["lanes"], stream=stream)
         b.step(100)
         with Timer(torch, stream) as t:
             b.step(steps)
         mlups = fluid * steps / (t.ms * 1e-3) / 1e6
-        row = {"fluid_mlups": round(mlups, 1), "ms_per_step": t.ms / steps, "tile_y": ty,
+        row = {"fluid_mlups": round(mlups, 1), "ms_per_step": t.ms / steps, "tile_y": ty, "lanes": cfg["lanes"],
                "speedup_vs_plain_loop": round(mlups / out["plain_loop_fluid_mlups"], 2),
                "hbm_gbs_algorithmic": round(alg_bytes(fluid, 0, storage) / (t.ms / steps * 1e-3) / 1e9, 1)}
         if storage == "f16":
@@ -199,13 +202,14 @@ def served_rows(M, torch, W, n_req=40, chunk=200):
     return s
 
 
-def headline_row(M, torch, case, mask, fluid, nodes, args, probe, tile_y_for):
-    ty = tile_y_for(mask, case.rhoA0, case.rhoB0, **case.params())
-    r = run_single(M, torch, case, mask, args.steps, args.warmup, tile_y=ty)
+def headline_row(M, torch, case, mask, fluid, nodes, args, probe, launch_config_for):
+    cfg = launch_config_for(mask, case.rhoA0, case.rhoB0, **case.params())
+    ty, lanes = cfg["tile_y"], cfg["lanes"]
+    r = run_single(M, torch, case, mask, args.steps, args.warmup, tile_y=ty, lanes=lanes)
     K = r["steps"]
     ms_per_step = r["ms"] / K
     mlups = fluid * K / (r["ms"] * 1e-3) / 1e6
-    kname = "k_step<float, %d, 2, 0, false>" % ty
+    kname = "%s<float, %d, 2, 0, false>" % ("k_step_ls" if lanes == 2 else "k_step", ty)
     achieved = alg_bytes(fluid, nodes) / (ms_per_step * 1e-3) / 1e9
     d = r["diag"]
     return {
@@ -224,7 +228,7 @@ def headline_row(M, torch, case, mask, fluid, nodes, args, probe, tile_y_for):
         "config": {"workload": "512x256 D2Q9 two-component, 30-degree stair wall, drop R=40, improved virtual "
                                "solid density (D2Q25), tau=1, G=0.9, rho 1.0/0.03, FP32 deviations",
                    "nx": case.nx, "ny": case.ny, "fluid_nodes": fluid, "total_nodes": nodes,
-                   "total_mlups": round(nodes * K / (r["ms"] * 1e-3) / 1e6, 1), "tile_y": ty,
+                   "total_mlups": round(nodes * K / (r["ms"] * 1e-3) / 1e6, 1), "tile_y": ty, "lanes": lanes,
                    "graph_steps": 100, "diag_every": 100,
                    "mass_drift": max(abs(d["mass"][k] - d["mass0"][k]) / d["mass0"][k] for k in range(2))},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -257,7 +261,7 @@ def main():
 
     import workloads as W
     import paper_2009_12584_amd as M
-    from paper_2009_12584_amd.autotune import tile_y_for
+    from paper_2009_12584_amd.autotune import launch_config_for
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
@@ -271,7 +275,7 @@ def main():
     fluid = int((mask == 0).sum())
     nodes = case.nx * case.ny
     if "headline" in rows:
-        out.update(headline_row(M, torch, case, mask, fluid, nodes, args, probe, tile_y_for))
+        out.update(headline_row(M, torch, case, mask, fluid, nodes, args, probe, launch_config_for))
     else:
         out.update({"metric": "fluid MLUPS, two-component D2Q9 wetting LBM step", "value": None, "unit": "MLUPS",
                     "n_gpus": 1, "steps": 0, "warmup": 0, "ms_per_step": None, "higher_is_better": True,

@@ -101,6 +101,8 @@ typedef struct {
     int32_t tile_y;      /* rows per tile: 0 = default (8), else 4, 8, 16 or 32 (512-thread workgroups) */
     int32_t model;       /* lbm_model */
     double psi_rho0;     /* single-component model: the density scale of psi */
+    int32_t lanes;       /* two-component step: 0 or 1 = one lane per node, 2 = one lane per
+                            node and component (bit-identical results; faster on small grids) */
 } lbm_params;
 
 /* Diagnostics, reduced in FP64 over fluid nodes at the handle's current time. */
@@ -118,7 +120,7 @@ typedef struct lbm_handle lbm_handle;
 
 /* Fills *p with defaults: tau 1, G 0.9, Martys-Chen with G_w 0, chi 1, D2Q25,
  * FP32 storage, rho_ref NaN, diag_every 0, drift_tol 0, graph_steps 0,
- * two-component model, psi_rho0 1. */
+ * two-component model, psi_rho0 1, lanes 0. */
 void lbm_params_default(lbm_params *p);
 
 /* Creates one simulation.  mask: nx*ny bytes, non-zero = solid (phi of

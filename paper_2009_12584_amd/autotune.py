@@ -1,11 +1,14 @@
-"""Tile-shape autotuner for the step kernels.
+"""Launch-shape autotuner for the step kernels.
 
-A tile is 64 nodes wide (one wavefront per row) and TY rows tall, TY in
-{4, 8, 16}.  Small grids want small tiles (more workgroups to cover the 256
-compute units); large grids want taller tiles (a smaller density halo per
-node).  The tuner times a few steps of the caller's own problem for each
-candidate on the device and keeps the fastest, cached per (storage, BC,
-grid-size bucket) for the life of the process and in a JSON file.
+A tile is 64 nodes wide (one wavefront row) and TY rows tall, TY in
+{4, 8, 16, 32}; the two-component step runs with one lane per node or one
+lane per node and component (bit-identical results).  Small grids want small
+tiles and two lanes (more wavefronts to cover the 256 compute units and
+shorter per-lane work); large grids want taller tiles and one lane (a
+smaller density halo per node, fewer instructions per byte).  The tuner
+times a few steps of the caller's own problem for each candidate on the
+device and keeps the fastest, cached per (storage, BC, grid-size bucket) for
+the life of the process and in a JSON file.
 """
 from __future__ import annotations
 
@@ -16,8 +19,9 @@ import time
 
 from .sim import Batch, Simulation
 
-CANDIDATES = (4, 8, 16, 32)
-_CACHE_PATH = os.path.join(os.path.expanduser("~"), ".cache", "mclbm", "autotune.json")
+# (tile rows, lanes per node)
+CANDIDATES = ((4, 1), (8, 1), (16, 1), (32, 1), (4, 2), (8, 2), (16, 2))
+_CACHE_PATH = os.path.join(os.path.expanduser("~"), ".cache", "mclbm", "autotune-v2.json")
 _cache = None
 
 
@@ -59,38 +63,43 @@ def _time(step, sync, steps):
     return time.perf_counter() - t0
 
 
-def tile_y_for(mask, rhoA0, rhoB0, *, storage="f32", steps=None, stream=None, refresh=False, **params):
-    """Best tile height for one simulation of this problem (timed on the device)."""
+def launch_config_for(mask, rhoA0, rhoB0, *, storage="f32", steps=None, stream=None, refresh=False, **params):
+    """Fastest {"tile_y", "lanes"} for one simulation of this problem (timed on the device)."""
     import torch
 
     ny, nx = mask.shape
     key = key_of(nx, ny, params.get("bc", 0), storage)
     cache = _load()
     if key in cache and not refresh:
-        return int(cache[key])
+        return dict(cache[key])
     nodes = nx * ny
     steps = steps or max(20, min(400, int(4e8 / max(nodes, 1))))
     best, best_t = CANDIDATES[0], float("inf")
-    for ty in CANDIDATES:
-        sim = Simulation(mask, rhoA0, rhoB0, stream=stream, storage=storage, tile_y=ty, **params)
+    for ty, lanes in CANDIDATES:
+        sim = Simulation(mask, rhoA0, rhoB0, stream=stream, storage=storage, tile_y=ty, lanes=lanes, **params)
         t = _time(sim.step, torch.cuda.synchronize, steps)
         sim.close()
         if t < best_t:
-            best, best_t = ty, t
-    cache[key] = best
+            best, best_t = (ty, lanes), t
+    cache[key] = dict(tile_y=best[0], lanes=best[1])
     _save()
-    return best
+    return dict(cache[key])
 
 
-def tile_y_for_batch(items, *, storage="f32", steps=50, stream=None):
-    """Best tile height for a batch (one height for all its instances)."""
+def tile_y_for(mask, rhoA0, rhoB0, **kw):
+    """Tile rows of launch_config_for."""
+    return launch_config_for(mask, rhoA0, rhoB0, **kw)["tile_y"]
+
+
+def launch_config_for_batch(items, *, storage="f32", steps=50, stream=None):
+    """Fastest {"tile_y", "lanes"} for a batch (one shape for all its instances)."""
     import torch
 
     best, best_t = CANDIDATES[0], float("inf")
-    for ty in CANDIDATES:
-        b = Batch(items, storage=storage, tile_y=ty, stream=stream)
+    for ty, lanes in CANDIDATES:
+        b = Batch(items, storage=storage, tile_y=ty, lanes=lanes, stream=stream)
         t = _time(b.step, torch.cuda.synchronize, steps)
         b.close()
         if t < best_t:
-            best, best_t = ty, t
-    return best
+            best, best_t = (ty, lanes), t
+    return dict(tile_y=best[0], lanes=best[1])

@@ -38,7 +38,7 @@ class LbmParams(ctypes.Structure):
         ("G_w", ctypes.c_double), ("chi", ctypes.c_double * 2), ("avg", ctypes.c_int32),
         ("storage", ctypes.c_int32), ("rho_ref", ctypes.c_double * 2), ("diag_every", ctypes.c_int32),
         ("drift_tol", ctypes.c_double), ("graph_steps", ctypes.c_int32), ("tile_y", ctypes.c_int32),
-        ("model", ctypes.c_int32), ("psi_rho0", ctypes.c_double),
+        ("model", ctypes.c_int32), ("psi_rho0", ctypes.c_double), ("lanes", ctypes.c_int32),
     ]
 
 
@@ -147,7 +147,7 @@ def check(code, handle=None):
 
 def make_params(nx, ny, *, tau=1.0, G=0.9, bc=BC_MARTYS_CHEN, Gw=0.0, chiA=1.0, chiB=1.0, avg=AVG_D2Q25,
                 periodic=0, storage=STORE_F32, rho_ref=None, diag_every=0, drift_tol=0.0, graph_steps=0,
-                tile_y=0, model=MODEL_TWO, rho0=1.0) -> LbmParams:
+                tile_y=0, model=MODEL_TWO, rho0=1.0, lanes=0) -> LbmParams:
     p = LbmParams()
     lib().lbm_params_default(ctypes.byref(p))
     p.nx, p.ny, p.periodic = int(nx), int(ny), int(periodic)
@@ -159,7 +159,7 @@ def make_params(nx, ny, *, tau=1.0, G=0.9, bc=BC_MARTYS_CHEN, Gw=0.0, chiA=1.0, 
     p.rho_ref[0], p.rho_ref[1] = float(rr[0]), float(rr[1])
     p.diag_every, p.drift_tol = int(diag_every), float(drift_tol)
     p.graph_steps, p.tile_y = int(graph_steps), int(tile_y)
-    p.model, p.psi_rho0 = int(model), float(rho0)
+    p.model, p.psi_rho0, p.lanes = int(model), float(rho0), int(lanes)
     return p
 
 

@@ -24,8 +24,9 @@ using namespace mclbm;
 namespace {
 
 template <typename S, int TY, int BC>
-__global__ __launch_bounds__(threads_for(TY)) void k_batch_step(const Inst *__restrict__ insts, const int2 *__restrict__ tiles,
-                                                   int launch_parity, long long L) {
+__global__ __launch_bounds__(threads_for(TY)) void k_batch_step(const Inst *__restrict__ insts,
+                                                                const int2 *__restrict__ tiles, int launch_parity,
+                                                                long long L) {
     __shared__ Smem<TY> sm;
     const int t = xcd_tile(blockIdx.x, gridDim.x);
     const int2 e = tiles[t];
@@ -36,6 +37,23 @@ __global__ __launch_bounds__(threads_for(TY)) void k_batch_step(const Inst *__re
     tile_coords(e.y, I.tiles_x, I.tiles_y, I.tg, tx, ty);
     DiagAcc acc;
     process_tile<S, TY, BC, MODE_STEP, false>(I, tx, ty, parity, sm, acc, Fields{});
+}
+
+// The same with two lanes per node (bit-identical results).
+template <typename S, int TY, int BC>
+__global__ __launch_bounds__(ls_threads(TY)) void k_batch_step_ls(const Inst *__restrict__ insts,
+                                                                  const int2 *__restrict__ tiles, int launch_parity,
+                                                                  long long L) {
+    __shared__ SmemLS<TY> sm;
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    const int2 e = tiles[t];
+    const Inst &I = insts[e.x];
+    if (L >= I.t_end) return;
+    const int parity = (I.parity0 ^ launch_parity) & 1;
+    int tx, ty;
+    tile_coords(e.y, I.tiles_x, I.tiles_y, I.tg, tx, ty);
+    DiagAcc acc;
+    process_tile_ls<S, TY, BC, MODE_STEP, false>(I, tx, ty, parity, sm, acc, Fields{});
 }
 
 // Tile lists are grouped by boundary rule so that each launch runs a kernel
@@ -64,27 +82,34 @@ TileLists build_tiles(int n, InstOf inst_of, std::vector<int2> &out) {
     return T;
 }
 
-template <typename S, int TY>
-void launch_batch_ty(hipStream_t s, const TileLists &T, const Inst *insts, const int2 *tiles, int lp, long long L) {
-    const dim3 b(threads_for(TY));
-    if (T.cnt[0]) hipLaunchKernelGGL((k_batch_step<S, TY, BC_MC>), dim3(T.cnt[0]), b, 0, s, insts, tiles + T.off[0], lp, L);
-    if (T.cnt[1]) hipLaunchKernelGGL((k_batch_step<S, TY, BC_LLKC>), dim3(T.cnt[1]), b, 0, s, insts, tiles + T.off[1], lp, L);
-    if (T.cnt[2])
-        hipLaunchKernelGGL((k_batch_step<S, TY, BC_IMPROVED>), dim3(T.cnt[2]), b, 0, s, insts, tiles + T.off[2], lp, L);
+template <typename S, int TY, int BC>
+void launch_batch_bc(hipStream_t s, int lanes, int n, const Inst *insts, const int2 *tiles, int lp, long long L) {
+    if (lanes == 2)
+        hipLaunchKernelGGL((k_batch_step_ls<S, TY, BC>), dim3(n), dim3(ls_threads(TY)), 0, s, insts, tiles, lp, L);
+    else
+        hipLaunchKernelGGL((k_batch_step<S, TY, BC>), dim3(n), dim3(threads_for(TY)), 0, s, insts, tiles, lp, L);
 }
 
-void launch_batch(int storage, int ty, hipStream_t s, const TileLists &T, const Inst *insts, const int2 *tiles, int lp,
-                  long long L) {
+template <typename S, int TY>
+void launch_batch_ty(hipStream_t s, int lanes, const TileLists &T, const Inst *insts, const int2 *tiles, int lp,
+                     long long L) {
+    if (T.cnt[0]) launch_batch_bc<S, TY, BC_MC>(s, lanes, T.cnt[0], insts, tiles + T.off[0], lp, L);
+    if (T.cnt[1]) launch_batch_bc<S, TY, BC_LLKC>(s, lanes, T.cnt[1], insts, tiles + T.off[1], lp, L);
+    if (T.cnt[2]) launch_batch_bc<S, TY, BC_IMPROVED>(s, lanes, T.cnt[2], insts, tiles + T.off[2], lp, L);
+}
+
+void launch_batch(int storage, int ty, int lanes, hipStream_t s, const TileLists &T, const Inst *insts,
+                  const int2 *tiles, int lp, long long L) {
     if (storage == LBM_STORE_F16) {
-        if (ty == 4) launch_batch_ty<__half, 4>(s, T, insts, tiles, lp, L);
-        else if (ty == 16) launch_batch_ty<__half, 16>(s, T, insts, tiles, lp, L);
-        else if (ty == 32) launch_batch_ty<__half, 32>(s, T, insts, tiles, lp, L);
-        else launch_batch_ty<__half, 8>(s, T, insts, tiles, lp, L);
+        if (ty == 4) launch_batch_ty<__half, 4>(s, lanes, T, insts, tiles, lp, L);
+        else if (ty == 16) launch_batch_ty<__half, 16>(s, lanes, T, insts, tiles, lp, L);
+        else if (ty == 32) launch_batch_ty<__half, 32>(s, lanes, T, insts, tiles, lp, L);
+        else launch_batch_ty<__half, 8>(s, lanes, T, insts, tiles, lp, L);
     } else {
-        if (ty == 4) launch_batch_ty<float, 4>(s, T, insts, tiles, lp, L);
-        else if (ty == 16) launch_batch_ty<float, 16>(s, T, insts, tiles, lp, L);
-        else if (ty == 32) launch_batch_ty<float, 32>(s, T, insts, tiles, lp, L);
-        else launch_batch_ty<float, 8>(s, T, insts, tiles, lp, L);
+        if (ty == 4) launch_batch_ty<float, 4>(s, lanes, T, insts, tiles, lp, L);
+        else if (ty == 16) launch_batch_ty<float, 16>(s, lanes, T, insts, tiles, lp, L);
+        else if (ty == 32) launch_batch_ty<float, 32>(s, lanes, T, insts, tiles, lp, L);
+        else launch_batch_ty<float, 8>(s, lanes, T, insts, tiles, lp, L);
     }
 }
 
@@ -259,7 +284,7 @@ struct Staging {
 struct lbm_batch {
     hipStream_t stream = nullptr;
     bool own_stream = false;
-    int storage = 0, ty = 8;
+    int storage = 0, ty = 8, lanes = 1;
     std::vector<Prepared> inst;
     std::vector<char *> blocks;
     Inst *d_inst = nullptr;
@@ -303,14 +328,16 @@ int lbm_batch_create(int32_t n, const lbm_params *params, const uint8_t *const *
             set_err("instance %d: batches run the two-component model only", k);
             return LBM_EINVAL;
         }
-        if (params[k].storage != params[0].storage || default_ty(params[k]) != default_ty(params[0])) {
-            set_err("instance %d: every instance of a batch uses the same storage and tile rows", k);
+        if (params[k].storage != params[0].storage || default_ty(params[k]) != default_ty(params[0]) ||
+            lanes_of(params[k]) != lanes_of(params[0])) {
+            set_err("instance %d: every instance of a batch uses the same storage, tile rows and lanes", k);
             return LBM_EINVAL;
         }
     }
     lbm_batch *b = new lbm_batch();
     b->storage = params[0].storage;
     b->ty = default_ty(params[0]);
+    b->lanes = lanes_of(params[0]);
     b->stream = (hipStream_t)stream;
     auto bail = [&](int code) {
         batch_release(b);
@@ -375,7 +402,8 @@ int lbm_batch_create(int32_t n, const lbm_params *params, const uint8_t *const *
             set_err("graph capture failed");
             return bail(LBM_EDEVICE);
         }
-        for (int s = 0; s < K; ++s) launch_batch(b->storage, b->ty, b->stream, b->lists, b->d_inst, b->d_tiles, s & 1, 0);
+        for (int s = 0; s < K; ++s)
+            launch_batch(b->storage, b->ty, b->lanes, b->stream, b->lists, b->d_inst, b->d_tiles, s & 1, 0);
         if (hipStreamEndCapture(b->stream, &b->graph) != hipSuccess ||
             hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0) != hipSuccess) {
             set_err("graph instantiate failed");
@@ -396,7 +424,7 @@ int lbm_batch_step(lbm_batch *b, int64_t nsteps) {
             nsteps -= b->glen;
             continue;
         }
-        launch_batch(b->storage, b->ty, b->stream, b->lists, b->d_inst, b->d_tiles, (int)(b->t & 1), 0);
+        launch_batch(b->storage, b->ty, b->lanes, b->stream, b->lists, b->d_inst, b->d_tiles, (int)(b->t & 1), 0);
         b->t += 1;
         nsteps -= 1;
     }
@@ -712,7 +740,7 @@ int lbm_pool_advance(lbm_pool *P, int64_t chunk) {
         if (s.used && s.joined) last_end = std::max(last_end, s.P.I.t_end);
     const int64_t n = std::min(chunk, last_end - P->L);
     for (int64_t q = 0; q < n; ++q) {
-        launch_batch(P->storage, P->ty, P->stream, P->lists, P->d_inst, P->d_tiles, (int)(P->L & 1),
+        launch_batch(P->storage, P->ty, 1, P->stream, P->lists, P->d_inst, P->d_tiles, (int)(P->L & 1),
                      (long long)P->L);
         P->L += 1;
     }

@@ -15,6 +15,7 @@
 
 #include "../../include/mclbm.h"
 #include "lbm_device.hpp"
+#include "lbm_pair.hpp"
 #include "lbm_sc1.hpp"
 
 namespace mclbm {
@@ -44,6 +45,8 @@ inline void set_err(const char *fmt, ...) {
 
 inline int pitch_of(int nx) { return (nx + 63) / 64 * 64; }
 inline int default_ty(const lbm_params &p) { return p.tile_y > 0 ? p.tile_y : 8; }
+// lanes per node of the two-component step: 1 (default) or 2 (lbm_pair.hpp)
+inline int lanes_of(const lbm_params &p) { return p.lanes == 2 && p.model == LBM_MODEL_TWO ? 2 : 1; }
 inline size_t store_bytes(int storage) { return storage == LBM_STORE_F16 ? 2 : 4; }
 // populations stored per node: 9 directions of both components, or of one
 inline int pops_per_node(const lbm_params &p) { return p.model == LBM_MODEL_SC1 ? 9 : 18; }
@@ -110,6 +113,10 @@ inline int validate(const lbm_params *p, const uint8_t *mask, const double *rA, 
     }
     if (p->tile_y != 0 && p->tile_y != 4 && p->tile_y != 8 && p->tile_y != 16 && p->tile_y != 32) {
         set_err("tile_y = %d: must be 0, 4, 8, 16 or 32", p->tile_y);
+        return LBM_EINVAL;
+    }
+    if (p->lanes < 0 || p->lanes > 2) {
+        set_err("lanes = %d: must be 0 (default), 1 or 2", p->lanes);
         return LBM_EINVAL;
     }
     if (p->diag_every < 0 || p->graph_steps < 0) {
@@ -439,6 +446,17 @@ __global__ __launch_bounds__(threads_for(TY)) void k_step(Inst I, int parity, Fi
     if (DIAG) diag_partial<TY>(sm, acc, partials, blockIdx.x);
 }
 
+// The same step with two lanes per node (lbm_pair.hpp); bit-identical results.
+template <typename S, int TY, int BC, int MODE, bool DIAG>
+__global__ __launch_bounds__(ls_threads(TY)) void k_step_ls(Inst I, int parity, Fields fo, double *partials) {
+    __shared__ SmemLS<TY> sm;
+    int tx, ty;
+    tile_coords(xcd_tile(blockIdx.x, gridDim.x), I.tiles_x, I.tiles_y, I.tg, tx, ty);
+    DiagAcc acc;
+    process_tile_ls<S, TY, BC, MODE, DIAG>(I, tx, ty, parity, sm, acc, fo);
+    if (DIAG) diag_partial_ls<TY>(sm, acc, partials, blockIdx.x);
+}
+
 template <typename S, int TY, int BC, int MODE, bool DIAG>
 __global__ __launch_bounds__(threads_for(TY)) void k_step_sc1(Inst I, int parity, Fields fo, double *partials) {
     __shared__ Smem<TY> sm;
@@ -502,6 +520,7 @@ struct Launch {
     int storage, ty, bc, mode;
     bool diag;
     int model = LBM_MODEL_TWO;
+    int lanes = 1;
 };
 
 template <typename S, int TY, int BC>
@@ -521,12 +540,23 @@ inline void launch3(const Launch &L, dim3 g, hipStream_t s, const Inst &I, int p
         }
         return;
     }
+    if (L.lanes == 2) {
+        const dim3 b(ls_threads(TY));
+        if (L.mode == MODE_FIELDS)
+            hipLaunchKernelGGL((k_step_ls<S, TY, BC, MODE_FIELDS, true>), g, b, 0, s, I, parity, fo, partials);
+        else if (L.diag)
+            hipLaunchKernelGGL((k_step_ls<S, TY, BC, MODE_STEP, true>), g, b, 0, s, I, parity, fo, partials);
+        else
+            hipLaunchKernelGGL((k_step_ls<S, TY, BC, MODE_STEP, false>), g, b, 0, s, I, parity, fo, partials);
+        return;
+    }
+    const dim3 b(threads_for(TY));
     if (L.mode == MODE_FIELDS)
-        hipLaunchKernelGGL((k_step<S, TY, BC, MODE_FIELDS, true>), g, dim3(threads_for(TY)), 0, s, I, parity, fo, partials);
+        hipLaunchKernelGGL((k_step<S, TY, BC, MODE_FIELDS, true>), g, b, 0, s, I, parity, fo, partials);
     else if (L.diag)
-        hipLaunchKernelGGL((k_step<S, TY, BC, MODE_STEP, true>), g, dim3(threads_for(TY)), 0, s, I, parity, fo, partials);
+        hipLaunchKernelGGL((k_step<S, TY, BC, MODE_STEP, true>), g, b, 0, s, I, parity, fo, partials);
     else
-        hipLaunchKernelGGL((k_step<S, TY, BC, MODE_STEP, false>), g, dim3(threads_for(TY)), 0, s, I, parity, fo, partials);
+        hipLaunchKernelGGL((k_step<S, TY, BC, MODE_STEP, false>), g, b, 0, s, I, parity, fo, partials);
 }
 
 template <typename S, int TY>

@@ -316,6 +316,7 @@ template <int TY> __device__ void diag_partial(Smem<TY> &sm, const DiagAcc &a, d
 template <typename S, int TY, int HF>
 __device__ __forceinline__ void frame_pass(const Inst &I, Smem<TY> &sm, const typename Store<S>::P *__restrict__ fin,
                                            uint32_t pb, int tx0, int ty0, bool edge, const float rref[2]) {
+#pragma clang fp contract(off)
     constexpr int W = TX + 2 * HF;
     constexpr int NBAND = HF * W;
     constexpr int NSIDE = HF * TY;
@@ -359,9 +360,13 @@ __device__ __forceinline__ void frame_pass(const Inst &I, Smem<TY> &sm, const ty
 
 // One time step (MODE_STEP) or the fields at the current time (MODE_FIELDS)
 // for the tile (tile_x, tile_y) of instance I.  parity selects the buffer read.
+// No multiply-add contraction: the one-lane and two-lane steps evaluate the
+// same expressions in the same order and agree bit for bit, whatever the
+// compiler would fuse in each.
 template <typename S, int TY, int BC, int MODE, bool DIAG>
 __device__ void process_tile(const Inst &I, int tile_x, int tile_y, int parity, Smem<TY> &sm, DiagAcc &acc,
                              const Fields &fo) {
+#pragma clang fp contract(off)
     constexpr int RPP = threads_for(TY) / 64;  // tile rows per pass of the workgroup
     constexpr int RPT = TY / RPP;             // tile rows per thread
     constexpr float SC = Store<S>::SC;

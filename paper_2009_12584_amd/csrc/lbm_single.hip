@@ -48,7 +48,7 @@ void release(lbm_handle *h) {
 }
 
 Launch launch_of(const lbm_handle *h, int mode, bool diag) {
-    return Launch{h->p.storage, h->ty, kernel_bc(h->p), mode, diag, h->p.model};
+    return Launch{h->p.storage, h->ty, kernel_bc(h->p), mode, diag, h->p.model, lanes_of(h->p)};
 }
 
 int run_fields(lbm_handle *h, const Fields &fo) {
@@ -101,6 +101,7 @@ void lbm_params_default(lbm_params *p) {
     p->rho_ref[0] = p->rho_ref[1] = NAN;
     p->model = LBM_MODEL_TWO;
     p->psi_rho0 = 1.0;
+    p->lanes = 0;
 }
 
 int lbm_create(const lbm_params *p, const uint8_t *mask, const double *rhoA0, const double *rhoB0, void *stream,

@@ -156,7 +156,7 @@ class Simulation:
 class Batch:
     """Many simulations advanced by one launch per step (lbm_batch_*)."""
 
-    def __init__(self, cases, *, storage="f32", graph_steps=0, tile_y=0, stream=None):
+    def __init__(self, cases, *, storage="f32", graph_steps=0, tile_y=0, lanes=0, stream=None):
         """cases: iterable of (mask, rhoA0, rhoB0, params dict)."""
         cases = list(cases)
         n = len(cases)
@@ -173,7 +173,7 @@ class Batch:
             rA = _host(rA, np.float64, mask.shape)
             rB = _host(rB, np.float64, mask.shape)
             self._keep += [mask, rA, rB]
-            P[k] = capi.make_params(nx, ny, storage=storage, tile_y=tile_y, **prm)
+            P[k] = capi.make_params(nx, ny, storage=storage, tile_y=tile_y, lanes=lanes, **prm)
             masks[k], ras[k], rbs[k] = mask.ctypes.data, rA.ctypes.data, rB.ctypes.data
             self.shapes.append((ny, nx))
         h = ctypes.c_void_p()

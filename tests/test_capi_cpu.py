@@ -57,6 +57,7 @@ def _sim(**kw):
     (dict(model=1, bc=2), "single-component"),
     (dict(model=1, rho0=0.0), "single-component"),
     (dict(model=0, rB=None), "rhoB0"),
+    (dict(lanes=3), "lanes"),
 ])
 def test_invalid_problems_rejected_on_host(kw, needle):
     import paper_2009_12584_amd as M

@@ -40,11 +40,12 @@ def masks_of(M, cases):
     return [M.mask_plane(c.nx, c.ny, c.geometry[1], c.geometry[2]) for c in cases]
 
 
-def test_batch_matches_single_and_oracle(M, ora):
+@pytest.mark.parametrize("lanes", [1, 2])
+def test_batch_matches_single_and_oracle(M, ora, lanes):
     cases = small_cases(7)
     masks = masks_of(M, cases)
-    say("batch of", [(c.nx, c.ny, c.bc) for c in cases])
-    b = M.Batch([(m, c.rhoA0, c.rhoB0, c.params()) for m, c in zip(masks, cases)])
+    say("batch of", [(c.nx, c.ny, c.bc) for c in cases], "lanes", lanes)
+    b = M.Batch([(m, c.rhoA0, c.rhoB0, c.params()) for m, c in zip(masks, cases)], lanes=lanes)
     b.step(60)
     for k, (m, c) in enumerate(zip(masks, cases)):
         s = M.Simulation(m, c.rhoA0, c.rhoB0, **c.params())

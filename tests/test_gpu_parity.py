@@ -201,12 +201,15 @@ def test_parity_config3_full_size(gpu, ora):
 
 # ------------------------------------------------- determinism and invariants
 
-def test_tile_shapes_bit_identical_and_runs_repeat(gpu, ora):
-    c = W.plane_drop(300, 150, 33.0, 20.0, W.IMPROVED, G=3.0)
+@pytest.mark.parametrize("bc", [W.MC, W.LLKC, W.IMPROVED])
+def test_tile_shapes_and_lanes_bit_identical_and_runs_repeat(gpu, ora, bc):
+    """Every tile height, one or two lanes per node: the same bits."""
+    c = W.plane_drop(300, 150, 33.0, 20.0, bc, G=3.0, chi=(1.1, 0.9))
     mask = gpu_mask(gpu, c)
     res = []
-    for ty in (4, 8, 16, 8):
-        sim = gpu.Simulation(mask, c.rhoA0, c.rhoB0, tile_y=ty, **c.params())
+    for ty, lanes in ((4, 1), (8, 1), (16, 1), (32, 1), (4, 2), (8, 2), (16, 2), (32, 2), (8, 1)):
+        say("case: tile rows %d lanes %d" % (ty, lanes))
+        sim = gpu.Simulation(mask, c.rhoA0, c.rhoB0, tile_y=ty, lanes=lanes, **c.params())
         sim.step(150)
         res.append(sim.fields())
         sim.close()
@@ -219,7 +222,7 @@ def test_graph_replay_matches_plain_launches(gpu, ora):
     c = W.plane_drop(256, 128, 30.0, 20.0, W.IMPROVED, G=3.0)
     mask = gpu_mask(gpu, c)
     a = gpu.Simulation(mask, c.rhoA0, c.rhoB0, **c.params())
-    b = gpu.Simulation(mask, c.rhoA0, c.rhoB0, graph_steps=16, diag_every=1, **c.params())
+    b = gpu.Simulation(mask, c.rhoA0, c.rhoB0, graph_steps=16, diag_every=1, lanes=2, **c.params())
     for n in (1, 40, 33, 64):  # odd counts fall back to plain launches until even again
         a.step(n)
         b.step(n)
