@@ -205,7 +205,8 @@ def served_rows(M, torch, W, n_req=40, chunk=200):
 def headline_row(M, torch, case, mask, fluid, nodes, args, probe, launch_config_for):
     cfg = launch_config_for(mask, case.rhoA0, case.rhoB0, **case.params())
     ty, lanes = cfg["tile_y"], cfg["lanes"]
-    r = run_single(M, torch, case, mask, args.steps, args.warmup, tile_y=ty, lanes=lanes)
+    gs = 100 if args.graph_steps is None else args.graph_steps
+    r = run_single(M, torch, case, mask, args.steps, args.warmup, tile_y=ty, lanes=lanes, graph_steps=gs)
     K = r["steps"]
     ms_per_step = r["ms"] / K
     mlups = fluid * K / (r["ms"] * 1e-3) / 1e6
@@ -229,7 +230,7 @@ def headline_row(M, torch, case, mask, fluid, nodes, args, probe, launch_config_
                                "solid density (D2Q25), tau=1, G=0.9, rho 1.0/0.03, FP32 deviations",
                    "nx": case.nx, "ny": case.ny, "fluid_nodes": fluid, "total_nodes": nodes,
                    "total_mlups": round(nodes * K / (r["ms"] * 1e-3) / 1e6, 1), "tile_y": ty, "lanes": lanes,
-                   "graph_steps": 100, "diag_every": 100,
+                   "graph_steps": gs, "diag_every": 100,
                    "mass_drift": max(abs(d["mass"][k] - d["mass0"][k]) / d["mass0"][k] for k in range(2))},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -250,6 +251,9 @@ def main():
     ap.add_argument("--rows", default="headline,large,sc1,batched,served,cpu",
                     help="comma list of rows to run (profiling runs select one)")
     ap.add_argument("--served-requests", type=int, default=40)
+    ap.add_argument("--graph-steps", type=int, default=None,
+                    help="steps per captured HIP graph in the single-simulation rows (0 = plain launches, "
+                         "which per-dispatch counter collection needs); default 100 (headline), 20 (large grids)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -290,7 +294,7 @@ def main():
         for storage in ("f32", "f16"):
             bty = 8  # 64 x 8 and 64 x 16 tiles are within 1% here; fixed so profiles name the same kernel
             rb = run_single(M, torch, big, bmask, args.large_steps, 10, storage=storage, tile_y=bty,
-                            graph_steps=20, diag_every=20)
+                            graph_steps=20 if args.graph_steps is None else args.graph_steps, diag_every=20)
             bms = rb["ms"] / rb["steps"]
             bach = alg_bytes(bfl, big.nx * big.ny, storage) / (bms * 1e-3) / 1e9
             kn = "k_step<%s, %d, 0, 0, false>" % ("float" if storage == "f32" else "__half", bty)
@@ -309,7 +313,7 @@ def main():
         srows = {}
         for storage in ("f32", "f16"):
             rs = run_single(M, torch, sc, sc.mask_user, args.large_steps, 10, storage=storage, tile_y=8,
-                            graph_steps=20, diag_every=20)
+                            graph_steps=20 if args.graph_steps is None else args.graph_steps, diag_every=20)
             sms = rs["ms"] / rs["steps"]
             sb = BYTES_PER_FLUID_SC1[storage] * sfl + BYTES_PER_NODE_FLAGS * sfl
             kn = "k_step_sc1<%s, 8, 0, 0, false>" % ("float" if storage == "f32" else "__half")
