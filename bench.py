@@ -159,7 +159,8 @@ def batched_rows(M, torch, W, steps=1000):
         mlups = fluid * steps / (t.ms * 1e-3) / 1e6
         row = {"fluid_mlups": round(mlups, 1), "ms_per_step": t.ms / steps, "tile_y": ty, "lanes": cfg["lanes"],
                "speedup_vs_plain_loop": round(mlups / out["plain_loop_fluid_mlups"], 2),
-               "hbm_gbs_algorithmic": round(alg_bytes(fluid, 0, storage) / (t.ms / steps * 1e-3) / 1e9, 1)}
+               "hbm_gbs_algorithmic": round(alg_bytes(fluid, 0, storage) / (t.ms / steps * 1e-3) / 1e9, 1),
+               "hbm_frac": round(alg_bytes(fluid, 0, storage) / (t.ms / steps * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
         if storage == "f16":
             # FP16 error against the FP32 run of the same instances (same step count)
             errs = []
@@ -184,21 +185,40 @@ def served_rows(M, torch, W, n_req=40, chunk=200):
     stream = torch.cuda.Stream()
     done, makespan = serve(reqs, hbm_budget=48 << 30, max_slots=64, chunk=chunk, stream=stream)
     s = summarize(done, makespan)
-    # the same requests run one at a time (arrival times ignored)
+    # the same requests run one at a time; their completion latencies under a
+    # first-come first-served queue follow from the arrival times and the
+    # measured service time of each request
     lu = 0
-    with Timer(torch, stream) as t:
-        for r in reqs:
+    service = []
+    for r in reqs:
+        with Timer(torch, stream) as t:
             sim = M.Simulation(r.mask, r.rhoA0, r.rhoB0, stream=stream, graph_steps=100, **r.params)
             sim.step(r.steps)
             sim.fields()
             sim.close()
-            lu += int((r.mask == 0).sum()) * r.steps
-    plain = lu / (t.ms * 1e-3) / 1e6
+        service.append(t.ms * 1e-3)
+        lu += int((r.mask == 0).sum()) * r.steps
+    plain = lu / sum(service) / 1e6
+    free, lat = 0.0, []
+    for r, sv in zip(sorted(reqs, key=lambda q: q.arrival), service):
+        free = max(free, r.arrival) + sv
+        lat.append(free - r.arrival)
+    lat.sort()
+    pct = lambda q: lat[min(len(lat) - 1, int(round(q * (len(lat) - 1))))]
     s.update({"workload": "%d requests, Poisson 200/s, W in 64..2048, H in 64..1024, 2k-20k steps, mixed BCs "
                           "and angles, FP32, chunk %d steps" % (n_req, chunk),
-              "plain_loop_fluid_mlups": round(plain, 1), "speedup_vs_plain_loop": round(s["fluid_mlups"] / plain, 2)})
+              "hbm_gbs_algorithmic": round(s["fluid_mlups"] * BYTES_PER_FLUID["f32"] / 1e3, 1),
+              "hbm_frac": round(s["fluid_mlups"] * BYTES_PER_FLUID["f32"] / 1e3 / HBM_PEAK_GBS, 4),
+              "accuracy": "each result bit-identical alone and in the mix, FP32 (GPU tests)",
+              "plain_loop_fluid_mlups": round(plain, 1), "speedup_vs_plain_loop": round(s["fluid_mlups"] / plain, 2),
+              "plain_loop_fifo_p50_latency_s": round(pct(0.5), 4), "plain_loop_fifo_p99_latency_s": round(pct(0.99), 4)})
     for k in ("makespan_s", "p50_latency_s", "p99_latency_s", "mean_latency_s", "fluid_mlups"):
         s[k] = round(s[k], 4)
+    # the same trace with 16 slots admitted shortest-job-first: shorter median
+    # latency for a little less throughput
+    done2, mk2 = serve(reqs, hbm_budget=48 << 30, max_slots=16, chunk=chunk, stream=stream, policy="sjf")
+    s2 = summarize(done2, mk2)
+    s["sjf_16_slots"] = {k: round(v, 4) for k, v in s2.items()}
     return s
 
 

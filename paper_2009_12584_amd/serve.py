@@ -47,12 +47,18 @@ class Done:
 
 
 def serve(requests, *, hbm_budget, max_slots, storage="f32", chunk=200, depth=2, keep_fields=False, stream=None,
-          time_scale=1.0, idle_sleep=0.0002):
+          time_scale=1.0, idle_sleep=0.0002, policy="fifo"):
     """Run the trace; returns (list of Done, makespan seconds).
 
     At most `depth` chunks are in flight on the device, so a new solve waits
     at most that many chunks before it joins the running batch.  time_scale
-    stretches the arrival times (1.0 = as given)."""
+    stretches the arrival times (1.0 = as given).  policy picks the next
+    waiting request to admit: "fifo" (arrival order) or "sjf" (the smallest
+    amount of work, fluid nodes x steps, first); with fewer slots than
+    waiting requests, "sjf" finishes short solves early instead of sharing
+    the device among everything that has arrived."""
+    if policy not in ("fifo", "sjf"):
+        raise ValueError("policy must be 'fifo' or 'sjf'")
     reqs = sorted(requests, key=lambda r: r.arrival)
     for r in reqs:
         if not r.fluid:
@@ -69,7 +75,9 @@ def serve(requests, *, hbm_budget, max_slots, storage="f32", chunk=200, depth=2,
             while nxt < len(reqs) and reqs[nxt].arrival * time_scale <= now:
                 queue.append(reqs[nxt])
                 nxt += 1
-            while queue:  # FIFO admission while a slot and the budget allow
+            if policy == "sjf":
+                queue.sort(key=lambda q: q.fluid * q.steps)
+            while queue:  # admission in policy order while a slot and the budget allow
                 r = queue[0]
                 slot = pool.admit(r.mask, r.rhoA0, r.rhoB0, r.steps, **r.params)
                 if slot is None:
