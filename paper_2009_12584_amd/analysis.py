@@ -172,17 +172,20 @@ def fit_exponent(t, b, lo, hi):
     return float(np.polyfit(np.log(t[sel]), np.log(b[sel]), 1)[0])
 
 
-def coalescence_study(R0s, Rs=None, *, samples=400, t_end=4.0, b_lo=3.0, storage="f32", log=None):
-    """Bridge growth for each initial radius at the paper's Ohnesorge number:
-    alpha fitted over b_lo <= b <= R0 / 3 (the viscous regime, which ends as
-    b passes R0 / 3), time in units of tau_nu = nu R0 / sigma."""
+def coalescence_study(R0s, Rs=None, *, samples=400, t_end=4.0, b_lo=3.0, storage="f32", nus=None, log=None):
+    """Bridge growth for each initial radius at the paper's Ohnesorge number
+    (or, with nus, for each kinematic viscosity at the first radius): alpha
+    fitted over b_lo <= b <= R0 / 3 (the viscous regime, which ends as b
+    passes R0 / 3), time in units of tau_nu = nu R0 / sigma."""
     import workloads as W
 
     from .sim import mask_disk, mask_plane
 
+    runs = [(R0, None) for R0 in R0s] if not nus else [(R0s[0], nu) for nu in nus]
     out = []
-    for R0 in R0s:
-        c = W.coalescence(R0, Rs)
+    for R0, nu in runs:
+        kw = {} if nu is None else {"Oh": nu / math.sqrt(0.026 * R0)}
+        c = W.coalescence(R0, Rs, **kw)
         steps = int(round(t_end * c.t_nu))
         every = max(1, steps // samples)
         g = c.geometry
@@ -191,8 +194,8 @@ def coalescence_study(R0s, Rs=None, *, samples=400, t_end=4.0, b_lo=3.0, storage
         t, b = bridge_history(c, mask, every=every, steps=steps, storage=storage)
         wall = time.perf_counter() - t0
         alpha = fit_exponent(t, b, b_lo, R0 / 3.0)
-        row = dict(R0=R0, Rs=Rs, nx=c.nx, ny=c.ny, tau=c.tau, t_nu=c.t_nu, steps=steps, every=every, alpha=alpha,
-                   t=t.tolist(), b=b.tolist(), seconds=wall)
+        row = dict(R0=R0, Rs=Rs, nu=(c.tau - 0.5) / 3.0, nx=c.nx, ny=c.ny, tau=c.tau, t_nu=c.t_nu, steps=steps,
+                   every=every, alpha=alpha, t=t.tolist(), b=b.tolist(), seconds=wall)
         out.append(row)
         if log:
             log("coalescence R0=%g %dx%d tau=%.4f steps=%d alpha=%.3f (%.1f s)" % (R0, c.nx, c.ny, c.tau, steps,
@@ -308,21 +311,23 @@ def main_coalescence(argv):
     ap.add_argument("--Rs", type=float, default=None, help="surface radius; flat when omitted")
     ap.add_argument("--t-end", type=float, default=4.0, help="in viscous times")
     ap.add_argument("--samples", type=int, default=400)
+    ap.add_argument("--nu", default="", help="comma list of viscosities at the first R0 (default: Oh = 0.286)")
     ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)
-    rows = coalescence_study([float(v) for v in a.R0.split(",")], a.Rs, samples=a.samples, t_end=a.t_end,
+    nus = [float(v) for v in a.nu.split(",") if v.strip()]
+    rows = coalescence_study([float(v) for v in a.R0.split(",")], a.Rs, samples=a.samples, t_end=a.t_end, nus=nus,
                              log=lambda m: print(m, flush=True))
     if a.out:
         with open(a.out, "w") as f:
             json.dump(dict(args=vars(a), rows=rows), f)
-    print("| R0 | grid | tau | steps | alpha | b/R0 at t/tau_nu = 0.5, 1, 2, 4 |")
-    print("|---|---|---|---|---|---|")
+    print("| R0 | nu | grid | tau | steps | alpha | b/R0 at t/tau_nu = 0.5, 1, 2, 4 |")
+    print("|---|---|---|---|---|---|---|")
     for r in rows:
         tt = np.array(r["t"]) / r["t_nu"]
         bb = np.array(r["b"]) / r["R0"]
         pts = ", ".join("%.3f" % np.interp(x, tt, bb) for x in (0.5, 1.0, 2.0, 4.0))
-        print("| %g | %dx%d | %.4f | %d | %.3f | %s |" % (r["R0"], r["nx"], r["ny"], r["tau"], r["steps"], r["alpha"],
-                                                       pts))
+        print("| %g | %.3f | %dx%d | %.4f | %d | %.3f | %s |" % (r["R0"], r["nu"], r["nx"], r["ny"], r["tau"],
+                                                              r["steps"], r["alpha"], pts))
     return 0
 
 
