@@ -63,6 +63,7 @@ __device__ __forceinline__ float psi_of(float rho, float psi0) { return psi0 * (
 template <typename S, int TY, int BC, int MODE, bool DIAG>
 __device__ void process_tile_sc1(const Inst &I, int tile_x, int tile_y, int parity, Smem<TY> &sm, DiagAcc &acc,
                                  const Fields &fo) {
+#pragma clang fp contract(off)
     constexpr int RPP = threads_for(TY) / 64;
     constexpr int RPT = TY / RPP;
     constexpr float SC = Store1<S>::SC;

@@ -116,3 +116,22 @@ def test_batch_and_pool_reject_the_single_component_model(ora):
         p.admit(m, c.rhoA0, c.rhoA0, 10, **c.params())
     assert e.value.code == LBM_EINVAL
     p.close()
+
+
+def test_sc1_graph_replay_and_diagnostics_do_not_change_results(ora):
+    """Plain launches, captured graphs and the fused FP64 diagnostics give the
+    same bits (no contraction differences between kernel variants)."""
+    from paper_2009_12584_amd.sim import Simulation, mask_plane
+
+    c = W.sc1_plane_drop(180, 100, 30.0, 15.0, W.LLKC)
+    m = mask_plane(c.nx, c.ny, c.geometry[1], c.geometry[2])
+    print("case: sc1 graph and diag variants", flush=True)
+    a = Simulation(m, c.rhoA0, None, **c.params())
+    b = Simulation(m, c.rhoA0, None, graph_steps=16, diag_every=1, **c.params())
+    for n in (1, 40, 33, 64):
+        a.step(n)
+        b.step(n)
+        for x, y in zip(a.fields(), b.fields()):
+            assert np.array_equal(x, y)
+    a.close()
+    b.close()
