@@ -186,10 +186,12 @@ def test_parity_config1_full(gpu, ora):
         assert er <= RHO_TOL and eu <= U_TOL, (T, er, eu)
 
 
-def test_parity_config2_full_size(gpu, ora):
-    """512x256 30-degree stair, improved scheme, at the size and launch shape the bench times."""
+@pytest.mark.parametrize("ty,lanes", [(8, 2), (4, 1)], ids=["two-lane-64x8", "one-lane-64x4"])
+def test_parity_config2_full_size(gpu, ora, ty, lanes):
+    """512x256 30-degree stair, improved scheme, at the size the bench times and
+    in the launch shapes its autotuner picks between."""
     c = W.config2()
-    for T, er, eu in compare_run(gpu, ora, c, [1, 10, 200]):
+    for T, er, eu in compare_run(gpu, ora, c, [1, 10, 200], tile_y=ty, lanes=lanes):
         assert er <= RHO_TOL and eu <= U_TOL, (T, er, eu)
 
 

@@ -490,3 +490,32 @@ def test_drop_at_rest_on_on_grid_wall(ora):
         cc = (w * np.cos(ang)[None, :]).sum()
         xs.append(math.atan2(s, cc) * nx / (2 * math.pi))
     assert abs(xs[1] - xs[0]) < 0.02
+
+
+@pytest.mark.parametrize("bc", [W.MC, W.LLKC, W.IMPROVED])
+def test_dependency_radius_is_four_nodes_per_step(ora, bc):
+    """After k steps a node depends on the initial state within 4 k nodes
+    (streaming reaches one node, the force stencil at most three), so a
+    periodic window of the initial state reproduces the full run in its
+    interior.  The full-size GPU checks compare on such windows."""
+    K, SIZE = 6, 110
+    margin = 4 * K + 2
+    c = W.plane_drop(300, 260, 30.0, 50.0, bc, G=3.0, rho_out=0.055, chi=(1.2, 0.8))
+    m = ora.mask_plane(c.nx, c.ny, c.geometry[1], c.geometry[2])
+    full = ora.Oracle(m, c.rhoA0, c.rhoB0, **c.params())
+    full.step(K)
+    F = full.fields()
+    x0, y0 = 150 + 25 - SIZE // 2, 130 - 43 - SIZE // 2   # on the contact line
+    cut = (slice(y0, y0 + SIZE), slice(x0, x0 + SIZE))
+    assert 0 < m[cut].sum() < SIZE * SIZE and c.rhoA0[cut].max() == 1.0
+    prm = c.params()
+    prm["periodic"] = 3
+    w = ora.Oracle(m[cut], c.rhoA0[cut], c.rhoB0[cut], **prm)
+    w.step(K)
+    Wf = w.fields()
+    inner = (slice(margin, SIZE - margin),) * 2
+    for a, b in zip(F, Wf):
+        np.testing.assert_allclose(b[inner], a[cut][inner], rtol=0, atol=1e-13)
+    # two nodes from the window's edge the wrap is felt (the run is not trivial)
+    near = (slice(2, SIZE - 2),) * 2
+    assert max(np.max(np.abs(b[near] - a[cut][near])) for a, b in zip(F, Wf)) > 1e-6
