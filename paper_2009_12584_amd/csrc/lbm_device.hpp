@@ -309,38 +309,71 @@ template <int TY> __device__ void diag_partial(Smem<TY> &sm, const DiagAcc &a, d
     }
 }
 
+// The halo frame of width HF around a 64 x TY tile, in slots: the HF rows
+// above the tile, the HF rows below it, then the HF columns left and right of
+// its own rows.  frame_slot gives slot k's position relative to the tile.
+template <int TY, int HF> constexpr int frame_total() { return 2 * HF * (TX + 2 * HF) + 2 * HF * TY; }
+
+template <int TY, int HF> __device__ __forceinline__ void frame_slot(int k, int &hx, int &hy) {
+    constexpr int W = TX + 2 * HF, NBAND = HF * W, NSIDE = HF * TY;
+    if (k < NBAND) {
+        hy = -HF + k / W;
+        hx = -HF + k % W;
+    } else if (k < 2 * NBAND) {
+        const int q = k - NBAND;
+        hy = TY + q / W;
+        hx = -HF + q % W;
+    } else if (k < 2 * NBAND + NSIDE) {
+        const int q = k - 2 * NBAND;
+        hy = q / HF;
+        hx = -HF + q % HF;
+    } else {
+        const int q = k - 2 * NBAND - NSIDE;
+        hy = q / HF;
+        hx = TX + q % HF;
+    }
+}
+
+// Slots a thread treats when T threads share a width-HMAX frame (the most any
+// frame needs).
+template <int TY, int T> constexpr int frame_slots() { return (frame_total<TY, HMAX>() + T - 1) / T; }
+
+// Node words of the frame slots first + s * T (s = 0, 1, ...), issued before
+// the owned nodes' pulls so that their latency overlaps the owned nodes' word
+// loads rather than following the pulls.
+template <int TY, int HF, int T, int NS>
+__device__ __forceinline__ void frame_words(const Inst &I, int tx0, int ty0, int first, uint32_t fw[NS]) {
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const int k = first + s * T;
+        fw[s] = NW_SOLID;
+        if (k < frame_total<TY, HF>()) {
+            int hx, hy;
+            frame_slot<TY, HF>(k, hx, hy);
+            fw[s] = node_word(I, tx0 + hx, ty0 + hy);
+        }
+    }
+}
+
 // Density pass over the halo frame of width HF (compile time): rows above and
 // below the tile, columns left and right of it.  Beyond the first ring only
 // fluid nodes within reach of an interface solid are needed (Eq. 7).  First-ring
-// positions also record their solid / interface-solid flags in LDS.
-template <typename S, int TY, int HF>
+// positions also record their solid / interface-solid flags in LDS.  fw holds
+// the node words of this thread's slots (frame_words).
+template <typename S, int TY, int HF, int NS>
 __device__ __forceinline__ void frame_pass(const Inst &I, Smem<TY> &sm, const typename Store<S>::P *__restrict__ fin,
-                                           uint32_t pb, int tx0, int ty0, bool edge, const float rref[2]) {
+                                           uint32_t pb, int tx0, int ty0, bool edge, const float rref[2],
+                                           const uint32_t fw[NS]) {
 #pragma clang fp contract(off)
-    constexpr int W = TX + 2 * HF;
-    constexpr int NBAND = HF * W;
-    constexpr int NSIDE = HF * TY;
-    constexpr int TOTAL = 2 * NBAND + 2 * NSIDE;
-    for (int k = threadIdx.x; k < TOTAL; k += threads_for(TY)) {
+    constexpr int T = threads_for(TY);
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const int k = threadIdx.x + s * T;
+        if (k >= frame_total<TY, HF>()) break;
         int hx, hy;
-        if (k < NBAND) {
-            hy = -HF + k / W;
-            hx = -HF + k % W;
-        } else if (k < 2 * NBAND) {
-            const int q = k - NBAND;
-            hy = TY + q / W;
-            hx = -HF + q % W;
-        } else if (k < 2 * NBAND + NSIDE) {
-            const int q = k - 2 * NBAND;
-            hy = q / HF;
-            hx = -HF + q % HF;
-        } else {
-            const int q = k - 2 * NBAND - NSIDE;
-            hy = q / HF;
-            hx = TX + q % HF;
-        }
+        frame_slot<TY, HF>(k, hx, hy);
         const int gx = tx0 + hx, gy = ty0 + hy;
-        const uint32_t w = node_word(I, gx, gy);
+        const uint32_t w = fw[s];
         const int ring = max(max(-hx, hx - (TX - 1)), max(-hy, hy - (TY - 1)));
         if (ring == 1)
             sm.lf[rt_idx<TY>(hx, hy)] = (uint8_t)(((w & NW_SOLID) ? LF_SOLID : 0) | ((w & NW_IFACE) ? LF_IFACE : 0));
@@ -385,8 +418,9 @@ __device__ void process_tile(const Inst &I, int tile_x, int tile_y, int parity, 
                          (MODE == MODE_FIELDS || (I.tflag[tile_y * I.tiles_x + tile_x] & TF_NEEDS_RT));
 
     // ---- phase 1a: owned rectangle; populations stay in registers.  The
-    // loads are issued here and consumed after the frame pass has issued its
-    // own, so the two memory latencies overlap.
+    // node words of the owned nodes and of the frame are loaded first, then
+    // the owned pulls are issued and consumed only after the frame pass has
+    // issued its own, so the loads form two dependent latencies, not four.
     const int lx = tid & (TX - 1);
     const int lr = tid >> 6;
     float d[RPT][2][9];
@@ -395,10 +429,17 @@ __device__ void process_tile(const Inst &I, int tile_x, int tile_y, int parity, 
     uint32_t own[RPT];  // byte offset of the owned node in a plane
     bool owned[RPT];
 #pragma unroll
+    for (int r = 0; r < RPT; ++r) w[r] = node_word(I, tx0 + lx, ty0 + lr + RPP * r);
+    constexpr int NFS = frame_slots<TY, threads_for(TY)>();
+    uint32_t fw[NFS];
+    if (need_rt)
+        frame_words<TY, HMAX, threads_for(TY), NFS>(I, tx0, ty0, tid, fw);
+    else
+        frame_words<TY, 1, threads_for(TY), NFS>(I, tx0, ty0, tid, fw);
+#pragma unroll
     for (int r = 0; r < RPT; ++r) {
         const int ly = lr + RPP * r;
         const int gx = tx0 + lx, gy = ty0 + ly;
-        w[r] = node_word(I, gx, gy);
         owned[r] = gx < I.nx && gy < I.ny;
         own[r] = (uint32_t)(gy * I.pitch + gx) * (uint32_t)sizeof(P);
         sm.lf[rt_idx<TY>(lx, ly)] =
@@ -429,9 +470,9 @@ __device__ void process_tile(const Inst &I, int tile_x, int tile_y, int parity, 
 
     // ---- phase 1b: halo frame
     if (need_rt)
-        frame_pass<S, TY, HMAX>(I, sm, fin, pb, tx0, ty0, edge, rref);
+        frame_pass<S, TY, HMAX, NFS>(I, sm, fin, pb, tx0, ty0, edge, rref, fw);
     else
-        frame_pass<S, TY, 1>(I, sm, fin, pb, tx0, ty0, edge, rref);
+        frame_pass<S, TY, 1, NFS>(I, sm, fin, pb, tx0, ty0, edge, rref, fw);
 
     // ---- phase 1c: owned densities (solid nodes hold no fluid)
 #pragma unroll

@@ -128,26 +128,13 @@ __device__ __forceinline__ void frame_ls(const Inst &I, SmemLS<TY> &sm, const ch
                                          int ty0, bool edge, float rref, int q, int c) {
 #pragma clang fp contract(off)
     constexpr int NPP = ls_threads(TY) / 2;
-    constexpr int W = TX + 2 * HF, NBAND = HF * W, NSIDE = HF * TY, TOTAL = 2 * NBAND + 2 * NSIDE;
     constexpr float SC = Store<S>::SC;
-    for (int k = q; k < TOTAL; k += NPP) {
+    // the node word is loaded here, after the owned pulls have been issued:
+    // in this layout, loading the frame's words ahead of the owned pulls (as
+    // the one-lane step does) measured slower on small grids
+    for (int k = q; k < frame_total<TY, HF>(); k += NPP) {
         int hx, hy;
-        if (k < NBAND) {
-            hy = -HF + k / W;
-            hx = -HF + k % W;
-        } else if (k < 2 * NBAND) {
-            const int qq = k - NBAND;
-            hy = TY + qq / W;
-            hx = -HF + qq % W;
-        } else if (k < 2 * NBAND + NSIDE) {
-            const int qq = k - 2 * NBAND;
-            hy = qq / HF;
-            hx = -HF + qq % HF;
-        } else {
-            const int qq = k - 2 * NBAND - NSIDE;
-            hy = qq / HF;
-            hx = TX + qq % HF;
-        }
+        frame_slot<TY, HF>(k, hx, hy);
         const int gx = tx0 + hx, gy = ty0 + hy;
         const uint32_t wf = node_word(I, gx, gy);
         const int ring = max(max(-hx, hx - (TX - 1)), max(-hy, hy - (TY - 1)));

@@ -84,11 +84,17 @@ __device__ void process_tile_sc1(const Inst &I, int tile_x, int tile_y, int pari
     double sd[RPT];
     uint32_t w[RPT], own[RPT];
     bool owned[RPT];
+    // node words of the owned nodes and of this thread's frame slot first
+    // (one latency), then the pulls
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) w[r] = node_word(I, tx0 + lx, ty0 + lr + RPP * r);
+    constexpr int NFS = (frame_total<TY, 1>() + threads_for(TY) - 1) / threads_for(TY);
+    uint32_t fw[NFS];
+    frame_words<TY, 1, threads_for(TY), NFS>(I, tx0, ty0, tid, fw);
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
         const int ly = lr + RPP * r;
         const int gx = tx0 + lx, gy = ty0 + ly;
-        w[r] = node_word(I, gx, gy);
         owned[r] = gx < I.nx && gy < I.ny;
         own[r] = (uint32_t)(gy * I.pitch + gx) * (uint32_t)sizeof(P);
         if (!(w[r] & NW_SOLID)) {
@@ -101,19 +107,14 @@ __device__ void process_tile_sc1(const Inst &I, int tile_x, int tile_y, int pari
 
     // ---- one-node frame: psi of the neighbours (0 at solids, never read there):
     // the rows above and below (TX + 2 each), then the columns left and right
-    constexpr int FW = TX + 2, TOTAL = 2 * FW + 2 * TY;
-    for (int k = tid; k < TOTAL; k += threads_for(TY)) {
+#pragma unroll
+    for (int s = 0; s < NFS; ++s) {
+        const int k = tid + s * threads_for(TY);
+        if (k >= frame_total<TY, 1>()) break;
         int hx, hy;
-        if (k < 2 * FW) {
-            hy = k < FW ? -1 : TY;
-            hx = (k < FW ? k : k - FW) - 1;
-        } else {
-            const int q = k - 2 * FW;
-            hy = q % TY;
-            hx = q < TY ? -1 : TX;
-        }
+        frame_slot<TY, 1>(k, hx, hy);
         const int gx = tx0 + hx, gy = ty0 + hy;
-        const uint32_t wf = node_word(I, gx, gy);
+        const uint32_t wf = fw[s];
         float ps = 0.f;
         if (!(wf & NW_SOLID)) {
             float df[9];
