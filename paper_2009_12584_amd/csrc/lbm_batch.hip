@@ -56,28 +56,71 @@ __global__ __launch_bounds__(ls_threads(TY)) void k_batch_step_ls(const Inst *__
     process_tile_ls<S, TY, BC, MODE_STEP, false>(I, tx, ty, parity, sm, acc, Fields{});
 }
 
-// Tile lists are grouped by boundary rule so that each launch runs a kernel
-// specialised (and register-allocated) for one rule.
+// One launch for every rule: each block takes its instance's rule.  The
+// kernel holds all three tile bodies (registers are allocated for the
+// largest), and a step pays one launch tail instead of three.
+template <typename S, int TY>
+__global__ __launch_bounds__(threads_for(TY)) void k_batch_step_all(const Inst *__restrict__ insts,
+                                                                    const int2 *__restrict__ tiles, int launch_parity,
+                                                                    long long L) {
+    __shared__ Smem<TY> sm;
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    const int2 e = tiles[t];
+    const Inst &I = insts[e.x];
+    if (L >= I.t_end) return;
+    const int parity = (I.parity0 ^ launch_parity) & 1;
+    int tx, ty;
+    tile_coords(e.y, I.tiles_x, I.tiles_y, I.tg, tx, ty);
+    DiagAcc acc;
+    if (I.bc == BC_MC)
+        process_tile<S, TY, BC_MC, MODE_STEP, false>(I, tx, ty, parity, sm, acc, Fields{});
+    else if (I.bc == BC_LLKC)
+        process_tile<S, TY, BC_LLKC, MODE_STEP, false>(I, tx, ty, parity, sm, acc, Fields{});
+    else
+        process_tile<S, TY, BC_IMPROVED, MODE_STEP, false>(I, tx, ty, parity, sm, acc, Fields{});
+}
+
+template <typename S, int TY>
+__global__ __launch_bounds__(ls_threads(TY)) void k_batch_step_ls_all(const Inst *__restrict__ insts,
+                                                                      const int2 *__restrict__ tiles,
+                                                                      int launch_parity, long long L) {
+    __shared__ SmemLS<TY> sm;
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    const int2 e = tiles[t];
+    const Inst &I = insts[e.x];
+    if (L >= I.t_end) return;
+    const int parity = (I.parity0 ^ launch_parity) & 1;
+    int tx, ty;
+    tile_coords(e.y, I.tiles_x, I.tiles_y, I.tg, tx, ty);
+    DiagAcc acc;
+    if (I.bc == BC_MC)
+        process_tile_ls<S, TY, BC_MC, MODE_STEP, false>(I, tx, ty, parity, sm, acc, Fields{});
+    else if (I.bc == BC_LLKC)
+        process_tile_ls<S, TY, BC_LLKC, MODE_STEP, false>(I, tx, ty, parity, sm, acc, Fields{});
+    else
+        process_tile_ls<S, TY, BC_IMPROVED, MODE_STEP, false>(I, tx, ty, parity, sm, acc, Fields{});
+}
+
+// Flattened (instance, tile) pairs in instance order; within an instance
+// tiles follow the grouped order of the single-instance kernel.  With one rule
+// in the list the launch runs the kernel specialised (and register-allocated)
+// for it; with several, the kernel that holds all three.
 struct TileLists {
-    int off[3] = {0, 0, 0}, cnt[3] = {0, 0, 0};
+    int cnt[3] = {0, 0, 0};
     int total() const { return cnt[0] + cnt[1] + cnt[2]; }
+    int rules() const { return (cnt[0] > 0) + (cnt[1] > 0) + (cnt[2] > 0); }
 };
 
-// Flattened (instance, tile) pairs, grouped by rule; within an instance tiles
-// follow the grouped order of the single-instance kernel.
 template <typename InstOf>
 TileLists build_tiles(int n, InstOf inst_of, std::vector<int2> &out) {
     TileLists T;
     out.clear();
-    for (int bc = 0; bc < 3; ++bc) {
-        T.off[bc] = (int)out.size();
-        for (int k = 0; k < n; ++k) {
-            const Inst *I = inst_of(k);
-            if (!I || I->bc != bc) continue;
-            const int nt = I->tiles_x * I->tiles_y;
-            for (int t = 0; t < nt; ++t) out.push_back(make_int2(k, t));
-        }
-        T.cnt[bc] = (int)out.size() - T.off[bc];
+    for (int k = 0; k < n; ++k) {
+        const Inst *I = inst_of(k);
+        if (!I) continue;
+        const int nt = I->tiles_x * I->tiles_y;
+        for (int t = 0; t < nt; ++t) out.push_back(make_int2(k, t));
+        T.cnt[I->bc] += nt;
     }
     return T;
 }
@@ -93,9 +136,18 @@ void launch_batch_bc(hipStream_t s, int lanes, int n, const Inst *insts, const i
 template <typename S, int TY>
 void launch_batch_ty(hipStream_t s, int lanes, const TileLists &T, const Inst *insts, const int2 *tiles, int lp,
                      long long L) {
-    if (T.cnt[0]) launch_batch_bc<S, TY, BC_MC>(s, lanes, T.cnt[0], insts, tiles + T.off[0], lp, L);
-    if (T.cnt[1]) launch_batch_bc<S, TY, BC_LLKC>(s, lanes, T.cnt[1], insts, tiles + T.off[1], lp, L);
-    if (T.cnt[2]) launch_batch_bc<S, TY, BC_IMPROVED>(s, lanes, T.cnt[2], insts, tiles + T.off[2], lp, L);
+    if (T.rules() > 1) {
+        if (lanes == 2)
+            hipLaunchKernelGGL((k_batch_step_ls_all<S, TY>), dim3(T.total()), dim3(ls_threads(TY)), 0, s, insts, tiles,
+                               lp, L);
+        else
+            hipLaunchKernelGGL((k_batch_step_all<S, TY>), dim3(T.total()), dim3(threads_for(TY)), 0, s, insts, tiles,
+                               lp, L);
+        return;
+    }
+    if (T.cnt[0]) launch_batch_bc<S, TY, BC_MC>(s, lanes, T.cnt[0], insts, tiles, lp, L);
+    if (T.cnt[1]) launch_batch_bc<S, TY, BC_LLKC>(s, lanes, T.cnt[1], insts, tiles, lp, L);
+    if (T.cnt[2]) launch_batch_bc<S, TY, BC_IMPROVED>(s, lanes, T.cnt[2], insts, tiles, lp, L);
 }
 
 void launch_batch(int storage, int ty, int lanes, hipStream_t s, const TileLists &T, const Inst *insts,

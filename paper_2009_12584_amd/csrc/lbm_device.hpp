@@ -397,8 +397,8 @@ __device__ __forceinline__ void frame_pass(const Inst &I, Smem<TY> &sm, const ty
 // same expressions in the same order and agree bit for bit, whatever the
 // compiler would fuse in each.
 template <typename S, int TY, int BC, int MODE, bool DIAG>
-__device__ void process_tile(const Inst &I, int tile_x, int tile_y, int parity, Smem<TY> &sm, DiagAcc &acc,
-                             const Fields &fo) {
+__device__ __forceinline__ void process_tile(const Inst &I, int tile_x, int tile_y, int parity, Smem<TY> &sm,
+                                             DiagAcc &acc, const Fields &fo) {
 #pragma clang fp contract(off)
     constexpr int RPP = threads_for(TY) / 64;  // tile rows per pass of the workgroup
     constexpr int RPT = TY / RPP;             // tile rows per thread

@@ -151,8 +151,8 @@ __device__ __forceinline__ void frame_ls(const Inst &I, SmemLS<TY> &sm, const ch
 }
 
 template <typename S, int TY, int BC, int MODE, bool DIAG>
-__device__ void process_tile_ls(const Inst &I, int tile_x, int tile_y, int parity, SmemLS<TY> &sm, DiagAcc &acc,
-                                const Fields &fo) {
+__device__ __forceinline__ void process_tile_ls(const Inst &I, int tile_x, int tile_y, int parity, SmemLS<TY> &sm,
+                                                DiagAcc &acc, const Fields &fo) {
 #pragma clang fp contract(off)
     constexpr int T = ls_threads(TY);
     constexpr int NPP = T / 2;         // nodes per pass of the workgroup

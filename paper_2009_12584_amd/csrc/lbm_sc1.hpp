@@ -61,8 +61,8 @@ __device__ __forceinline__ void pull9_1(const typename Store1<S>::P *__restrict_
 __device__ __forceinline__ float psi_of(float rho, float psi0) { return psi0 * (1.f - expf(-rho / psi0)); }
 
 template <typename S, int TY, int BC, int MODE, bool DIAG>
-__device__ void process_tile_sc1(const Inst &I, int tile_x, int tile_y, int parity, Smem<TY> &sm, DiagAcc &acc,
-                                 const Fields &fo) {
+__device__ __forceinline__ void process_tile_sc1(const Inst &I, int tile_x, int tile_y, int parity, Smem<TY> &sm,
+                                                 DiagAcc &acc, const Fields &fo) {
 #pragma clang fp contract(off)
     constexpr int RPP = threads_for(TY) / 64;
     constexpr int RPT = TY / RPP;
