@@ -67,6 +67,40 @@ __device__ constexpr float WF[9] = {4.f / 9.f,  1.f / 9.f,  1.f / 9.f,  1.f / 9.
 __device__ constexpr float W25_BY_R2[9] = {0.f,        4.f / 21.f, 4.f / 45.f, 0.f, 1.f / 60.f,
                                            2.f / 315.f, 0.f,        0.f,        1.f / 5040.f};
 
+// Collision of one component in direction i = 1..8 (Eqs. 1, 2, 4), in
+// deviation form and storage units:
+//   d* = (1 - omega) d + omega w_i SC (dr + rho eq_i) + w_i SC g S_i,
+//   eq_i = (c_i.u) (3 + 4.5 c_i.u) - 1.5 u.u,
+//   S_i  = (c_i.F) (3 + 9 c_i.u) - 3 u.F,
+// with dr the exact incoming deviation sum, g = 1 - 1/(2 tau) and S_i the
+// Guo source term 3 (c_i - u).F + 9 (c_i.u)(c_i.F) regrouped.  Every step
+// kernel evaluates it through these functions, with explicit multiply-adds in
+// a fixed order, so that the one-lane and two-lane steps round identically.
+struct CollK {
+    float omc;    // 1 - omega
+    float wo[2];  // omega w_i SC for axis (w = 1/9) and diagonal (w = 1/36) directions
+    float wg[2];  // w_i SC g
+};
+__device__ __forceinline__ CollK coll_consts(float omega, float guo, float sc) {
+    CollK k;
+    k.omc = 1.f - omega;
+    k.wo[0] = omega * ((1.f / 9.f) * sc);
+    k.wo[1] = omega * ((1.f / 36.f) * sc);
+    k.wg[0] = ((1.f / 9.f) * sc) * guo;
+    k.wg[1] = ((1.f / 36.f) * sc) * guo;
+    return k;
+}
+// Per direction, shared by both components: eq_i and 3 + 9 c_i.u.
+__device__ __forceinline__ float coll_eq(float cu, float m15uu) { return fmaf(cu, fmaf(4.5f, cu, 3.f), m15uu); }
+__device__ __forceinline__ float coll_t(float cu) { return fmaf(9.f, cu, 3.f); }
+// One component: d its incoming deviation, cF = c_i.F, uF3 = 3 u.F.
+__device__ __forceinline__ float coll_dir(int i, float d, float dr, float rho, float eq, float t, float cF, float uF3,
+                                          const CollK &k) {
+    const int a = i < 5 ? 0 : 1;
+    const float src = k.wg[a] * fmaf(cF, t, -uF3);
+    return fmaf(k.omc, d, fmaf(k.wo[a], fmaf(rho, eq, dr), src));
+}
+
 // FP16 deviations are stored multiplied by 2^10, which keeps the smallest
 // populations of a 0.03 minority phase clear of the subnormal range.  The
 // kernels work in storage units (deviation x SC): the power-of-two scale is
@@ -551,7 +585,10 @@ __device__ __forceinline__ void process_tile(const Inst &I, int tile_x, int tile
         }
         const float ra = sm.rho[0][rho_idx<TY>(lx, ly)];
         const float rb = sm.rho[1][rho_idx<TY>(lx, ly)];
-        // Eq. 5 over fluid neighbours, Eq. 6 over solid neighbours
+        // Eq. 5 over fluid neighbours, Eq. 6 over solid neighbours.  Solid
+        // and out-of-domain positions hold density 0 in LDS and fluid
+        // positions hold rho~ 0, so both sums run over all 8 neighbours
+        // without a branch; only the wall normal of Eq. 6 reads the node word.
         float sax = 0.f, say = 0.f, sbx = 0.f, sby = 0.f;  // sum w psi c (A and B)
         float nxs = 0.f, nys = 0.f;                          // sum w phi c
         float tax = 0.f, tay = 0.f, tbx = 0.f, tby = 0.f;  // sum w rho~ c
@@ -559,24 +596,24 @@ __device__ __forceinline__ void process_tile(const Inst &I, int tile_x, int tile
         for (int i = 1; i < 9; ++i) {
             const int qx = lx + CX[i], qy = ly + CY[i];
             const float wi = WF[i];
-            if (!((w[r] >> (i - 1)) & 1u)) {
-                const float a = wi * sm.rho[0][rho_idx<TY>(qx, qy)];
-                const float b = wi * sm.rho[1][rho_idx<TY>(qx, qy)];
-                sax += a * CX[i];
-                say += a * CY[i];
-                sbx += b * CX[i];
-                sby += b * CY[i];
-            } else {
-                nxs += wi * CX[i];
-                nys += wi * CY[i];
-                if (BC == BC_IMPROVED) {
-                    const float a = wi * sm.rt[0][rt_idx<TY>(qx, qy)];
-                    const float b = wi * sm.rt[1][rt_idx<TY>(qx, qy)];
-                    tax += a * CX[i];
-                    tay += a * CY[i];
-                    tbx += b * CX[i];
-                    tby += b * CY[i];
-                }
+            const float a = wi * sm.rho[0][rho_idx<TY>(qx, qy)];
+            const float b = wi * sm.rho[1][rho_idx<TY>(qx, qy)];
+            sax += a * CX[i];
+            say += a * CY[i];
+            sbx += b * CX[i];
+            sby += b * CY[i];
+            if (BC != BC_IMPROVED) {
+                const bool sol = (w[r] >> (i - 1)) & 1u;
+                nxs += sol ? wi * CX[i] : 0.f;
+                nys += sol ? wi * CY[i] : 0.f;
+            } else if (need_rt) {
+                // tiles without interface solids in reach leave rho~ unset
+                const float ta = wi * sm.rt[0][rt_idx<TY>(qx, qy)];
+                const float tb = wi * sm.rt[1][rt_idx<TY>(qx, qy)];
+                tax += ta * CX[i];
+                tay += ta * CY[i];
+                tbx += tb * CX[i];
+                tby += tb * CY[i];
             }
         }
         float FAx = -I.G * ra * sbx, FAy = -I.G * ra * sby;
@@ -641,27 +678,20 @@ __device__ __forceinline__ void process_tile(const Inst &I, int tile_x, int tile
         // systematic FP32 mass drift).  The velocity terms of the equilibrium
         // are common to both components.
         const float uu = ux * ux + uy * uy;
-        float eq[9];
-#pragma unroll
-        for (int i = 1; i < 9; ++i) {
-            const float cu = CX[i] * ux + CY[i] * uy;
-            eq[i] = 3.f * cu + 4.5f * cu * cu - 1.5f * uu;
-        }
-        const float uFA = ux * FAx + uy * FAy, uFB = ux * FBx + uy * FBy;
+        const float m15uu = -1.5f * uu;
+        const float uFA3 = 3.f * (ux * FAx + uy * FAy), uFB3 = 3.f * (ux * FBx + uy * FBy);
         const float drA = (float)sd[r][0] * (1.f / SC), drB = (float)sd[r][1] * (1.f / SC);
+        const CollK ck = coll_consts(I.omega, I.guo, SC);
         P *o = at(fout, own[r]);
         double soA = 0.0, soB = 0.0;
 #pragma unroll
         for (int i = 1; i < 9; ++i) {
             const float cu = CX[i] * ux + CY[i] * uy;
+            const float eq = coll_eq(cu, m15uu), t = coll_t(cu);
             const float cFA = CX[i] * FAx + CY[i] * FAy;
             const float cFB = CX[i] * FBx + CY[i] * FBy;
-            const float deqA = (WF[i] * SC) * (drA + ra * eq[i]);
-            const float deqB = (WF[i] * SC) * (drB + rb * eq[i]);
-            const float srcA = (WF[i] * SC) * I.guo * (3.f * (cFA - uFA) + 9.f * cu * cFA);
-            const float srcB = (WF[i] * SC) * I.guo * (3.f * (cFB - uFB) + 9.f * cu * cFB);
-            const float dA = d[r][0][i], dB = d[r][1][i];
-            const auto q = Store<S>::enc2(dA + I.omega * (deqA - dA) + srcA, dB + I.omega * (deqB - dB) + srcB);
+            const auto q = Store<S>::enc2(coll_dir(i, d[r][0][i], drA, ra, eq, t, cFA, uFA3, ck),
+                                          coll_dir(i, d[r][1][i], drB, rb, eq, t, cFB, uFB3, ck));
             const float2 qd = Store<S>::dec2(q);
             soA += (double)qd.x;
             soB += (double)qd.y;

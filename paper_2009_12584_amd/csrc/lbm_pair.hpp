@@ -297,24 +297,25 @@ __device__ __forceinline__ void process_tile_ls(const Inst &I, int tile_x, int t
         const float rm = sm.rho[c][rho_idx<TY>(lx, ly)];      // own component
         const float ro = sm.rho[c ^ 1][rho_idx<TY>(lx, ly)];  // the other one
         // Eq. 5 over fluid neighbours with the other component's density;
-        // Eq. 6 over solid neighbours
+        // Eq. 6 over solid neighbours.  Solid and out-of-domain positions
+        // hold density 0 in LDS and fluid positions hold rho~ 0: no branch.
         float sx = 0.f, sy = 0.f, nxs = 0.f, nys = 0.f, tx = 0.f, ty = 0.f;
 #pragma unroll
         for (int i = 1; i < 9; ++i) {
             const int qx = lx + CX[i], qy = ly + CY[i];
             const float wi = WF[i];
-            if (!((w[r] >> (i - 1)) & 1u)) {
-                const float a = wi * sm.rho[c ^ 1][rho_idx<TY>(qx, qy)];
-                sx += a * CX[i];
-                sy += a * CY[i];
-            } else {
-                nxs += wi * CX[i];
-                nys += wi * CY[i];
-                if (BC == BC_IMPROVED) {
-                    const float a = wi * sm.rt[c ^ 1][rt_idx<TY>(qx, qy)];
-                    tx += a * CX[i];
-                    ty += a * CY[i];
-                }
+            const float a = wi * sm.rho[c ^ 1][rho_idx<TY>(qx, qy)];
+            sx += a * CX[i];
+            sy += a * CY[i];
+            if (BC != BC_IMPROVED) {
+                const bool sol = (w[r] >> (i - 1)) & 1u;
+                nxs += sol ? wi * CX[i] : 0.f;
+                nys += sol ? wi * CY[i] : 0.f;
+            } else if (need_rt) {
+                // tiles without interface solids in reach leave rho~ unset
+                const float t = wi * sm.rt[c ^ 1][rt_idx<TY>(qx, qy)];
+                tx += t * CX[i];
+                ty += t * CY[i];
             }
         }
         float Fx = -I.G * rm * sx, Fy = -I.G * rm * sy;
@@ -375,19 +376,18 @@ __device__ __forceinline__ void process_tile_ls(const Inst &I, int tile_x, int t
         // Eqs. 1, 2, 4 in deviation form and storage units; the rest
         // population takes the exact remainder of the incoming sum
         const float uu = ux * ux + uy * uy;
-        const float uF = ux * Fx + uy * Fy;
+        const float m15uu = -1.5f * uu;
+        const float uF3 = 3.f * (ux * Fx + uy * Fy);
         const float dr = (float)sd[r] * (1.f / SC);
+        const CollK ck = coll_consts(I.omega, I.guo, SC);
         char *o = fout + own[r];
         double so = 0.0;
 #pragma unroll
         for (int i = 1; i < 9; ++i) {
             const float cu = CX[i] * ux + CY[i] * uy;
-            const float eq = 3.f * cu + 4.5f * cu * cu - 1.5f * uu;
+            const float eq = coll_eq(cu, m15uu), t = coll_t(cu);
             const float cF = CX[i] * Fx + CY[i] * Fy;
-            const float deq = (WF[i] * SC) * (dr + rm * eq);
-            const float src = (WF[i] * SC) * I.guo * (3.f * (cF - uF) + 9.f * cu * cF);
-            const float di = d[r][i];
-            const auto v = Comp<S>::enc(di + I.omega * (deq - di) + src);
+            const auto v = Comp<S>::enc(coll_dir(i, d[r][i], dr, rm, eq, t, cF, uF3, ck));
             so += (double)Comp<S>::dec(v);
             Comp<S>::put(o + (uint32_t)i * pb, v, I.nt != 0);
         }

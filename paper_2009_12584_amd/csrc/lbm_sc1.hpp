@@ -201,19 +201,17 @@ __device__ __forceinline__ void process_tile_sc1(const Inst &I, int tile_x, int 
         // Eqs. 1, 2, 4 in deviation form and storage units; the rest
         // population takes the exact remainder of the incoming sum
         const float uu = ux * ux + uy * uy;
-        const float uF = ux * Fx + uy * Fy;
+        const float m15uu = -1.5f * uu;
+        const float uF3 = 3.f * (ux * Fx + uy * Fy);
         const float dr = (float)sd[r] * (1.f / SC);
+        const CollK ck = coll_consts(I.omega, I.guo, SC);
         P *o = at(fout, own[r]);
         double so = 0.0;
 #pragma unroll
         for (int i = 1; i < 9; ++i) {
             const float cu = CX[i] * ux + CY[i] * uy;
             const float cF = CX[i] * Fx + CY[i] * Fy;
-            const float eq = 3.f * cu + 4.5f * cu * cu - 1.5f * uu;
-            const float deq = (WF[i] * SC) * (dr + ra * eq);
-            const float src = (WF[i] * SC) * I.guo * (3.f * (cF - uF) + 9.f * cu * cF);
-            const float di = d[r][i];
-            const P q = Store1<S>::enc(di + I.omega * (deq - di) + src);
+            const P q = Store1<S>::enc(coll_dir(i, d[r][i], dr, ra, coll_eq(cu, m15uu), coll_t(cu), cF, uF3, ck));
             so += (double)Store1<S>::dec(q);
             if (I.nt)
                 Store1<S>::putnt(at(o, (uint32_t)i * pb), q);
