@@ -7,10 +7,18 @@ Usage (after the rocprofv3 runs named in the summary it writes):
 --stats   directory of a `rocprofv3 --kernel-trace --stats --output-format csv` run
 --fetch   directory of a `rocprofv3 --pmc FETCH_SIZE --output-format csv` run
 --write   directory of a `rocprofv3 --pmc WRITE_SIZE --output-format csv` run
+--issue   directory of a `rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU SQ_INSTS_SALU
+          SQ_INSTS_LDS SQ_INSTS_VMEM_RD SQ_INSTS_VMEM_WR GRBM_GUI_ACTIVE` run
 
 FETCH_SIZE and WRITE_SIZE (KiB per dispatch) are calibrated with the copy
 probe kernel of the same runs, whose true read and write byte counts are
 known: bytes = counter KiB * 1024 * (true copy bytes / copy counter bytes).
+
+The issue table gives wavefront instructions per wave and the VALU issue
+fraction: SQ_INSTS_VALU over the cycles the dispatch had, at one VALU
+wavefront instruction per compute unit and cycle (4 SIMDs, each taking 4
+cycles for a 64-wide instruction); the cycles are GRBM_GUI_ACTIVE, which
+counts on every XCD, divided by the XCD count of the agent.
 """
 from __future__ import annotations
 
@@ -65,6 +73,35 @@ def pmc_means(dirname, counter):
     return {k: sum(v) / len(v) for k, v in acc.items()}
 
 
+def pmc_table(dirname):
+    """Per kernel: mean of every counter over its dispatches, and the mean
+    dispatch duration in ns."""
+    acc = defaultdict(lambda: defaultdict(list))
+    dur = defaultdict(dict)
+    with open(_one(dirname, "_counter_collection.csv")) as f:
+        for r in csv.DictReader(f):
+            k = short_name(r["Kernel_Name"])
+            acc[k][r["Counter_Name"]].append(float(r["Counter_Value"]))
+            dur[k][r["Dispatch_Id"]] = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+    out = {}
+    for k, c in acc.items():
+        m = {n: sum(v) / len(v) for n, v in c.items()}
+        m["ns"] = sum(dur[k].values()) / len(dur[k])
+        out[k] = m
+    return out
+
+
+def agent_field(dirname, field, default):
+    try:
+        with open(_one(dirname, "_agent_info.csv")) as f:
+            for r in csv.DictReader(f):
+                if r.get("Name", "").startswith("gfx") and r.get(field):
+                    return int(r[field])
+    except (OSError, ValueError):
+        pass
+    return default
+
+
 def copy_bytes(dirname, counter):
     """True bytes per copy-probe dispatch, from its grid size (16 B per lane)."""
     with open(_one(dirname, "_counter_collection.csv")) as f:
@@ -79,6 +116,7 @@ def main():
     ap.add_argument("--stats", required=True)
     ap.add_argument("--fetch")
     ap.add_argument("--write")
+    ap.add_argument("--issue")
     ap.add_argument("--kernel-hash", required=True)
     ap.add_argument("--out", required=True)
     ap.add_argument("--title", default="rocprofv3 summary")
@@ -113,6 +151,31 @@ def main():
             fb = fetch[k] * 1024 * kf / 1e6
             wb = write[k] * 1024 * kw / 1e6
             lines.append("| %s | %.3f | %.3f | %.3f |" % (k, fb, wb, fb + wb))
+        lines.append("")
+    if a.issue:
+        t = pmc_table(a.issue)
+        xcc = agent_field(a.issue, "Num_Xcc", 8)
+        cus = agent_field(a.issue, "Cu_Count", 256)
+        lines += ["## Instruction issue (`--pmc SQ_WAVES SQ_INSTS_VALU SQ_INSTS_SALU SQ_INSTS_LDS "
+                  "SQ_INSTS_VMEM_RD SQ_INSTS_VMEM_WR GRBM_GUI_ACTIVE`)", "",
+                  "Per wavefront: instructions issued.  Clock = GRBM_GUI_ACTIVE / %d XCDs / dispatch "
+                  "duration.  VALU issue = SQ_INSTS_VALU / (%d CUs x cycles)." % (xcc, cus), "",
+                  "| kernel | waves | VALU/wave | SALU/wave | LDS/wave | VMEM rd/wave | VMEM wr/wave | "
+                  "us | clock GHz | VALU issue |", "|---|---|---|---|---|---|---|---|---|---|"]
+        # the step kernels and the copy probe; the clock and issue columns
+        # only for dispatches long enough (50 us) that the counters' window
+        # is the dispatch
+        rows = [(k, m) for k, m in t.items() if m.get("SQ_WAVES") and "SQ_INSTS_VALU" in m and
+                (k.startswith("k_step") or k.startswith("k_batch") or COPY_KERNEL in k)]
+        for k, m in sorted(rows, key=lambda km: -km[1]["ns"]):
+            w = m["SQ_WAVES"]
+            cyc = m.get("GRBM_GUI_ACTIVE", 0.0) / xcc
+            long_enough = cyc > 0 and m["ns"] >= 50e3
+            ghz = "%.2f" % (cyc / m["ns"]) if long_enough else "-"
+            util = "%.2f" % (m["SQ_INSTS_VALU"] / (cus * cyc)) if long_enough else "-"
+            lines.append("| %s | %d | %.0f | %.0f | %.1f | %.1f | %.1f | %.1f | %s | %s |" % (
+                k, w, m["SQ_INSTS_VALU"] / w, m.get("SQ_INSTS_SALU", 0) / w, m.get("SQ_INSTS_LDS", 0) / w,
+                m.get("SQ_INSTS_VMEM_RD", 0) / w, m.get("SQ_INSTS_VMEM_WR", 0) / w, m["ns"] / 1e3, ghz, util))
         lines.append("")
     os.makedirs(os.path.dirname(os.path.abspath(a.out)), exist_ok=True)
     with open(a.out, "w") as f:
