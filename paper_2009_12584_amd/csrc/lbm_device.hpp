@@ -67,6 +67,19 @@ __device__ constexpr float WF[9] = {4.f / 9.f,  1.f / 9.f,  1.f / 9.f,  1.f / 9.
 __device__ constexpr float W25_BY_R2[9] = {0.f,        4.f / 21.f, 4.f / 45.f, 0.f, 1.f / 60.f,
                                            2.f / 315.f, 0.f,        0.f,        1.f / 5040.f};
 
+// c_i . (x, y), and s += v c_i, without the products by a zero lattice
+// component: once the direction loops are unrolled i is a constant, and those
+// terms would only add a signed zero.
+__device__ __forceinline__ float cdot(int i, float x, float y) {
+    if (CX[i] == 0) return CY[i] * y;
+    if (CY[i] == 0) return CX[i] * x;
+    return CX[i] * x + CY[i] * y;
+}
+__device__ __forceinline__ void cacc(int i, float v, float &sx, float &sy) {
+    if (CX[i] != 0) sx += v * CX[i];
+    if (CY[i] != 0) sy += v * CY[i];
+}
+
 // Collision of one component in direction i = 1..8 (Eqs. 1, 2, 4), in
 // deviation form and storage units:
 //   d* = (1 - omega) d + omega w_i SC (dr + rho eq_i) + w_i SC g S_i,
@@ -598,22 +611,17 @@ __device__ __forceinline__ void process_tile(const Inst &I, int tile_x, int tile
             const float wi = WF[i];
             const float a = wi * sm.rho[0][rho_idx<TY>(qx, qy)];
             const float b = wi * sm.rho[1][rho_idx<TY>(qx, qy)];
-            sax += a * CX[i];
-            say += a * CY[i];
-            sbx += b * CX[i];
-            sby += b * CY[i];
+            cacc(i, a, sax, say);
+            cacc(i, b, sbx, sby);
             if (BC != BC_IMPROVED) {
                 const bool sol = (w[r] >> (i - 1)) & 1u;
-                nxs += sol ? wi * CX[i] : 0.f;
-                nys += sol ? wi * CY[i] : 0.f;
+                cacc(i, sol ? wi : 0.f, nxs, nys);
             } else if (need_rt) {
                 // tiles without interface solids in reach leave rho~ unset
                 const float ta = wi * sm.rt[0][rt_idx<TY>(qx, qy)];
                 const float tb = wi * sm.rt[1][rt_idx<TY>(qx, qy)];
-                tax += ta * CX[i];
-                tay += ta * CY[i];
-                tbx += tb * CX[i];
-                tby += tb * CY[i];
+                cacc(i, ta, tax, tay);
+                cacc(i, tb, tbx, tby);
             }
         }
         float FAx = -I.G * ra * sbx, FAy = -I.G * ra * sby;
@@ -686,10 +694,10 @@ __device__ __forceinline__ void process_tile(const Inst &I, int tile_x, int tile
         double soA = 0.0, soB = 0.0;
 #pragma unroll
         for (int i = 1; i < 9; ++i) {
-            const float cu = CX[i] * ux + CY[i] * uy;
+            const float cu = cdot(i, ux, uy);
             const float eq = coll_eq(cu, m15uu), t = coll_t(cu);
-            const float cFA = CX[i] * FAx + CY[i] * FAy;
-            const float cFB = CX[i] * FBx + CY[i] * FBy;
+            const float cFA = cdot(i, FAx, FAy);
+            const float cFB = cdot(i, FBx, FBy);
             const auto q = Store<S>::enc2(coll_dir(i, d[r][0][i], drA, ra, eq, t, cFA, uFA3, ck),
                                           coll_dir(i, d[r][1][i], drB, rb, eq, t, cFB, uFB3, ck));
             const float2 qd = Store<S>::dec2(q);

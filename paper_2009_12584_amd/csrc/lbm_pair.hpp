@@ -305,17 +305,14 @@ __device__ __forceinline__ void process_tile_ls(const Inst &I, int tile_x, int t
             const int qx = lx + CX[i], qy = ly + CY[i];
             const float wi = WF[i];
             const float a = wi * sm.rho[c ^ 1][rho_idx<TY>(qx, qy)];
-            sx += a * CX[i];
-            sy += a * CY[i];
+            cacc(i, a, sx, sy);
             if (BC != BC_IMPROVED) {
                 const bool sol = (w[r] >> (i - 1)) & 1u;
-                nxs += sol ? wi * CX[i] : 0.f;
-                nys += sol ? wi * CY[i] : 0.f;
+                cacc(i, sol ? wi : 0.f, nxs, nys);
             } else if (need_rt) {
                 // tiles without interface solids in reach leave rho~ unset
                 const float t = wi * sm.rt[c ^ 1][rt_idx<TY>(qx, qy)];
-                tx += t * CX[i];
-                ty += t * CY[i];
+                cacc(i, t, tx, ty);
             }
         }
         float Fx = -I.G * rm * sx, Fy = -I.G * rm * sy;
@@ -384,9 +381,9 @@ __device__ __forceinline__ void process_tile_ls(const Inst &I, int tile_x, int t
         double so = 0.0;
 #pragma unroll
         for (int i = 1; i < 9; ++i) {
-            const float cu = CX[i] * ux + CY[i] * uy;
+            const float cu = cdot(i, ux, uy);
             const float eq = coll_eq(cu, m15uu), t = coll_t(cu);
-            const float cF = CX[i] * Fx + CY[i] * Fy;
+            const float cF = cdot(i, Fx, Fy);
             const auto v = Comp<S>::enc(coll_dir(i, d[r][i], dr, rm, eq, t, cF, uF3, ck));
             so += (double)Comp<S>::dec(v);
             Comp<S>::put(o + (uint32_t)i * pb, v, I.nt != 0);

@@ -159,11 +159,9 @@ __device__ __forceinline__ void process_tile_sc1(const Inst &I, int tile_x, int 
             const float wi = WF[i];
             if (!((w[r] >> (i - 1)) & 1u)) {
                 const float a = wi * sm.rho[0][rho_idx<TY>(lx + CX[i], ly + CY[i])];
-                sx += a * CX[i];
-                sy += a * CY[i];
+                cacc(i, a, sx, sy);
             } else {
-                nxs += wi * CX[i];
-                nys += wi * CY[i];
+                cacc(i, wi, nxs, nys);
             }
         }
         const float Sw = BC == BC_MC ? 1.f : px;  // the solid's pseudopotential
@@ -209,8 +207,8 @@ __device__ __forceinline__ void process_tile_sc1(const Inst &I, int tile_x, int 
         double so = 0.0;
 #pragma unroll
         for (int i = 1; i < 9; ++i) {
-            const float cu = CX[i] * ux + CY[i] * uy;
-            const float cF = CX[i] * Fx + CY[i] * Fy;
+            const float cu = cdot(i, ux, uy);
+            const float cF = cdot(i, Fx, Fy);
             const P q = Store1<S>::enc(coll_dir(i, d[r][i], dr, ra, coll_eq(cu, m15uu), coll_t(cu), cF, uF3, ck));
             so += (double)Store1<S>::dec(q);
             if (I.nt)
