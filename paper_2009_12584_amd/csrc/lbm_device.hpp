@@ -549,6 +549,9 @@ __device__ __forceinline__ void process_tile(const Inst &I, int tile_x, int tile
                 // out-of-domain positions as 0, so the numerator needs no mask:
                 // all 48 reads issue back to back; the mask enters only the
                 // denominator
+                // the components one after the other: 24 LDS values in
+                // flight at a time instead of 48 keeps the phase within the
+                // registers of the rest of the step
                 float na = 0.f, nb = 0.f, den = 0.f;
                 int j = 0;
 #pragma unroll
@@ -560,9 +563,18 @@ __device__ __forceinline__ void process_tile(const Inst &I, int tile_x, int tile
                         // D2Q25 weights, or the D2Q9 ones on the first belt
                         const float wt = I.avg == 0 ? W25_BY_R2[r2] : (r2 == 1 ? 1.f / 9.f : (r2 == 2 ? 1.f / 36.f : 0.f));
                         na += wt * sm.rho[0][rho_idx<TY>(vx + ex, vy + ey)];
-                        nb += wt * sm.rho[1][rho_idx<TY>(vx + ex, vy + ey)];
                         den += ((m >> j) & 1u) ? wt : 0.f;
                         ++j;
+                    }
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int ey = -2; ey <= 2; ++ey)
+#pragma unroll
+                    for (int ex = -2; ex <= 2; ++ex) {
+                        if (ex == 0 && ey == 0) continue;
+                        const int r2 = ex * ex + ey * ey;
+                        const float wt = I.avg == 0 ? W25_BY_R2[r2] : (r2 == 1 ? 1.f / 9.f : (r2 == 2 ? 1.f / 36.f : 0.f));
+                        nb += wt * sm.rho[1][rho_idx<TY>(vx + ex, vy + ey)];
                     }
                 // den > 0: an interface solid has a fluid first-belt neighbour
                 ta = chi[0] * na / den;
