@@ -36,8 +36,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-BYTES_PER_FLUID = {"f32": 144, "f16": 72}   # 18 populations read + written per fluid node
-BYTES_PER_FLUID_SC1 = {"f32": 72, "f16": 36}  # 9 populations read + written, single-component model
+# 18 populations read + written per fluid node; with FP16 storage the two
+# rest populations stay FP32 (16 FP16 + 2 FP32 values each way)
+BYTES_PER_FLUID = {"f32": 144, "f16": 80}
+BYTES_PER_FLUID_SC1 = {"f32": 72, "f16": 40}  # 9 populations read + written, single-component model
 BYTES_PER_NODE_FLAGS = 2                     # one 16-bit node word per node
 KERNEL_SOURCES = ["lbm_device.hpp", "lbm_pair.hpp", "lbm_sc1.hpp", "lbm_common.hpp", "lbm_single.hip",
                   "lbm_batch.hip"]

@@ -184,8 +184,8 @@ InstMem layout(const lbm_params &p, int ty) {
         o += al(b);
         return r;
     };
-    m.off_buf0 = take(18 * plane * store_bytes(p.storage));
-    m.off_buf1 = take(18 * plane * store_bytes(p.storage));
+    m.off_buf0 = take(pop_buffer_bytes(p));
+    m.off_buf1 = take(pop_buffer_bytes(p));
     m.off_word = take(plane * sizeof(uint16_t));
     m.off_m25 = take(plane * sizeof(uint32_t));
     m.off_nbr = take(n);
@@ -241,7 +241,7 @@ int prepare(Prepared &P, const lbm_params &p, int ty, char *base, const uint8_t 
     P.partials = (double *)(base + P.m.off_part);
     P.dd = (DiagDev *)(base + P.m.off_dd);
     P.fields = (float *)(base + P.m.off_fields);
-    const size_t bufbytes = 18 * np * store_bytes(p.storage);
+    const size_t bufbytes = pop_buffer_bytes(p);
     MCLBM_HIP(hipMemsetAsync(P.I.buf[0], 0, bufbytes, s));
     MCLBM_HIP(hipMemsetAsync(P.I.buf[1], 0, bufbytes, s));
     MCLBM_HIP(hipMemsetAsync(word, 0, np * sizeof(uint16_t), s));

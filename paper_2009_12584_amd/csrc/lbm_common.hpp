@@ -50,9 +50,11 @@ inline int lanes_of(const lbm_params &p) { return p.lanes == 2 && p.model == LBM
 inline size_t store_bytes(int storage) { return storage == LBM_STORE_F16 ? 2 : 4; }
 // populations stored per node: 9 directions of both components, or of one
 inline int pops_per_node(const lbm_params &p) { return p.model == LBM_MODEL_SC1 ? 9 : 18; }
-// bytes of one population buffer
+// bytes of one population buffer: nine planes per component; with FP16
+// storage the rest population has an FP32 plane of its own after them
 inline size_t pop_buffer_bytes(const lbm_params &p) {
-    return (size_t)pops_per_node(p) * (size_t)p.ny * pitch_of(p.nx) * store_bytes(p.storage);
+    const size_t np = (size_t)p.ny * pitch_of(p.nx), comps = (size_t)pops_per_node(p) / 9;
+    return comps * np * (9 * store_bytes(p.storage) + (p.storage == LBM_STORE_F16 ? 4 : 0));
 }
 
 // Bytes of device memory one simulation holds (two population buffers, node
@@ -90,7 +92,7 @@ inline int validate(const lbm_params *p, const uint8_t *mask, const double *rA, 
         return LBM_EINVAL;
     }
     // the 9 population planes are addressed with 32-bit byte offsets
-    if ((double)p->ny * pitch_of(p->nx) * pops_per_node(*p) * (double)store_bytes(p->storage) >= 4294967296.0) {
+    if ((double)pop_buffer_bytes(*p) >= 4294967296.0) {
         set_err("grid %d x %d: a population buffer would exceed 4 GiB", p->nx, p->ny);
         return LBM_EINVAL;
     }
@@ -344,8 +346,12 @@ __global__ void k_init(Inst I, const double *__restrict__ rA, const double *__re
         const int xs = wrap(x + CX[j], I.nx, true), ys = wrap(y + CY[j], I.ny, true);
         int64_t src = (int64_t)ys * I.nx + xs;
         if (I.node[(int64_t)ys * I.pitch + xs] & NW_SOLID) src = k;
-        Store<S>::put2(b + (int64_t)j * I.plane + own, Store<S>::enc2((float)(wd[j] * (rA[src] - rrefA) * sc),
-                                                                      (float)(wd[j] * (rB[src] - rrefB) * sc)));
+        const float va = (float)(wd[j] * (rA[src] - rrefA) * sc), vb = (float)(wd[j] * (rB[src] - rrefB) * sc);
+        if (j == 0)  // the rest population: FP32 in both storages
+            put_rest<S>(b, (uint32_t)(I.plane * (int64_t)sizeof(P)), (uint32_t)(own * (int64_t)sizeof(P)), va, vb,
+                        false);
+        else
+            Store<S>::put2(b + (int64_t)j * I.plane + own, Store<S>::enc2(va, vb));
     }
 }
 
@@ -365,7 +371,11 @@ __global__ void k_init_sc1(Inst I, const double *__restrict__ rA, double rref, i
         const int xs = wrap(x + CX[j], I.nx, true), ys = wrap(y + CY[j], I.ny, true);
         int64_t src = (int64_t)ys * I.nx + xs;
         if (I.node[(int64_t)ys * I.pitch + xs] & NW_SOLID) src = k;
-        Store1<S>::put(b + (int64_t)j * I.plane + own, Store1<S>::enc((float)(wd[j] * (rA[src] - rref) * sc)));
+        const float v = (float)(wd[j] * (rA[src] - rref) * sc);
+        if (j == 0)  // the rest population: FP32 in both storages
+            put_rest1<S>(b, (uint32_t)(I.plane * (int64_t)sizeof(P)), (uint32_t)(own * (int64_t)sizeof(P)), v, false);
+        else
+            Store1<S>::put(b + (int64_t)j * I.plane + own, Store1<S>::enc(v));
     }
 }
 

@@ -119,6 +119,16 @@ __device__ __forceinline__ float coll_dir(int i, float d, float dr, float rho, f
 // kernels work in storage units (deviation x SC): the power-of-two scale is
 // folded into the equilibrium and source weights and into the density and
 // momentum sums, so loads and stores are bare conversions.
+//
+// The rest population is the exact remainder of the node's incoming mass
+// (the step stores the 8 moving populations first).  With FP16 storage it
+// stays in FP32, in a plane of (A, B) float pairs after the nine FP16 planes
+// (whose plane 0 is then unused): rounding it to FP16 would move the node's
+// mass by up to 2^-12 of the rest population every step, and those roundings
+// add up (4% of a component's mass over 20k steps of a drop on the 30-degree
+// plane), where the FP32 remainder keeps the mass as FP32 storage does.
+// rest_off is the byte offset of a node's rest element from the buffer base,
+// own the node's byte offset within one of the nine planes, pb a plane's bytes.
 template <typename S> struct Store;
 template <> struct Store<float> {
     using P = float2;  // one direction of components A and B
@@ -132,6 +142,7 @@ template <> struct Store<float> {
         f2v t = {v.x, v.y};
         __builtin_nontemporal_store(t, (f2v *)p);
     }
+    static __device__ __forceinline__ uint32_t rest_off(uint32_t, uint32_t own) { return own; }
 };
 template <> struct Store<__half> {
     using P = __half2;
@@ -143,7 +154,26 @@ template <> struct Store<__half> {
     static __device__ __forceinline__ void put2nt(__half2 *p, __half2 v) {
         __builtin_nontemporal_store(__builtin_bit_cast(uint32_t, v), (uint32_t *)p);
     }
+    static __device__ __forceinline__ uint32_t rest_off(uint32_t pb, uint32_t own) { return 9u * pb + 2u * own; }
 };
+
+// The rest population of components A and B at a node, storage units, FP32.
+template <typename S>
+__device__ __forceinline__ float2 ld_rest(const typename Store<S>::P *base, uint32_t pb, uint32_t own) {
+    return *(const float2 *)((const char *)base + Store<S>::rest_off(pb, own));
+}
+template <typename S>
+__device__ __forceinline__ void put_rest(typename Store<S>::P *base, uint32_t pb, uint32_t own, float a, float b,
+                                         bool nt) {
+    float2 *p = (float2 *)((char *)base + Store<S>::rest_off(pb, own));
+    if (nt) {
+        typedef float f2v __attribute__((ext_vector_type(2)));
+        f2v t = {a, b};
+        __builtin_nontemporal_store(t, (f2v *)p);
+    } else {
+        *p = make_float2(a, b);
+    }
+}
 
 template <typename S> __device__ __forceinline__ const S *at(const S *base, uint32_t byte_off) {
     return (const S *)((const char *)base + byte_off);
@@ -285,7 +315,7 @@ template <typename S>
 __device__ __forceinline__ void pull9(const typename Store<S>::P *__restrict__ base, uint32_t pb, const Around &a,
                                       uint32_t w, float dA[9], float dB[9]) {
     const uint32_t own = a.row[1] + a.col[1];
-    float2 v = Store<S>::ld2(at(base, own));
+    float2 v = ld_rest<S>(base, pb, own);
     dA[0] = v.x;
     dB[0] = v.y;
 #pragma unroll
@@ -720,11 +750,7 @@ __device__ __forceinline__ void process_tile(const Inst &I, int tile_x, int tile
             else
                 Store<S>::put2(at(o, (uint32_t)i * pb), q);
         }
-        const auto q0 = Store<S>::enc2((float)(sd[r][0] - soA), (float)(sd[r][1] - soB));
-        if (I.nt)
-            Store<S>::put2nt(o, q0);
-        else
-            Store<S>::put2(o, q0);
+        put_rest<S>(fout, pb, own[r], (float)(sd[r][0] - soA), (float)(sd[r][1] - soB), I.nt != 0);
     }
 }
 

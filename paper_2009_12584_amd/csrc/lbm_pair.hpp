@@ -42,6 +42,9 @@ template <int TY> struct SmemLS {
 // One component of a pair element: loads and stores at byte offset off of a
 // plane base already advanced to the lane's component.
 template <typename S> struct Comp;
+// ld_rest / put_rest address the lane's component c of the node's rest
+// element (FP32 in both storages, see Store): base is already advanced to the
+// component within a pair element of the nine planes.
 template <> struct Comp<float> {
     static __device__ __forceinline__ float ld(const char *p) { return *(const float *)p; }
     static __device__ __forceinline__ float enc(float v) { return v; }
@@ -51,6 +54,12 @@ template <> struct Comp<float> {
             __builtin_nontemporal_store(v, (float *)p);
         else
             *(float *)p = v;
+    }
+    static __device__ __forceinline__ float ld_rest(const char *base, uint32_t, uint32_t own, int) {
+        return *(const float *)(base + own);
+    }
+    static __device__ __forceinline__ void put_rest(char *base, uint32_t, uint32_t own, int, float v, bool nt) {
+        put(base + own, v, nt);
     }
     using E = float;
 };
@@ -64,6 +73,14 @@ template <> struct Comp<__half> {
         else
             *(__half *)p = v;
     }
+    // the float pair at 9 pb + 2 own from the buffer base, component c at
+    // 4 c; base is the buffer base plus 2 c
+    static __device__ __forceinline__ float ld_rest(const char *base, uint32_t pb, uint32_t own, int c) {
+        return *(const float *)(base + 9u * pb + 2u * own + 2u * (uint32_t)c);
+    }
+    static __device__ __forceinline__ void put_rest(char *base, uint32_t pb, uint32_t own, int c, float v, bool nt) {
+        Comp<float>::put(base + 9u * pb + 2u * own + 2u * (uint32_t)c, v, nt);
+    }
     using E = __half;
 };
 
@@ -71,9 +88,9 @@ template <> struct Comp<__half> {
 // bounce-back from the node word); base points at the lane's component of
 // the first pair plane.
 template <typename S>
-__device__ __forceinline__ void pull9c(const char *base, uint32_t pb, const Around &a, uint32_t w, float d[9]) {
+__device__ __forceinline__ void pull9c(const char *base, uint32_t pb, const Around &a, uint32_t w, int c, float d[9]) {
     const uint32_t own = a.row[1] + a.col[1];
-    d[0] = Comp<S>::ld(base + own);
+    d[0] = Comp<S>::ld_rest(base, pb, own, c);
 #pragma unroll
     for (int i = 1; i < 9; ++i) {
         const uint32_t up = a.row[1 - CY[i]] + a.col[1 - CX[i]];
@@ -143,7 +160,7 @@ __device__ __forceinline__ void frame_ls(const Inst &I, SmemLS<TY> &sm, const ch
         float rc = 0.f;
         if (!(wf & NW_SOLID) && (HF == 1 || ring <= 1 || (wf & NW_NEAR))) {
             float df[9];
-            pull9c<S>(fin, pb, around<S>(I, gx, gy, edge), wf, df);
+            pull9c<S>(fin, pb, around<S>(I, gx, gy, edge), wf, c, df);
             rc = rref + fsum9(df) * (1.f / SC);
         }
         sm.rho[c][rho_idx<TY>(hx, hy)] = rc;
@@ -193,7 +210,7 @@ __device__ __forceinline__ void process_tile_ls(const Inst &I, int tile_x, int t
             sm.lf[rt_idx<TY>(lx, ly)] =
                 (uint8_t)(((w[r] & NW_SOLID) ? LF_SOLID : 0) | ((w[r] & NW_IFACE) ? LF_IFACE : 0));
         if (!(w[r] & NW_SOLID)) {
-            pull9c<S>(fin, pb, around<S>(I, gx, gy, edge), w[r], d[r]);
+            pull9c<S>(fin, pb, around<S>(I, gx, gy, edge), w[r], c, d[r]);
         } else {
 #pragma unroll
             for (int i = 0; i < 9; ++i) d[r][i] = 0.f;
@@ -388,7 +405,7 @@ __device__ __forceinline__ void process_tile_ls(const Inst &I, int tile_x, int t
             so += (double)Comp<S>::dec(v);
             Comp<S>::put(o + (uint32_t)i * pb, v, I.nt != 0);
         }
-        Comp<S>::put(o, Comp<S>::enc((float)(sd[r] - so)), I.nt != 0);
+        Comp<S>::put_rest(fout, pb, own[r], c, (float)(sd[r] - so), I.nt != 0);
     }
 }
 

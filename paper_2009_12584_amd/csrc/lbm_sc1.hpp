@@ -30,6 +30,7 @@ template <> struct Store1<float> {
     static __device__ __forceinline__ float dec(float v) { return v; }
     static __device__ __forceinline__ void put(float *p, float v) { *p = v; }
     static __device__ __forceinline__ void putnt(float *p, float v) { __builtin_nontemporal_store(v, p); }
+    static __device__ __forceinline__ uint32_t rest_off(uint32_t, uint32_t own) { return own; }
 };
 template <> struct Store1<__half> {
     using P = __half;
@@ -41,14 +42,30 @@ template <> struct Store1<__half> {
     static __device__ __forceinline__ void putnt(__half *p, __half v) {
         __builtin_nontemporal_store(__builtin_bit_cast(uint16_t, v), (uint16_t *)p);
     }
+    // the rest population in FP32 after the nine FP16 planes, as in Store<__half>
+    static __device__ __forceinline__ uint32_t rest_off(uint32_t pb, uint32_t own) { return 9u * pb + 2u * own; }
 };
+
+// The node's rest population, storage units, FP32 in both storages.
+template <typename S>
+__device__ __forceinline__ float ld_rest1(const typename Store1<S>::P *base, uint32_t pb, uint32_t own) {
+    return *(const float *)((const char *)base + Store1<S>::rest_off(pb, own));
+}
+template <typename S>
+__device__ __forceinline__ void put_rest1(typename Store1<S>::P *base, uint32_t pb, uint32_t own, float v, bool nt) {
+    float *p = (float *)((char *)base + Store1<S>::rest_off(pb, own));
+    if (nt)
+        __builtin_nontemporal_store(v, p);
+    else
+        *p = v;
+}
 
 // Pull of the 9 populations at a fluid node (bounce-back from the node word).
 template <typename S>
 __device__ __forceinline__ void pull9_1(const typename Store1<S>::P *__restrict__ base, uint32_t pb, const Around &a,
                                         uint32_t w, float d[9]) {
     const uint32_t own = a.row[1] + a.col[1];
-    d[0] = Store1<S>::ld(at(base, own));
+    d[0] = ld_rest1<S>(base, pb, own);
 #pragma unroll
     for (int i = 1; i < 9; ++i) {
         const uint32_t up = a.row[1 - CY[i]] + a.col[1 - CX[i]];
@@ -216,11 +233,7 @@ __device__ __forceinline__ void process_tile_sc1(const Inst &I, int tile_x, int 
             else
                 Store1<S>::put(at(o, (uint32_t)i * pb), q);
         }
-        const P q0 = Store1<S>::enc((float)(sd[r] - so));
-        if (I.nt)
-            Store1<S>::putnt(o, q0);
-        else
-            Store1<S>::put(o, q0);
+        put_rest1<S>(fout, pb, own[r], (float)(sd[r] - so), I.nt != 0);
     }
 }
 

@@ -81,4 +81,5 @@ def test_pool_footprint_counts_both_buffers():
     f32 = M.Pool.footprint(512, 256)
     f16 = M.Pool.footprint(512, 256, storage="f16")
     assert f32 >= 2 * 18 * 512 * 256 * 4
-    assert f16 >= 2 * 18 * 512 * 256 * 2 and f16 < f32
+    # FP16: nine FP16 planes and the FP32 rest-population plane per component
+    assert f16 >= 2 * 2 * 512 * 256 * (9 * 2 + 4) and f16 < f32

@@ -284,6 +284,24 @@ def test_mass_conserved_config2_20k_steps(gpu, ora):
     sim.close()
 
 
+def test_fp16_mass_conserved_config2_20k_steps(gpu, ora):
+    """FP16 storage keeps the rest population, which takes each node's exact mass
+    remainder, in FP32: the node's mass then moves by one FP32 rounding per step
+    as with FP32 storage, and the same bound holds.  (With the remainder rounded
+    to FP16 this case lost 4% of a component's mass.)"""
+    c = W.config2()
+    mask = gpu_mask(gpu, c)
+    print("case: config 2, FP16 storage, %d steps" % c.steps, flush=True)
+    sim = gpu.Simulation(mask, c.rhoA0, c.rhoB0, diag_every=1000, drift_tol=1e-4, storage="f16", **c.params())
+    sim.step(c.steps)
+    d = sim.diag()
+    say("fp16 mass drift", [abs(d["mass"][k] - d["mass0"][k]) / d["mass0"][k] for k in range(2)])
+    assert d["flags"] == 0
+    for k in range(2):
+        assert abs(d["mass"][k] - d["mass0"][k]) / d["mass0"][k] < 2e-5
+    sim.close()
+
+
 def test_fp16_storage_error_is_reported_and_small(gpu, ora):
     """FP16 deviation storage: error against the FP64 oracle stated (not pinned to the FP32 bar)."""
     c = W.plane_drop(203, 97, 25.0, 15.0, W.IMPROVED)

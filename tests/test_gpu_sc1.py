@@ -102,6 +102,22 @@ def test_sc1_fp16_storage_error_is_reported_and_small(ora):
     b.close()
 
 
+def test_sc1_fp16_mass_conserved(ora):
+    """The rest population stays FP32 under FP16 storage: mass drift as in FP32."""
+    from paper_2009_12584_amd.sim import Simulation, mask_plane
+
+    c = W.sc1_plane_drop(512, 256, 30.0, 40.0, W.MC)
+    m = mask_plane(c.nx, c.ny, c.geometry[1], c.geometry[2])
+    print("case: sc1 fp16 mass, 512x256, 10000 steps", flush=True)
+    s = Simulation(m, c.rhoA0, None, storage="f16", diag_every=1000, **c.params())
+    s.step(10000)
+    d = s.diag()
+    drift = abs(d["mass"][0] - d["mass0"][0]) / d["mass0"][0]
+    print("  fp16 mass drift %.3e" % drift, flush=True)
+    assert drift < 2e-5
+    s.close()
+
+
 def test_batch_and_pool_reject_the_single_component_model(ora):
     from paper_2009_12584_amd.capi import LBM_EINVAL, LbmError
     from paper_2009_12584_amd.sim import Batch, Pool, mask_plane
