@@ -296,7 +296,7 @@ def main():
                          "which per-dispatch counter collection needs); default 100 (headline), 20 (large grids)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(the slab decomposition is a design note, not code).", file=sys.stderr)
         sys.exit(2)
 

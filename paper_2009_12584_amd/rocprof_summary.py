@@ -126,7 +126,7 @@ def main():
 
     lines = ["# %s" % a.title, "", "kernel source hash: `%s`" % a.kernel_hash, ""]
     if a.commands:
-        lines += ["Commands (run from the repository root on the GPU box):", "", "```"]
+        lines += ["Commands (run from the repository root on an MI355X):", "", "```"]
         lines += [c.strip() for c in a.commands.split(";;") if c.strip()]
         lines += ["```", ""]
     lines += ["## Kernel time (`--kernel-trace --stats`)", "", "| kernel | calls | avg us | % time |",
