@@ -100,6 +100,41 @@ def test_batch_fp16_close_to_fp32(M):
     h.close()
 
 
+def test_fp16_batch_and_pool_match_single_fp16(M):
+    """FP16 storage (moving populations FP16, rest population FP32) has the same
+    layout in the batched, pooled and single forms: results are bit-identical."""
+    cases = small_cases(3, seed=9)
+    masks = masks_of(M, cases)
+    items = [(m, c.rhoA0, c.rhoB0, c.params()) for m, c in zip(masks, cases)]
+    say("fp16 batch/pool vs single", [(c.nx, c.ny, c.bc) for c in cases])
+    b = M.Batch(items, storage="f16")
+    b.step(40)
+    budget = sum(M.Pool.footprint(c.nx, c.ny, storage="f16") for c in cases) + 4096
+    pool = M.Pool(budget, 4, storage="f16")
+    slots = {pool.admit(m, c.rhoA0, c.rhoB0, 40, **c.params()): k for k, (m, c) in enumerate(zip(masks, cases))}
+    assert None not in slots
+    pooled = {}
+    for _ in range(2000):
+        pool.advance(10)
+        for s in pool.poll():
+            pooled[slots[s]] = pool.fields(s)
+            pool.release(s)
+        if len(pooled) == len(cases):
+            break
+        time.sleep(0.002)
+    assert len(pooled) == len(cases)
+    pool.close()
+    for k, (m, c) in enumerate(zip(masks, cases)):
+        s = M.Simulation(m, c.rhoA0, c.rhoB0, storage="f16", **c.params())
+        s.step(40)
+        ref = s.fields()
+        s.close()
+        for x, y, z in zip(b.fields(k), pooled[k], ref):
+            assert np.array_equal(x, z), k
+            assert np.array_equal(y, z), k
+    b.close()
+
+
 def test_pool_results_same_alone_and_in_the_mix(M):
     """Continuous batching: requests join while others run, each stops at its own
     step count, and each result equals the same solve run alone."""

@@ -234,15 +234,18 @@ def test_graph_replay_matches_plain_launches(gpu, ora):
     b.close()
 
 
-def test_checkpoint_resume_bit_exact(gpu, ora):
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_checkpoint_resume_bit_exact(gpu, ora, storage):
+    """The state copy holds the whole population buffer (with FP16 storage, the
+    FP32 rest-population plane too): a resumed run is bit-identical."""
     c = W.plane_drop(200, 100, 30.0, 15.0, W.LLKC, G=3.0)
     mask = gpu_mask(gpu, c)
-    a = gpu.Simulation(mask, c.rhoA0, c.rhoB0, **c.params())
+    a = gpu.Simulation(mask, c.rhoA0, c.rhoB0, storage=storage, **c.params())
     a.step(37)
     st, t = a.get_state()
     a.step(50)
     ref = a.fields()
-    b = gpu.Simulation(mask, c.rhoA0, c.rhoB0, **c.params())
+    b = gpu.Simulation(mask, c.rhoA0, c.rhoB0, storage=storage, **c.params())
     b.set_state(st, t)
     b.step(50)
     for x, y in zip(ref, b.fields()):
