@@ -83,3 +83,25 @@ def test_pool_footprint_counts_both_buffers():
     assert f32 >= 2 * 18 * 512 * 256 * 4
     # FP16: nine FP16 planes and the FP32 rest-population plane per component
     assert f16 >= 2 * 2 * 512 * 256 * (9 * 2 + 4) and f16 < f32
+
+
+@pytest.mark.parametrize("nx,ny,storage", [(8000, 8000, "f32"), (11000, 9000, "f16"), (16000, 16000, "f16")])
+def test_grid_beyond_the_32bit_buffer_offsets_rejected(nx, ny, storage):
+    """A population buffer is addressed with 32-bit byte offsets: FP32 holds 72 B
+    per node, FP16 44 B (nine FP16 planes and the FP32 rest plane, two
+    components).  Larger grids are refused before the mask or densities are
+    read, so one-element host buffers suffice here."""
+    import ctypes
+
+    from paper_2009_12584_amd import capi
+
+    p = capi.make_params(nx, ny, storage=storage)
+    mask = np.ones(1, np.uint8)
+    rho = np.zeros(1)
+    h = ctypes.c_void_p()
+    code = capi.lib().lbm_create(ctypes.byref(p), mask.ctypes.data_as(ctypes.c_void_p),
+                                 rho.ctypes.data_as(ctypes.c_void_p), rho.ctypes.data_as(ctypes.c_void_p), None,
+                                 ctypes.byref(h))
+    assert code == capi.LBM_EINVAL
+    assert "4 GiB" in capi.lib().lbm_last_error(None).decode()
+    assert not h.value
