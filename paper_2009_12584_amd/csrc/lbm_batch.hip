@@ -111,16 +111,25 @@ struct TileLists {
     int rules() const { return (cnt[0] > 0) + (cnt[1] > 0) + (cnt[2] > 0); }
 };
 
-template <typename InstOf>
-TileLists build_tiles(int n, InstOf inst_of, std::vector<int2> &out) {
+// Tiles without a fluid node are left out (fluid_of(k): one flag per logical
+// tile of instance k): such a tile moves no population, and its workgroup
+// would only occupy a slot of the launch.
+template <typename InstOf, typename FluidOf>
+TileLists build_tiles(int n, InstOf inst_of, FluidOf fluid_of, std::vector<int2> &out) {
     TileLists T;
     out.clear();
     for (int k = 0; k < n; ++k) {
         const Inst *I = inst_of(k);
         if (!I) continue;
+        const std::vector<uint8_t> &f = fluid_of(k);
         const int nt = I->tiles_x * I->tiles_y;
-        for (int t = 0; t < nt; ++t) out.push_back(make_int2(k, t));
-        T.cnt[I->bc] += nt;
+        int kept = 0;
+        for (int t = 0; t < nt; ++t)
+            if (f[t]) {
+                out.push_back(make_int2(k, t));
+                ++kept;
+            }
+        T.cnt[I->bc] += kept;
     }
     return T;
 }
@@ -211,6 +220,7 @@ struct Prepared {
     int ntiles = 0;
     int ty = 8;
     int64_t fluid = 0;
+    std::vector<uint8_t> tile_fluid;  // per logical tile: holds a fluid node
 };
 
 // Classification, tile flags, initial populations and step-0 mass for one
@@ -231,6 +241,20 @@ int prepare(Prepared &P, const lbm_params &p, int ty, char *base, const uint8_t 
     int64_t fl = 0;
     for (size_t k = 0; k < n; ++k) fl += mask[k] ? 0 : 1;
     P.fluid = fl;
+    P.tile_fluid.assign(P.ntiles, 0);
+    for (int t = 0; t < P.ntiles; ++t) {
+        int tx, tyy;
+        tile_coords(t, P.I.tiles_x, P.I.tiles_y, P.I.tg, tx, tyy);
+        const int x0 = tx * TX, y0 = tyy * ty, x1 = std::min(x0 + TX, p.nx), y1 = std::min(y0 + ty, p.ny);
+        bool any = false;
+        for (int y = y0; y < y1 && !any; ++y)
+            for (int x = x0; x < x1; ++x)
+                if (!mask[(size_t)y * p.nx + x]) {
+                    any = true;
+                    break;
+                }
+        P.tile_fluid[t] = any ? 1 : 0;
+    }
     P.I.buf[0] = base + P.m.off_buf0;
     P.I.buf[1] = base + P.m.off_buf1;
     uint16_t *word = (uint16_t *)(base + P.m.off_word);
@@ -437,7 +461,9 @@ int lbm_batch_create(int32_t n, const lbm_params *params, const uint8_t *const *
         b->fluid += b->inst[k].fluid;
     }
     st.release();
-    b->lists = build_tiles(n, [&](int k) { return &host_inst[k]; }, tiles);
+    b->lists = build_tiles(
+        n, [&](int k) { return &host_inst[k]; }, [&](int k) -> const std::vector<uint8_t> & { return b->inst[k].tile_fluid; },
+        tiles);
     if (hipMalloc(&b->d_inst, sizeof(Inst) * n) != hipSuccess ||
         hipMalloc(&b->d_tiles, sizeof(int2) * tiles.size()) != hipSuccess) {
         set_err("batch tables: hipMalloc failed");
@@ -625,7 +651,7 @@ static int pool_upload(lbm_pool *P) {
     }
     const TileLists T = build_tiles(
         P->max_slots, [&](int k) { return (P->slots[k].used && P->slots[k].joined) ? &P->slots[k].P.I : nullptr; },
-        tiles);
+        [&](int k) -> const std::vector<uint8_t> & { return P->slots[k].P.tile_fluid; }, tiles);
     if (tiles.size() > P->tiles_cap) {
         // grow: wait for launches that read the old list, then reallocate
         MCLBM_HIP(hipStreamSynchronize(P->stream));

@@ -438,7 +438,7 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
 // columns (TG x 64 nodes = 4 KiB of FP32 per row, long contiguous HBM runs),
 // down each group row by row, so the tile below a tile runs TG tiles later on
 // the same XCD while the rows their density halos share are still in L2.
-__device__ __forceinline__ void tile_coords(int t, int tiles_x, int tiles_y, int tg, int &tx, int &ty) {
+__host__ __device__ __forceinline__ void tile_coords(int t, int tiles_x, int tiles_y, int tg, int &tx, int &ty) {
     const int per_group = tg * tiles_y;
     const int g = t / per_group, r = t - g * per_group;
     const int gw = min(tg, tiles_x - g * tg);
