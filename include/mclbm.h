@@ -249,7 +249,8 @@ int lbm_line_probe(lbm_handle *h, int32_t x0, int32_t y0, int32_t dx, int32_t dy
 int lbm_copy_probe(void *dst, const void *src, size_t bytes, void *stream);
 
 /* ---- batched form: many independent simulations advanced by one launch per
- *      step over a flattened (instance, tile) list ---- */
+ *      step over a flattened (instance, tile) list of the tiles that hold a
+ *      fluid node ---- */
 typedef struct lbm_batch lbm_batch;
 
 /* n instances; arrays of n pointers to the same per-instance inputs as
