@@ -21,6 +21,14 @@
  * Floating point is IEEE double throughout; build with -ffp-contract=off.
  * OpenMP only splits independent per-node loops; it changes no arithmetic.
  *
+ * Pins: every part is checked on the CPU against something other than
+ * itself (tests/test_oracle_pins.py, test_sc1.py, test_contact_angle.py,
+ * test_coalescence.py): exact lattice moments, closed forms of the
+ * equilibrium, source and force, invariants (mass, momentum, mirror symmetry,
+ * fixed points, the 4-node-per-step dependency radius), transport
+ * coefficients, hand-drawn classifications and the values the paper prints.
+ * No function is left without a pin.
+ *
  * Readings where the paper is silent or garbled (all listed in the design
  * notes of the repository):
  *   - Eq. 1 writes f without the index i: read as f_i.
