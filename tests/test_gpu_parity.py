@@ -234,6 +234,41 @@ def test_graph_replay_matches_plain_launches(gpu, ora):
     b.close()
 
 
+def test_numeric_flags_raised_from_a_host_made_state(gpu, ora):
+    """Failure handling, forced from the host: a state whose deviations were
+    scaled (mass no longer that of step 0) raises the drift flag, a state of
+    NaNs the non-finite flag; lbm_diag then returns LBM_ENUMERIC.  The kernels
+    run normally on both (NaN arithmetic does not fault)."""
+    from paper_2009_12584_amd.capi import LBM_ENUMERIC, LbmError
+
+    c = W.plane_drop(160, 80, 20.0, 12.0, W.MC, G=3.0)
+    mask = gpu_mask(gpu, c)
+    sim = gpu.Simulation(mask, c.rhoA0, c.rhoB0, diag_every=10, drift_tol=1e-6, **c.params())
+    sim.step(20)
+    assert sim.diag()["flags"] == 0
+    st, t = sim.get_state()
+    scaled = st.view(np.float32) * np.float32(1.5)
+    sim.set_state(scaled.view(np.uint8), t)
+    sim.step(10)
+    with pytest.raises(LbmError) as e:
+        sim.diag()
+    assert e.value.code == LBM_ENUMERIC
+    d = sim.diag(raise_on_flags=False)
+    assert d["flags"] & 4 and not d["flags"] & 1
+    # a flagged simulation refuses to step on
+    with pytest.raises(LbmError) as e:
+        sim.step(1)
+    assert e.value.code == LBM_ENUMERIC
+    sim.close()
+    sim = gpu.Simulation(mask, c.rhoA0, c.rhoB0, diag_every=10, drift_tol=1e-6, **c.params())
+    nan = np.full(st.size // 4, np.nan, np.float32)
+    sim.set_state(nan.view(np.uint8), t)
+    sim.step(10)
+    d = sim.diag(raise_on_flags=False)
+    assert d["flags"] & 1
+    sim.close()
+
+
 @pytest.mark.parametrize("storage", ["f32", "f16"])
 def test_checkpoint_resume_bit_exact(gpu, ora, storage):
     """The state copy holds the whole population buffer (with FP16 storage, the
