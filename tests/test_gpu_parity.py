@@ -196,8 +196,10 @@ def test_parity_config2_full_size(gpu, ora, ty, lanes):
 
 
 def test_parity_config3_full_size(gpu, ora):
+    """1024 x 1024, disk R = 300 with two drops on it, improved scheme with
+    chi^A != chi^B, at full size for 200 steps."""
     c = W.config3(2)
-    for T, er, eu in compare_run(gpu, ora, c, [1, 10]):
+    for T, er, eu in compare_run(gpu, ora, c, [1, 10, 200]):
         assert er <= RHO_TOL and eu <= U_TOL, (T, er, eu)
 
 
