@@ -47,7 +47,7 @@ class Done:
 
 
 def serve(requests, *, hbm_budget, max_slots, storage="f32", chunk=200, depth=2, keep_fields=False, stream=None,
-          time_scale=1.0, idle_sleep=0.0002, policy="fifo"):
+          time_scale=1.0, idle_sleep=0.0002, policy="fifo", pool_factory=None, clock=None, sleep=None):
     """Run the trace; returns (list of Done, makespan seconds).
 
     At most `depth` chunks are in flight on the device, so a new solve waits
@@ -56,22 +56,27 @@ def serve(requests, *, hbm_budget, max_slots, storage="f32", chunk=200, depth=2,
     waiting request to admit: "fifo" (arrival order) or "sjf" (the smallest
     amount of work, fluid nodes x steps, first); with fewer slots than
     waiting requests, "sjf" finishes short solves early instead of sharing
-    the device among everything that has arrived."""
+    the device among everything that has arrived.  pool_factory, clock and
+    sleep replace the device pool (Pool's constructor and methods), the wall
+    clock (time.perf_counter) and time.sleep, so that the scheduling logic
+    can run against a simulated device and clock."""
     if policy not in ("fifo", "sjf"):
         raise ValueError("policy must be 'fifo' or 'sjf'")
+    now_fn = clock or time.perf_counter
+    sleep_fn = sleep or time.sleep
     reqs = sorted(requests, key=lambda r: r.arrival)
     for r in reqs:
         if not r.fluid:
             r.fluid = int((np.asarray(r.mask) == 0).sum())
-    pool = Pool(hbm_budget, max_slots, storage=storage, stream=stream)
+    pool = (pool_factory or Pool)(hbm_budget, max_slots, storage=storage, stream=stream)
     queue = []
     live = {}
     done = []
     nxt = 0
-    t0 = time.perf_counter()
+    t0 = now_fn()
     try:
         while nxt < len(reqs) or queue or live:
-            now = time.perf_counter() - t0
+            now = now_fn() - t0
             while nxt < len(reqs) and reqs[nxt].arrival * time_scale <= now:
                 queue.append(reqs[nxt])
                 nxt += 1
@@ -82,8 +87,12 @@ def serve(requests, *, hbm_budget, max_slots, storage="f32", chunk=200, depth=2,
                 slot = pool.admit(r.mask, r.rhoA0, r.rhoB0, r.steps, **r.params)
                 if slot is None:
                     break
-                live[slot] = (r, time.perf_counter() - t0)
+                live[slot] = (r, now_fn() - t0)
                 queue.pop(0)
+            if queue and not live:
+                # an empty pool that cannot take the next request never will
+                raise ValueError("request %r does not fit an empty pool (budget %d B, %d slots)"
+                                 % (queue[0].tag, hbm_budget, max_slots))
             if live:
                 launched, completed = pool.progress()
                 if launched - completed < depth * chunk:
@@ -93,13 +102,13 @@ def serve(requests, *, hbm_budget, max_slots, storage="f32", chunk=200, depth=2,
                 r, ta = live.pop(slot)
                 f = pool.fields(slot) if keep_fields else None
                 pool.release(slot)
-                done.append(Done(r.tag, r.arrival * time_scale, ta, time.perf_counter() - t0, r.steps, r.fluid, f))
+                done.append(Done(r.tag, r.arrival * time_scale, ta, now_fn() - t0, r.steps, r.fluid, f))
             if not finished and not queue and nxt < len(reqs) and not live:
                 # nothing to do until the next arrival
-                time.sleep(max(0.0, min(0.01, reqs[nxt].arrival * time_scale - (time.perf_counter() - t0))))
+                sleep_fn(max(0.0, min(0.01, reqs[nxt].arrival * time_scale - (now_fn() - t0))))
             elif not finished and live:
-                time.sleep(idle_sleep)
-        makespan = time.perf_counter() - t0
+                sleep_fn(idle_sleep)
+        makespan = now_fn() - t0
     finally:
         pool.close()
     return done, makespan
