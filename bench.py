@@ -275,6 +275,7 @@ def headline_row(M, torch, case, mask, fluid, nodes, args, probe, launch_config_
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic(kname, "k_step_improved_plane30_512x256.md"), "kernel": kname,
+                     "profile": "profiles/k_step_improved_plane30_512x256.md",
                      "bytes_per_launch": alg_bytes(fluid, nodes),
                      "note": "algorithmic bytes = 144 B per fluid node + 2 B node word per node; the 18.9 MB working set "
                              "stays in L2/Infinity Cache, see roofline_out_of_cache for HBM"},
@@ -342,7 +343,8 @@ def main():
                               "frac_of_copy_probe": round(bach / probe["gbs"], 4), "ms_per_step": round(bms, 4),
                               "fluid_mlups": round(bfl * rb["steps"] / (rb["ms"] * 1e-3) / 1e6, 1), "tile_y": bty,
                               "kernel": kn, "bytes_per_launch": alg_bytes(bfl, big.nx * big.ny, storage),
-                              "traffic": measured_traffic(kn, "k_step_mc_periodic_5600x4000.md")}
+                              "traffic": measured_traffic(kn, "k_step_mc_periodic_5600x4000.md"),
+                              "profile": "profiles/k_step_mc_periodic_5600x4000.md"}
         out["roofline_out_of_cache"] = dict(
             workload="5600x4000 fully periodic G=3 mixture (Martys-Chen path), 3.2 GB ping-pong in FP32",
             bound="hbm", peak=HBM_PEAK_GBS, unit="GB/s", **lrows["f32"], f16=lrows["f16"])
@@ -360,7 +362,8 @@ def main():
             srows[storage] = {"achieved": round(sb / (sms * 1e-3) / 1e9, 1),
                               "frac": round(sb / (sms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "ms_per_step": round(sms, 4),
                               "fluid_mlups": round(sfl * rs["steps"] / (rs["ms"] * 1e-3) / 1e6, 1), "kernel": kn,
-                              "bytes_per_launch": sb, "traffic": measured_traffic(kn, "k_step_sc1_periodic_5600x4000.md")}
+                              "bytes_per_launch": sb, "traffic": measured_traffic(kn, "k_step_sc1_periodic_5600x4000.md"),
+                              "profile": "profiles/k_step_sc1_periodic_5600x4000.md"}
         out["single_component"] = dict(
             workload="5600x4000 fully periodic single-component Shan-Chen at G=-5 (liquid-vapour separation), "
                      "Martys-Chen path", bound="hbm", peak=HBM_PEAK_GBS, unit="GB/s", **srows["f32"], f16=srows["f16"])
