@@ -78,7 +78,7 @@ typedef enum { LBM_AVG_D2Q25 = 0, LBM_AVG_D2Q9 = 1 } lbm_avg;
 typedef enum { LBM_MODEL_TWO = 0, LBM_MODEL_SC1 = 1 } lbm_model;
 /* storage of the populations as deviations d_i = f_i - w_i rho_ref: FP32, or
  * FP16 (scaled by 2^10) for the 8 moving populations with the rest population,
- * which carries each node's exact mass remainder, kept in FP32 */
+ * which carries the remainder of each node's mass, kept in FP32 */
 typedef enum { LBM_STORE_F32 = 0, LBM_STORE_F16 = 1 } lbm_storage;
 
 /* Problem statement of one simulation (Sections 2 and 3.1). */

@@ -25,16 +25,46 @@ AVG_D2Q25, AVG_D2Q9 = 0, 1
 MODEL_TWO, MODEL_SC1 = 0, 1
 
 
+# -march=native for the host that runs it; no contraction and no fast-math,
+# so every IEEE double operation rounds exactly as written, on any CPU
+FLAGS = ["-O3", "-march=native", "-std=c99", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+         "-fno-fast-math", "-Wall"]
+
+
+def host_cpu() -> str:
+    """CPU model of this host (first 'model name' of /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _stamp() -> str:
+    return host_cpu() + "|" + " ".join(FLAGS)
+
+
 def build(force: bool = False) -> str:
-    """Compile liboracle.so with gcc (OpenMP, -ffp-contract=off)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(
-        os.path.getmtime(_SRC), os.path.getmtime(os.path.join(_HERE, "lbm_oracle.h"))
-    ):
+    """Compile liboracle.so with gcc for this host's CPU.  A library built on
+    another CPU model (the stamp file beside it) or older than its sources is
+    rebuilt."""
+    stamp_file = _LIB + ".host"
+    stale = (not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(
+        os.path.getmtime(_SRC), os.path.getmtime(os.path.join(_HERE, "lbm_oracle.h"))))
+    if not stale:
+        try:
+            stale = open(stamp_file).read() != _stamp()
+        except OSError:
+            stale = True
+    if force or stale:
         tmp = _LIB + ".tmp%d" % os.getpid()
-        cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
-               "-fno-fast-math", "-Wall", "-o", tmp, _SRC, "-lm"]
-        subprocess.run(cmd, check=True)
+        subprocess.run(["gcc", *FLAGS, "-o", tmp, _SRC, "-lm"], check=True)
         os.replace(tmp, _LIB)
+        with open(stamp_file, "w") as f:
+            f.write(_stamp())
     return _LIB
 
 

@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmclbm.so")
 SOURCES = ["lbm_single.hip", "lbm_batch.hip", "lbm_analysis.hip"]
-HEADERS = ["lbm_device.hpp", "lbm_common.hpp", "lbm_analysis.hpp"]
+HEADERS = ["lbm_tiling.hpp", "lbm_device.hpp", "lbm_pair.hpp", "lbm_sc1.hpp", "lbm_common.hpp", "lbm_analysis.hpp"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

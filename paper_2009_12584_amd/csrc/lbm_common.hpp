@@ -184,9 +184,9 @@ inline void fill_inst(Inst &I, const lbm_params &p, const double rref[2], int ty
     I.tiles_y = (p.ny + ty - 1) / ty;
     I.plane = (int64_t)p.ny * I.pitch;
     I.periodic = p.periodic;
-    // the compare-and-add wrap covers excursions of a tile plus halo; shorter
-    // periodic sizes wrap by modulo
-    I.small = (((p.periodic & 1u) && p.nx < TX + 2 * FH + 8) || ((p.periodic & 2u) && p.ny < 16 + 2 * FH + 8)) ? 1 : 0;
+    // the compare-and-add wrap covers one excursion of a tile plus its halo;
+    // periodic sizes shorter than that reach wrap by modulo
+    I.small = (((p.periodic & 1u) && needs_modulo(p.nx, TX)) || ((p.periodic & 2u) && needs_modulo(p.ny, ty))) ? 1 : 0;
     I.bc = kernel_bc(p);
     I.avg = p.avg;
     I.omega = (float)(1.0 / p.tau);

@@ -38,14 +38,14 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#define MCLBM_HD __host__ __device__ __forceinline__
+#include "lbm_tiling.hpp"
+
 namespace mclbm {
 
-constexpr int TX = 64;        // tile width: one wavefront per tile row
 // Threads per workgroup for a tile of TY rows: 4 wavefronts, or 8 for the
 // 32-row tile (each thread then owns TY / (threads / 64) rows).
 constexpr int threads_for(int TY) { return TY == 32 ? 512 : 256; }
-constexpr int HMAX = 3;       // widest density halo (improved scheme, D2Q25 average)
-constexpr int FH = HMAX + 1;  // flag halo: a halo node's pull needs its neighbours' phi
 
 // Node word: bit (i-1), i = 1..8, set when neighbour x + c_i is solid or lies
 // beyond a closed border; then the flags below.
@@ -85,7 +85,7 @@ __device__ __forceinline__ void cacc(int i, float v, float &sx, float &sy) {
 //   d* = (1 - omega) d + omega w_i SC (dr + rho eq_i) + w_i SC g S_i,
 //   eq_i = (c_i.u) (3 + 4.5 c_i.u) - 1.5 u.u,
 //   S_i  = (c_i.F) (3 + 9 c_i.u) - 3 u.F,
-// with dr the exact incoming deviation sum, g = 1 - 1/(2 tau) and S_i the
+// with dr the incoming deviation sum, g = 1 - 1/(2 tau) and S_i the
 // Guo source term 3 (c_i - u).F + 9 (c_i.u)(c_i.F) regrouped.  Every step
 // kernel evaluates it through these functions, with explicit multiply-adds in
 // a fixed order, so that the one-lane and two-lane steps round identically.
@@ -120,8 +120,9 @@ __device__ __forceinline__ float coll_dir(int i, float d, float dr, float rho, f
 // folded into the equilibrium and source weights and into the density and
 // momentum sums, so loads and stores are bare conversions.
 //
-// The rest population is the exact remainder of the node's incoming mass
-// (the step stores the 8 moving populations first).  With FP16 storage it
+// The rest population is the remainder of the node's incoming mass after the
+// 8 moving populations are rounded to storage (remainder_term below).  With
+// FP16 storage it
 // stays in FP32, in a plane of (A, B) float pairs after the nine FP16 planes
 // (whose plane 0 is then unused): rounding it to FP16 would move the node's
 // mass by up to 2^-12 of the rest population every step, and those roundings
@@ -182,8 +183,9 @@ template <typename S> __device__ __forceinline__ S *at(S *base, uint32_t byte_of
     return (S *)((char *)base + byte_off);
 }
 
-// Exact sum of the 9 deviations of one component (a double holds the sum of
-// nine floats of this range without rounding), in a fixed order.
+// Sum of the 9 deviations of one component in a fixed order: the density
+// (FP32), and in FP64 the node's exact mass for the diagnostics' total-mass
+// reduction (a double holds the sum of nine floats of this range exactly).
 __device__ __forceinline__ float fsum9(const float d[9]) {
     float s = 0.f;
 #pragma unroll
@@ -196,6 +198,14 @@ __device__ __forceinline__ double dsum9(const float d[9]) {
     for (int i = 0; i < 9; ++i) s += (double)d[i];
     return s;
 }
+
+// One term of the rest population's remainder d_0 + sum_{i=1..8} (d_i - q_i):
+// the incoming deviation d_i less the stored outgoing one q_i of the same
+// direction.  Near equilibrium the two agree to within a factor of 2, so the
+// FP32 difference is exact (Sterbenz) and a node at rest keeps its mass
+// exactly; elsewhere the difference is small against the node's mass and so
+// is its rounding.  Summed in FP32 in direction order by every step kernel.
+__device__ __forceinline__ float remainder_term(float d, float q) { return d - q; }
 
 // Everything one simulation needs on the device.  The single-instance kernels
 // take it by value; the batched kernels read it from a table.
@@ -235,15 +245,6 @@ struct DiagDev {
 struct Fields {  // fields mode outputs, unpadded nx * ny planes, any may be null
     float *rhoA, *rhoB, *ux, *uy, *FAx, *FAy, *FBx, *FBy, *rtA, *rtB;
 };
-
-// Periodic wrap of a coordinate at most a tile plus halo outside [0, n).
-__device__ __forceinline__ int wrap(int g, int n, bool small) {
-    if (small) {
-        g %= n;
-        return g < 0 ? g + n : g;
-    }
-    return g < 0 ? g + n : (g >= n ? g - n : g);
-}
 
 template <int TY> struct Smem {
     static constexpr int RW = TX + 2 * HMAX; // density tile width
@@ -488,8 +489,7 @@ __device__ __forceinline__ void process_tile(const Inst &I, int tile_x, int tile
     const uint32_t pb = (uint32_t)(I.plane * (int64_t)sizeof(P));
     const float rref[2] = {I.rrefA, I.rrefB};
     // tiles whose halo crosses a periodic border need coordinate wraps
-    const bool edge = I.small || ((I.periodic & 1u) && (tx0 - FH < 0 || tx0 + TX + FH > I.nx)) ||
-                      ((I.periodic & 2u) && (ty0 - FH < 0 || ty0 + TY + FH > I.ny));
+    const bool edge = tile_edge(I.small != 0, I.periodic, tx0, ty0, I.nx, I.ny, TY);
 
     const bool need_rt = (BC == BC_IMPROVED) &&
                          (MODE == MODE_FIELDS || (I.tflag[tile_y * I.tiles_x + tile_x] & TF_NEEDS_RT));
@@ -501,7 +501,7 @@ __device__ __forceinline__ void process_tile(const Inst &I, int tile_x, int tile
     const int lx = tid & (TX - 1);
     const int lr = tid >> 6;
     float d[RPT][2][9];
-    double sd[RPT][2];  // exact incoming deviation sums, storage units
+    float sd[RPT][2];   // incoming deviation sums, storage units
     uint32_t w[RPT];    // node words
     uint32_t own[RPT];  // byte offset of the owned node in a plane
     bool owned[RPT];
@@ -555,11 +555,11 @@ __device__ __forceinline__ void process_tile(const Inst &I, int tile_x, int tile
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
         const int ly = lr + RPP * r;
-        sd[r][0] = dsum9(d[r][0]);
-        sd[r][1] = dsum9(d[r][1]);
+        sd[r][0] = fsum9(d[r][0]);
+        sd[r][1] = fsum9(d[r][1]);
         const bool fl = !(w[r] & NW_SOLID);
-        sm.rho[0][rho_idx<TY>(lx, ly)] = fl ? rref[0] + fsum9(d[r][0]) * (1.f / SC) : 0.f;
-        sm.rho[1][rho_idx<TY>(lx, ly)] = fl ? rref[1] + fsum9(d[r][1]) * (1.f / SC) : 0.f;
+        sm.rho[0][rho_idx<TY>(lx, ly)] = fl ? rref[0] + sd[r][0] * (1.f / SC) : 0.f;
+        sm.rho[1][rho_idx<TY>(lx, ly)] = fl ? rref[1] + sd[r][1] * (1.f / SC) : 0.f;
     }
     __syncthreads();
 
@@ -699,9 +699,9 @@ __device__ __forceinline__ void process_tile(const Inst &I, int tile_x, int tile
         const float uy = (jy + 0.5f * (FAy + FBy)) * inv;
 
         if (DIAG) {
-            // exact per-node mass: reference plus the exact deviation sum
-            acc.mA += (double)rref[0] + sd[r][0] * (double)(1.f / SC);
-            acc.mB += (double)rref[1] + sd[r][1] * (double)(1.f / SC);
+            // total-mass reduction in FP64: reference plus the exact deviation sum
+            acc.mA += (double)rref[0] + dsum9(d[r][0]) * (double)(1.f / SC);
+            acc.mB += (double)rref[1] + dsum9(d[r][1]) * (double)(1.f / SC);
             acc.px += (double)rt * (double)ux;
             acc.py += (double)rt * (double)uy;
             acc.u2max = fmaxf(acc.u2max, ux * ux + uy * uy);
@@ -723,17 +723,18 @@ __device__ __forceinline__ void process_tile(const Inst &I, int tile_x, int tile
         }
         // Eqs. 1, 2, 4 in deviation form, in storage units.  The 8 moving
         // populations are computed and rounded to storage; the rest population
-        // takes the exact remainder of the incoming deviation sum, so the stored
-        // node mass equals the incoming one up to a single rounding (no
-        // systematic FP32 mass drift).  The velocity terms of the equilibrium
-        // are common to both components.
+        // takes the remainder of the node's incoming mass, d_0 + sum_i (d_i - q_i)
+        // over the stored q_i (remainder()), so that a step moves each node's
+        // mass unchanged up to roundings of the small differences d_i - q_i
+        // (no systematic FP32 mass drift).  The velocity terms of the
+        // equilibrium are common to both components.
         const float uu = ux * ux + uy * uy;
         const float m15uu = -1.5f * uu;
         const float uFA3 = 3.f * (ux * FAx + uy * FAy), uFB3 = 3.f * (ux * FBx + uy * FBy);
-        const float drA = (float)sd[r][0] * (1.f / SC), drB = (float)sd[r][1] * (1.f / SC);
+        const float drA = sd[r][0] * (1.f / SC), drB = sd[r][1] * (1.f / SC);
         const CollK ck = coll_consts(I.omega, I.guo, SC);
         P *o = at(fout, own[r]);
-        double soA = 0.0, soB = 0.0;
+        float eA = 0.f, eB = 0.f;
 #pragma unroll
         for (int i = 1; i < 9; ++i) {
             const float cu = cdot(i, ux, uy);
@@ -743,14 +744,14 @@ __device__ __forceinline__ void process_tile(const Inst &I, int tile_x, int tile
             const auto q = Store<S>::enc2(coll_dir(i, d[r][0][i], drA, ra, eq, t, cFA, uFA3, ck),
                                           coll_dir(i, d[r][1][i], drB, rb, eq, t, cFB, uFB3, ck));
             const float2 qd = Store<S>::dec2(q);
-            soA += (double)qd.x;
-            soB += (double)qd.y;
+            eA += remainder_term(d[r][0][i], qd.x);
+            eB += remainder_term(d[r][1][i], qd.y);
             if (I.nt)
                 Store<S>::put2nt(at(o, (uint32_t)i * pb), q);
             else
                 Store<S>::put2(at(o, (uint32_t)i * pb), q);
         }
-        put_rest<S>(fout, pb, own[r], (float)(sd[r][0] - soA), (float)(sd[r][1] - soB), I.nt != 0);
+        put_rest<S>(fout, pb, own[r], d[r][0][0] + eA, d[r][1][0] + eB, I.nt != 0);
     }
 }
 

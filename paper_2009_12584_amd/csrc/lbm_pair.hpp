@@ -186,8 +186,7 @@ __device__ __forceinline__ void process_tile_ls(const Inst &I, int tile_x, int t
     char *fout = (char *)I.buf[parity ^ 1] + c * sizeof(S);
     const uint32_t pb = (uint32_t)(I.plane * (int64_t)sizeof(P));
     const float rref = c == 0 ? I.rrefA : I.rrefB;
-    const bool edge = I.small || ((I.periodic & 1u) && (tx0 - FH < 0 || tx0 + TX + FH > I.nx)) ||
-                      ((I.periodic & 2u) && (ty0 - FH < 0 || ty0 + TY + FH > I.ny));
+    const bool edge = tile_edge(I.small != 0, I.periodic, tx0, ty0, I.nx, I.ny, TY);
     const bool need_rt = (BC == BC_IMPROVED) &&
                          (MODE == MODE_FIELDS || (I.tflag[tile_y * I.tiles_x + tile_x] & TF_NEEDS_RT));
 
@@ -195,7 +194,7 @@ __device__ __forceinline__ void process_tile_ls(const Inst &I, int tile_x, int t
     const int lx = q & (TX - 1);
     const int lr = q / TX;
     float d[RPT][9];
-    double sd[RPT];     // exact incoming deviation sum, storage units
+    float sd[RPT];      // incoming deviation sum, storage units
     uint32_t w[RPT];    // node words
     uint32_t own[RPT];  // byte offset of the node's pair element in a plane
     bool owned[RPT];
@@ -244,8 +243,8 @@ __device__ __forceinline__ void process_tile_ls(const Inst &I, int tile_x, int t
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
         const int ly = lr + RPP * r;
-        sd[r] = dsum9(d[r]);
-        sm.rho[c][rho_idx<TY>(lx, ly)] = (w[r] & NW_SOLID) ? 0.f : rref + fsum9(d[r]) * (1.f / SC);
+        sd[r] = fsum9(d[r]);
+        sm.rho[c][rho_idx<TY>(lx, ly)] = (w[r] & NW_SOLID) ? 0.f : rref + sd[r] * (1.f / SC);
     }
     __syncthreads();
 
@@ -359,7 +358,8 @@ __device__ __forceinline__ void process_tile_ls(const Inst &I, int tile_x, int t
         const float uy = (sjy + 0.5f * (FAy + FBy)) * inv;
 
         if (DIAG) {
-            const double m = (double)rref + sd[r] * (double)(1.f / SC);
+            // total-mass reduction in FP64: reference plus the exact deviation sum
+            const double m = (double)rref + dsum9(d[r]) * (double)(1.f / SC);
             if (c == 0) {
                 acc.mA += m;
                 acc.px += (double)(ra + rb) * (double)ux;
@@ -388,24 +388,25 @@ __device__ __forceinline__ void process_tile_ls(const Inst &I, int tile_x, int t
             continue;
         }
         // Eqs. 1, 2, 4 in deviation form and storage units; the rest
-        // population takes the exact remainder of the incoming sum
+        // population takes the remainder d_0 + sum_i (d_i - q_i) of the
+        // node's incoming mass, as in the one-lane step
         const float uu = ux * ux + uy * uy;
         const float m15uu = -1.5f * uu;
         const float uF3 = 3.f * (ux * Fx + uy * Fy);
-        const float dr = (float)sd[r] * (1.f / SC);
+        const float dr = sd[r] * (1.f / SC);
         const CollK ck = coll_consts(I.omega, I.guo, SC);
         char *o = fout + own[r];
-        double so = 0.0;
+        float e = 0.f;
 #pragma unroll
         for (int i = 1; i < 9; ++i) {
             const float cu = cdot(i, ux, uy);
             const float eq = coll_eq(cu, m15uu), t = coll_t(cu);
             const float cF = cdot(i, Fx, Fy);
             const auto v = Comp<S>::enc(coll_dir(i, d[r][i], dr, rm, eq, t, cF, uF3, ck));
-            so += (double)Comp<S>::dec(v);
+            e += remainder_term(d[r][i], Comp<S>::dec(v));
             Comp<S>::put(o + (uint32_t)i * pb, v, I.nt != 0);
         }
-        Comp<S>::put_rest(fout, pb, own[r], c, (float)(sd[r] - so), I.nt != 0);
+        Comp<S>::put_rest(fout, pb, own[r], c, d[r][0] + e, I.nt != 0);
     }
 }
 

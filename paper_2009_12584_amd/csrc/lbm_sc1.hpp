@@ -90,15 +90,14 @@ __device__ __forceinline__ void process_tile_sc1(const Inst &I, int tile_x, int 
     const P *__restrict__ fin = (const P *)I.buf[parity];
     P *__restrict__ fout = (P *)I.buf[parity ^ 1];
     const uint32_t pb = (uint32_t)(I.plane * (int64_t)sizeof(P));
-    const double rref = (double)I.rrefA;
-    const bool edge = I.small || ((I.periodic & 1u) && (tx0 - FH < 0 || tx0 + TX + FH > I.nx)) ||
-                      ((I.periodic & 2u) && (ty0 - FH < 0 || ty0 + TY + FH > I.ny));
+    const float rref = I.rrefA;
+    const bool edge = tile_edge(I.small != 0, I.periodic, tx0, ty0, I.nx, I.ny, TY);
 
     // ---- owned rectangle: populations in registers
     const int lx = tid & (TX - 1);
     const int lr = tid >> 6;
     float d[RPT][9];
-    double sd[RPT];
+    float sd[RPT];
     uint32_t w[RPT], own[RPT];
     bool owned[RPT];
     // node words of the owned nodes and of this thread's frame slot first
@@ -136,7 +135,7 @@ __device__ __forceinline__ void process_tile_sc1(const Inst &I, int tile_x, int 
         if (!(wf & NW_SOLID)) {
             float df[9];
             pull9_1<S>(fin, pb, around<S, 1>(I, gx, gy, edge), wf, df);
-            ps = psi_of((float)(rref + dsum9(df) * (double)(1.f / SC)), I.psi0);
+            ps = psi_of(rref + fsum9(df) * (1.f / SC), I.psi0);
         }
         sm.rho[0][rho_idx<TY>(hx, hy)] = ps;
     }
@@ -146,8 +145,8 @@ __device__ __forceinline__ void process_tile_sc1(const Inst &I, int tile_x, int 
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
         const int ly = lr + RPP * r;
-        sd[r] = dsum9(d[r]);
-        rho[r] = (float)(rref + sd[r] * (double)(1.f / SC));
+        sd[r] = fsum9(d[r]);
+        rho[r] = rref + sd[r] * (1.f / SC);
         sm.rho[0][rho_idx<TY>(lx, ly)] = (w[r] & NW_SOLID) ? 0.f : psi_of(rho[r], I.psi0);
     }
     __syncthreads();
@@ -193,7 +192,8 @@ __device__ __forceinline__ void process_tile_sc1(const Inst &I, int tile_x, int 
         const float uy = (jy + 0.5f * Fy) * inv;
 
         if (DIAG) {
-            acc.mA += rref + sd[r] * (double)(1.f / SC);
+            // total-mass reduction in FP64: reference plus the exact deviation sum
+            acc.mA += (double)rref + dsum9(d[r]) * (double)(1.f / SC);
             acc.px += (double)ra * (double)ux;
             acc.py += (double)ra * (double)uy;
             acc.u2max = fmaxf(acc.u2max, ux * ux + uy * uy);
@@ -214,26 +214,27 @@ __device__ __forceinline__ void process_tile_sc1(const Inst &I, int tile_x, int 
             continue;
         }
         // Eqs. 1, 2, 4 in deviation form and storage units; the rest
-        // population takes the exact remainder of the incoming sum
+        // population takes the remainder d_0 + sum_i (d_i - q_i) of the
+        // node's incoming mass, as in the two-component step
         const float uu = ux * ux + uy * uy;
         const float m15uu = -1.5f * uu;
         const float uF3 = 3.f * (ux * Fx + uy * Fy);
-        const float dr = (float)sd[r] * (1.f / SC);
+        const float dr = sd[r] * (1.f / SC);
         const CollK ck = coll_consts(I.omega, I.guo, SC);
         P *o = at(fout, own[r]);
-        double so = 0.0;
+        float e = 0.f;
 #pragma unroll
         for (int i = 1; i < 9; ++i) {
             const float cu = cdot(i, ux, uy);
             const float cF = cdot(i, Fx, Fy);
             const P q = Store1<S>::enc(coll_dir(i, d[r][i], dr, ra, coll_eq(cu, m15uu), coll_t(cu), cF, uF3, ck));
-            so += (double)Store1<S>::dec(q);
+            e += remainder_term(d[r][i], Store1<S>::dec(q));
             if (I.nt)
                 Store1<S>::putnt(at(o, (uint32_t)i * pb), q);
             else
                 Store1<S>::put(at(o, (uint32_t)i * pb), q);
         }
-        put_rest1<S>(fout, pb, own[r], (float)(sd[r] - so), I.nt != 0);
+        put_rest1<S>(fout, pb, own[r], d[r][0] + e, I.nt != 0);
     }
 }
 

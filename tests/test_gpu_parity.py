@@ -171,6 +171,27 @@ def test_parity_periodic_wrap(gpu, ora, periodic):
         assert er <= RHO_TOL and eu <= U_TOL, (T, er, eu)
 
 
+@pytest.mark.parametrize("nx,ny,periodic,ty", [(130, 33, 2, 32), (65, 40, 3, 8), (67, 37, 3, 16)],
+                         ids=["y33-tile32", "x65-tile8", "x67-tile16"])
+def test_parity_periodic_size_just_above_a_tile(gpu, ora, nx, ny, periodic, ty):
+    """A periodic size just above one tile: the last tile's rows (or columns)
+    beyond the lattice and its 4-node reach wrap past the far side, which the
+    compare-and-add wrap cannot map back (33 rows in 32-row tiles reach row 67);
+    such sizes must take the modulo wrap.  Improved scheme with an obstacle, so
+    the 3-node density frame is in use."""
+    m = np.zeros((ny, nx), np.uint8)
+    if not periodic & 1:
+        m[:, 0] = m[:, -1] = 1
+    if not periodic & 2:
+        m[0, :] = m[-1, :] = 1
+    m[10:18, 30:37] = 1
+    rA, rB = W.random_mixture(nx, ny, seed=11, amp=0.1)
+    c = W.Case("wrap-%dx%d" % (nx, ny), nx, ny, periodic=periodic, tau=0.8, G=2.5, bc=W.IMPROVED, chiA=1.1,
+               chiB=0.9, rhoA0=rA, rhoB0=rB, mask_user=m)
+    for T, er, eu in compare_run(gpu, ora, c, [1, 30, 120], tile_y=ty):
+        assert er <= RHO_TOL and eu <= U_TOL, (T, er, eu)
+
+
 def test_parity_tiny_periodic_box_smaller_than_tile(gpu, ora):
     nx, ny = 5, 3
     rA, rB = W.random_mixture(nx, ny, seed=2, amp=0.2)

@@ -306,6 +306,67 @@ def test_virtual_density_linear_response_reveals_stencil(ora):
             assert tA2[1, x] - tA[1, x] == pytest.approx(expect, rel=1e-9)
 
 
+def test_virtual_density_d2q9_linear_response(ora):
+    """The D2Q9 branch of Eq. 7 (the alternative averaging lattice named after
+    Eq. 7): the average runs over the fluid nodes of the first belt only, with
+    the D2Q9 weights of Section 2 (1/9 on the axes, 1/36 on the diagonals).
+    Below a flat wall an interface solid at row 1 sees the fluid nodes
+    (x-1, 2), (x, 2), (x+1, 2), so its normalisation is 1/9 + 2/36 = 1/6, and
+    perturbing the fluid node (px, 2) by d moves rho~ at (px, 1) by
+    chi (1/9) d / (1/6) and at (px +- 1, 1) by chi (1/36) d / (1/6).  A node of
+    the second belt, (px, 3), changes nothing.  Swapped axis and diagonal
+    weights, or the D2Q25 table in this branch, fail one of these."""
+    nx, ny = 16, 12
+    m = W.rows_mask(nx, ny, (0, 1, ny - 1))
+    rA = np.full((ny, nx), 0.5)
+    rB = np.full((ny, nx), 0.3)
+    px, d, chi = 7, 1e-3, 1.5
+    w9 = {int(k): float(Fraction(v)) for k, v in GOLDEN["d2q9_weights"]["value"].items()}
+    kw = dict(tau=1.0, G=0.9, bc=W.IMPROVED, chiA=chi, chiB=1.0, periodic=1, avg=1)
+    tA, _ = ora.Oracle(m, rA, rB, **kw).virtual_density()
+    first = rA.copy()
+    first[2, px] += d
+    tA1, _ = ora.Oracle(m, first, rB, **kw).virtual_density()
+    den = w9[1] + 2 * w9[2]
+    assert den == pytest.approx(1.0 / 6.0, rel=1e-15)
+    delta = tA1 - tA
+    changed = {(int(y), int(x)) for y, x in np.argwhere(np.abs(delta) > 1e-15)}
+    assert changed == {(1, px - 1), (1, px), (1, px + 1)}
+    assert delta[1, px] == pytest.approx(chi * w9[1] * d / den, rel=1e-9)
+    assert delta[1, px - 1] == pytest.approx(chi * w9[2] * d / den, rel=1e-9)
+    assert delta[1, px + 1] == pytest.approx(chi * w9[2] * d / den, rel=1e-9)
+    second = rA.copy()
+    second[3, px] += d
+    tA2, _ = ora.Oracle(m, second, rB, **kw).virtual_density()
+    assert np.array_equal(tA2, tA)
+    # the D2Q25 average of the same solids does see the second belt
+    tA25, _ = ora.Oracle(m, rA, rB, **dict(kw, avg=0)).virtual_density()
+    tA25b, _ = ora.Oracle(m, second, rB, **dict(kw, avg=0)).virtual_density()
+    assert np.abs(tA25b - tA25).max() > 1e-6
+
+
+def test_virtual_density_d2q9_internal_corner_takes_one_fluid_node(ora):
+    """Section 3.2: with the D2Q9 average an internal corner of a stair wall
+    sees a single fluid node, the diagonal one, so there rho~ = chi rho of that
+    node exactly, whatever the weights; the D2Q25 average also takes the second
+    belt.  L-shaped wall: solid for x <= 3 or y <= 3 (and the closed borders);
+    the corner solid (3, 3) has only (4, 4) fluid among its 8 neighbours."""
+    nx, ny = 14, 12
+    yy, xx = np.mgrid[0:ny, 0:nx]
+    m = ((xx <= 3) | (yy <= 3) | (xx == nx - 1) | (yy == ny - 1)).astype(np.uint8)
+    rng = np.random.default_rng(5)
+    rA = 0.2 + 0.6 * rng.random((ny, nx))
+    rB = 0.1 + 0.3 * rng.random((ny, nx))
+    nbr, cls = ora.classify(m, 0)
+    assert cls[3, 3] == 2 and bin(int(nbr[3, 3])).count("1") == 7
+    kw = dict(tau=1.0, G=0.9, bc=W.IMPROVED, chiA=1.2, chiB=0.7, periodic=0)
+    tA, tB = ora.Oracle(m, rA, rB, avg=1, **kw).virtual_density()
+    assert tA[3, 3] == pytest.approx(1.2 * rA[4, 4], rel=1e-14)
+    assert tB[3, 3] == pytest.approx(0.7 * rB[4, 4], rel=1e-14)
+    tA25, _ = ora.Oracle(m, rA, rB, avg=0, **kw).virtual_density()
+    assert abs(tA25[3, 3] - 1.2 * rA[4, 4]) > 1e-3
+
+
 # --------------------------------------------------- closed-form dynamics
 
 def test_uniform_mixture_is_fixed_point(ora):
