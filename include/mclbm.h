@@ -96,10 +96,14 @@ typedef struct {
     int32_t storage;     /* lbm_storage */
     double rho_ref[2];   /* deviation reference per component; NaN = the smallest
                             initial density over fluid nodes */
-    int32_t diag_every;  /* fused FP64 diagnostics every k steps; 0 = only on lbm_diag */
+    int32_t diag_every;  /* fused FP64 diagnostics after every step t with
+                            (t + 1) % diag_every == 0, in graphs too; 0 = only on lbm_diag */
     double drift_tol;    /* relative mass drift that flags LBM_ENUMERIC; <= 0 = off */
-    int32_t graph_steps; /* > 0: lbm_step replays a captured HIP graph of this many
-                            steps (rounded up to even); 0 = plain launches */
+    int32_t graph_steps; /* > 0: lbm_step replays a captured HIP graph of G steps
+                            (graph_steps rounded up to even) whenever the time is a
+                            multiple of G and at least G steps remain, plain launches
+                            otherwise; G and diag_every must divide one another;
+                            0 = plain launches only */
     int32_t tile_y;      /* rows per tile: 0 = default (8), else 4, 8, 16 or 32 (512-thread workgroups) */
     int32_t model;       /* lbm_model */
     double psi_rho0;     /* single-component model: the density scale of psi */
@@ -130,8 +134,9 @@ void lbm_params_default(lbm_params *p);
  * each >= 0 and finite, their sum > 0).  The initial populations are the rest
  * equilibrium w_i rho_0.  stream: a hipStream_t or NULL.  On success *out
  * owns device memory until lbm_destroy.  Errors: LBM_EINVAL (sizes, tau,
- * enum values, fluid on a non-periodic border, bad densities), LBM_ENOMEM,
- * LBM_EDEVICE.  Synchronises the stream before returning. */
+ * enum values, fluid on a non-periodic border, bad densities, graph_steps and
+ * diag_every that do not divide one another), LBM_ENOMEM, LBM_EDEVICE.
+ * Synchronises the stream before returning. */
 int lbm_create(const lbm_params *p, const uint8_t *mask, const double *rhoA0, const double *rhoB0,
                void *stream, lbm_handle **out);
 
@@ -142,6 +147,10 @@ int lbm_step(lbm_handle *h, int64_t nsteps);
 
 /* Current time step count. */
 int64_t lbm_time(const lbm_handle *h);
+
+/* Steps run so far by graph replays and by plain launches (either may be
+ * NULL): how lbm_step actually launched the work. */
+int lbm_launch_counts(const lbm_handle *h, int64_t *graph_steps, int64_t *plain_steps);
 
 /* Fields at the current time into caller-owned host arrays of nx*ny doubles
  * (any may be NULL): densities, and the velocity of Eq. 3.  Synchronises. */
@@ -248,20 +257,38 @@ int lbm_line_probe(lbm_handle *h, int32_t x0, int32_t y0, int32_t dx, int32_t dy
  * equal byte counts; its PMC byte counters calibrate the step kernel's. */
 int lbm_copy_probe(void *dst, const void *src, size_t bytes, void *stream);
 
+/* Bytes of the raw state (one population buffer) of a simulation with these
+ * parameters: the size lbm_get_state, lbm_batch_get_state and
+ * lbm_pool_get_state copy.  0 for invalid sizes. */
+size_t lbm_params_state_bytes(const lbm_params *p);
+
 /* ---- batched form: many independent simulations advanced by one launch per
  *      step over a flattened (instance, tile) list of the tiles that hold a
  *      fluid node ---- */
 typedef struct lbm_batch lbm_batch;
 
 /* n instances; arrays of n pointers to the same per-instance inputs as
- * lbm_create.  Every instance must use the same storage.  graph_steps > 0
- * captures that many steps of the whole batch in one HIP graph. */
+ * lbm_create.  Every instance must use the same storage, tile rows, lanes and
+ * diag_every (the fused diagnostics run for all instances together, each
+ * reduced into its own targets with its own drift_tol).  graph_steps > 0
+ * captures graphs of the whole batch, replayed as lbm_step does. */
 int lbm_batch_create(int32_t n, const lbm_params *params, const uint8_t *const *masks,
                      const double *const *rhoA0, const double *const *rhoB0, void *stream,
                      int32_t graph_steps, lbm_batch **out);
 int lbm_batch_step(lbm_batch *b, int64_t nsteps);
+/* Steps run by graph replays and by plain launches (either may be NULL). */
+int lbm_batch_launch_counts(const lbm_batch *b, int64_t *graph_steps, int64_t *plain_steps);
+/* Fields of instance idx (as lbm_fields); the pass also reduces that
+ * instance's diagnostics, and a broken instance returns LBM_ENUMERIC with its
+ * fields written.  The other instances are unaffected. */
 int lbm_batch_fields(lbm_batch *b, int32_t idx, double *rhoA, double *rhoB, double *ux, double *uy);
+/* Diagnostics of instance idx at the current time (as lbm_diag), including the
+ * flags its cadence reductions set; LBM_ENUMERIC for a broken instance. */
 int lbm_batch_diag(lbm_batch *b, int32_t idx, lbm_diag_t *out);
+/* Raw state of instance idx (lbm_params_state_bytes bytes) to or from the
+ * host, at the batch's current time.  Synchronise the batch's stream. */
+int lbm_batch_get_state(lbm_batch *b, int32_t idx, void *host);
+int lbm_batch_set_state(lbm_batch *b, int32_t idx, const void *host);
 /* lbm_contour_fit for instance idx of the batch. */
 int lbm_batch_contour_fit(lbm_batch *b, int32_t idx, const lbm_contour_req *req, lbm_circle_t *out);
 int64_t lbm_batch_fluid_nodes(const lbm_batch *b);
@@ -271,9 +298,13 @@ int lbm_batch_destroy(lbm_batch *b);
 typedef struct lbm_pool lbm_pool;
 
 /* hbm_budget: bytes of device memory the pool may hold for simulation state;
- * max_slots: most simultaneous solves; storage: lbm_storage for all slots. */
-int lbm_pool_create(size_t hbm_budget, int32_t max_slots, int32_t storage, void *stream,
-                    lbm_pool **out);
+ * max_slots: most simultaneous solves; storage: lbm_storage for all slots;
+ * diag_every: fused FP64 diagnostics (each slot reduced into its own targets,
+ * drift against its own step 0 with the drift_tol it was admitted with) after
+ * every launch L with (L + 1) % diag_every == 0 of the pool's launch counter;
+ * 0 = only when a slot's fields or diagnostics are read. */
+int lbm_pool_create(size_t hbm_budget, int32_t max_slots, int32_t storage, int32_t diag_every,
+                    void *stream, lbm_pool **out);
 /* Bytes of device memory one solve of these parameters occupies. */
 size_t lbm_pool_footprint(const lbm_params *p);
 /* Admits one solve of nsteps steps.  Returns LBM_EAGAIN when neither a slot
@@ -283,10 +314,28 @@ int lbm_pool_admit(lbm_pool *pool, const lbm_params *p, const uint8_t *mask, con
 /* Advances every active, unfinished slot by up to chunk steps in one batched
  * launch per step; a slot stops exactly at its own step count. */
 int lbm_pool_advance(lbm_pool *pool, int64_t chunk);
-/* Writes up to max ids of finished, unreleased slots; *n receives the count. */
+/* Writes up to max ids of finished, unreleased slots; *n receives the count.
+ * A slot whose flags a completed diagnostic launch has set (non-finite or
+ * negative density, drift) is reported too and stops advancing from the next
+ * launch on; the other slots go on. */
 int lbm_pool_poll(lbm_pool *pool, int32_t *slots, int32_t max, int32_t *n);
+/* What the host knows of a slot without waiting on the device: LBM_OK,
+ * LBM_ENUMERIC once lbm_pool_poll has reported it broken, LBM_ENOTFOUND for a
+ * free slot. */
+int lbm_pool_status(const lbm_pool *pool, int32_t slot);
+/* Fields of a slot at its last step (as lbm_fields); returns LBM_ENUMERIC,
+ * with the fields written, for a broken slot. */
 int lbm_pool_fields(lbm_pool *pool, int32_t slot, double *rhoA, double *rhoB, double *ux,
                     double *uy);
+/* Diagnostics of a slot at its current step (as lbm_diag; step counts the
+ * slot's own steps).  Synchronises the pool's stream.  LBM_ENUMERIC for a
+ * broken slot. */
+int lbm_pool_diag(lbm_pool *pool, int32_t slot, lbm_diag_t *out);
+/* Raw state of a slot (lbm_params_state_bytes bytes) to or from the host: the
+ * populations its next launch reads (before it first advances, the initial
+ * state), for checkpoint and resume.  Synchronises the pool's streams. */
+int lbm_pool_get_state(lbm_pool *pool, int32_t slot, void *host);
+int lbm_pool_set_state(lbm_pool *pool, int32_t slot, const void *host);
 int lbm_pool_release(lbm_pool *pool, int32_t slot);
 int lbm_pool_stats(const lbm_pool *pool, int32_t *active, size_t *bytes_in_use);
 /* Launches enqueued so far and launches the device has completed; a serving

@@ -387,7 +387,7 @@ static void macroscopic(ora_state *s) {
                 const double psi = r0 * (1.0 - exp(-s->rho[0][k] / r0));
                 double scx = 0.0, scy = 0.0, adx = 0.0, ady = 0.0;
                 for (int i = 1; i < 9; ++i) {
-                    long kn;
+                    long kn = k; /* a fluid node's neighbours lie inside the domain */
                     neighbour(s, x, y, CX[i], CY[i], &kn);
                     if (!s->phi[kn]) {
                         const double pn = r0 * (1.0 - exp(-s->rho[0][kn] / r0));
@@ -409,7 +409,7 @@ static void macroscopic(ora_state *s) {
                 double scx = 0.0, scy = 0.0; /* sum_i w_i psi^sbar(x+c_i) c_i over fluid neighbours */
                 double adx = 0.0, ady = 0.0; /* sum_i w_i S^sbar(x+c_i) c_i over solid neighbours */
                 for (int i = 1; i < 9; ++i) {
-                    long kn;
+                    long kn = k; /* a fluid node's neighbours lie inside the domain */
                     neighbour(s, x, y, CX[i], CY[i], &kn); /* fluid never touches a closed border */
                     if (!s->phi[kn]) {
                         scx += W9[i] * s->rho[cb][kn] * CX[i];
@@ -467,7 +467,7 @@ static void collide_stream(ora_state *s) {
                 for (int i = 0; i < 9; ++i) {
                     const double fi = s->f[c][i][k];
                     const double post = fi - (fi - feq[i]) / tau + S[i]; /* Eq. 1 */
-                    long kn;
+                    long kn = k; /* a fluid node's neighbours lie inside the domain */
                     neighbour(s, x, y, CX[i], CY[i], &kn);
                     if (s->phi[kn])
                         s->g[c][OPP[i]][k] = post; /* half-way bounce-back */

@@ -20,14 +20,15 @@ MODEL_TWO, MODEL_SC1 = 0, 1
 
 # every symbol include/mclbm.h declares
 EXPORTS = [
-    "lbm_params_default", "lbm_create", "lbm_step", "lbm_time", "lbm_fields", "lbm_fields_device",
+    "lbm_params_default", "lbm_create", "lbm_step", "lbm_time", "lbm_launch_counts", "lbm_fields", "lbm_fields_device",
     "lbm_forces", "lbm_diag", "lbm_classify", "lbm_state_bytes", "lbm_get_state", "lbm_set_state",
     "lbm_destroy", "lbm_strerror", "lbm_last_error", "lbm_mask_plane", "lbm_mask_disk", "lbm_copy_probe",
     "lbm_contour_fit", "lbm_batch_contour_fit", "lbm_line_probe",
-    "lbm_batch_create", "lbm_batch_step", "lbm_batch_fields", "lbm_batch_diag", "lbm_batch_fluid_nodes",
-    "lbm_batch_destroy", "lbm_pool_create", "lbm_pool_footprint", "lbm_pool_admit", "lbm_pool_advance",
-    "lbm_pool_poll", "lbm_pool_fields", "lbm_pool_release", "lbm_pool_stats", "lbm_pool_progress",
-    "lbm_pool_destroy",
+    "lbm_params_state_bytes", "lbm_batch_create", "lbm_batch_step", "lbm_batch_launch_counts", "lbm_batch_fields",
+    "lbm_batch_diag", "lbm_batch_get_state", "lbm_batch_set_state", "lbm_batch_fluid_nodes", "lbm_batch_destroy",
+    "lbm_pool_create", "lbm_pool_footprint", "lbm_pool_admit", "lbm_pool_advance", "lbm_pool_poll",
+    "lbm_pool_status", "lbm_pool_fields", "lbm_pool_diag", "lbm_pool_get_state", "lbm_pool_set_state", "lbm_pool_release",
+    "lbm_pool_stats", "lbm_pool_progress", "lbm_pool_destroy",
 ]
 
 
@@ -87,6 +88,7 @@ def lib():
             "lbm_create": (I32, [PP, P, P, P, P, ctypes.POINTER(P)]),
             "lbm_step": (I32, [P, I64]),
             "lbm_time": (I64, [P]),
+            "lbm_launch_counts": (I32, [P, ctypes.POINTER(I64), ctypes.POINTER(I64)]),
             "lbm_fields": (I32, [P, P, P, P, P]),
             "lbm_fields_device": (I32, [P, P, P, P, P]),
             "lbm_forces": (I32, [P, P, P, P, P, P, P]),
@@ -104,18 +106,26 @@ def lib():
             "lbm_contour_fit": (I32, [P, ctypes.POINTER(LbmContourReq), ctypes.POINTER(LbmCircle)]),
             "lbm_batch_contour_fit": (I32, [P, I32, ctypes.POINTER(LbmContourReq), ctypes.POINTER(LbmCircle)]),
             "lbm_line_probe": (I32, [P, I32, I32, I32, I32, I32, D, P]),
+            "lbm_params_state_bytes": (SZ, [PP]),
             "lbm_batch_create": (I32, [I32, PP, P, P, P, P, I32, ctypes.POINTER(P)]),
             "lbm_batch_step": (I32, [P, I64]),
+            "lbm_batch_launch_counts": (I32, [P, ctypes.POINTER(I64), ctypes.POINTER(I64)]),
+            "lbm_batch_get_state": (I32, [P, I32, P]),
+            "lbm_batch_set_state": (I32, [P, I32, P]),
             "lbm_batch_fields": (I32, [P, I32, P, P, P, P]),
             "lbm_batch_diag": (I32, [P, I32, ctypes.POINTER(LbmDiag)]),
             "lbm_batch_fluid_nodes": (I64, [P]),
             "lbm_batch_destroy": (I32, [P]),
-            "lbm_pool_create": (I32, [SZ, I32, I32, P, ctypes.POINTER(P)]),
+            "lbm_pool_create": (I32, [SZ, I32, I32, I32, P, ctypes.POINTER(P)]),
             "lbm_pool_footprint": (SZ, [PP]),
             "lbm_pool_admit": (I32, [P, PP, P, P, P, I64, ctypes.POINTER(I32)]),
             "lbm_pool_advance": (I32, [P, I64]),
             "lbm_pool_poll": (I32, [P, P, I32, ctypes.POINTER(I32)]),
             "lbm_pool_fields": (I32, [P, I32, P, P, P, P]),
+            "lbm_pool_diag": (I32, [P, I32, ctypes.POINTER(LbmDiag)]),
+            "lbm_pool_status": (I32, [P, I32]),
+            "lbm_pool_get_state": (I32, [P, I32, P]),
+            "lbm_pool_set_state": (I32, [P, I32, P]),
             "lbm_pool_release": (I32, [P, I32]),
             "lbm_pool_stats": (I32, [P, ctypes.POINTER(I32), ctypes.POINTER(SZ)]),
             "lbm_pool_progress": (I32, [P, ctypes.POINTER(I64), ctypes.POINTER(I64)]),

@@ -2,9 +2,9 @@
 //
 // Batch: many independent simulations of uneven sizes advance together; one
 // launch per time step covers the flattened list of (instance, tile) pairs of
-// all instances, so small grids no longer pay one launch each and the tail
-// of one grid overlaps the bulk of another.  K steps can be captured in one
-// HIP graph.
+// all instances (lbm_batch_kernels.hpp), so small grids no longer pay one
+// launch each and the tail of one grid overlaps the bulk of another.  Graphs
+// of several steps are captured and replayed as for a single simulation.
 //
 // Pool: resident slots with continuous batching.  Solves are admitted while
 // others run, as slots and HBM budget free up; their set-up kernels run on a
@@ -13,165 +13,73 @@
 // finished slot exit at once), and finished slots are polled, read back and
 // released without stopping the others.  Device memory comes from one arena
 // reserved at creation (first-fit, no allocation in the serving loop).
+//
+// Both forms run the fused FP64 diagnostics at a cadence: on those launches
+// every tile writes its partials, and one block per instance reduces its own
+// tiles into that instance's targets (mass, momentum, drift against step 0,
+// sticky non-finite / negative / drift flags).  A broken instance is reported
+// by its own calls (LBM_ENUMERIC) while the others go on; the pool also
+// copies the flags to the host as the launches complete, reports a broken
+// slot from lbm_pool_poll and stops advancing it.
 #include <algorithm>
 #include <deque>
 #include <map>
 
 #include "lbm_analysis.hpp"
+#include "lbm_batch_kernels.hpp"
 
 using namespace mclbm;
 
 namespace {
 
-template <typename S, int TY, int BC>
-__global__ __launch_bounds__(threads_for(TY)) void k_batch_step(const Inst *__restrict__ insts,
-                                                                const int2 *__restrict__ tiles, int launch_parity,
-                                                                long long L) {
-    __shared__ Smem<TY> sm;
-    const int t = xcd_tile(blockIdx.x, gridDim.x);
-    const int2 e = tiles[t];
-    const Inst &I = insts[e.x];  // uniform, read-only: scalar loads, no private copy
-    if (L >= I.t_end) return;  // this slot has finished; the whole block leaves together
-    const int parity = (I.parity0 ^ launch_parity) & 1;
-    int tx, ty;
-    tile_coords(e.y, I.tiles_x, I.tiles_y, I.tg, tx, ty);
-    DiagAcc acc;
-    process_tile<S, TY, BC, MODE_STEP, false>(I, tx, ty, parity, sm, acc, Fields{});
+// Per-instance reduction of a diagnostic launch: block k reduces the partials
+// of instance k's tiles (a contiguous range of the list) into its targets and
+// leaves its sticky flags in flags[k].  Entries without tiles in the list, or
+// that have finished, are skipped (their blocks wrote no partials).
+__global__ __launch_bounds__(256) void k_batch_diag_reduce(const Inst *__restrict__ insts,
+                                                           const double *__restrict__ partials, long long L,
+                                                           int *flags) {
+    const Inst &I = insts[blockIdx.x];
+    if (I.ntl <= 0 || L >= I.t_end) return;
+    const int f = diag_reduce_block(partials + (size_t)I.tile0 * 6, I.ntl, I.dd);
+    if (flags && threadIdx.x == 0) flags[blockIdx.x] = f;
 }
 
-// The same with two lanes per node (bit-identical results).
-template <typename S, int TY, int BC>
-__global__ __launch_bounds__(ls_threads(TY)) void k_batch_step_ls(const Inst *__restrict__ insts,
-                                                                  const int2 *__restrict__ tiles, int launch_parity,
-                                                                  long long L) {
-    __shared__ SmemLS<TY> sm;
-    const int t = xcd_tile(blockIdx.x, gridDim.x);
-    const int2 e = tiles[t];
-    const Inst &I = insts[e.x];
-    if (L >= I.t_end) return;
-    const int parity = (I.parity0 ^ launch_parity) & 1;
-    int tx, ty;
-    tile_coords(e.y, I.tiles_x, I.tiles_y, I.tg, tx, ty);
-    DiagAcc acc;
-    process_tile_ls<S, TY, BC, MODE_STEP, false>(I, tx, ty, parity, sm, acc, Fields{});
-}
-
-// One launch for every rule: each block takes its instance's rule.  The
-// kernel holds all three tile bodies (registers are allocated for the
-// largest), and a step pays one launch tail instead of three.
-template <typename S, int TY>
-__global__ __launch_bounds__(threads_for(TY)) void k_batch_step_all(const Inst *__restrict__ insts,
-                                                                    const int2 *__restrict__ tiles, int launch_parity,
-                                                                    long long L) {
-    __shared__ Smem<TY> sm;
-    const int t = xcd_tile(blockIdx.x, gridDim.x);
-    const int2 e = tiles[t];
-    const Inst &I = insts[e.x];
-    if (L >= I.t_end) return;
-    const int parity = (I.parity0 ^ launch_parity) & 1;
-    int tx, ty;
-    tile_coords(e.y, I.tiles_x, I.tiles_y, I.tg, tx, ty);
-    DiagAcc acc;
-    if (I.bc == BC_MC)
-        process_tile<S, TY, BC_MC, MODE_STEP, false>(I, tx, ty, parity, sm, acc, Fields{});
-    else if (I.bc == BC_LLKC)
-        process_tile<S, TY, BC_LLKC, MODE_STEP, false>(I, tx, ty, parity, sm, acc, Fields{});
+// One launch at launch counter L of every listed tile; with diag, the
+// per-tile partials and the per-instance reduction.
+void launch_batch(const BatchLaunch &B, hipStream_t s, long long L, bool diag) {
+    const int lp = (int)(L & 1);
+    if (B.storage == LBM_STORE_F16)
+        launch_batch_f16(B, s, lp, L, diag);
     else
-        process_tile<S, TY, BC_IMPROVED, MODE_STEP, false>(I, tx, ty, parity, sm, acc, Fields{});
-}
-
-template <typename S, int TY>
-__global__ __launch_bounds__(ls_threads(TY)) void k_batch_step_ls_all(const Inst *__restrict__ insts,
-                                                                      const int2 *__restrict__ tiles,
-                                                                      int launch_parity, long long L) {
-    __shared__ SmemLS<TY> sm;
-    const int t = xcd_tile(blockIdx.x, gridDim.x);
-    const int2 e = tiles[t];
-    const Inst &I = insts[e.x];
-    if (L >= I.t_end) return;
-    const int parity = (I.parity0 ^ launch_parity) & 1;
-    int tx, ty;
-    tile_coords(e.y, I.tiles_x, I.tiles_y, I.tg, tx, ty);
-    DiagAcc acc;
-    if (I.bc == BC_MC)
-        process_tile_ls<S, TY, BC_MC, MODE_STEP, false>(I, tx, ty, parity, sm, acc, Fields{});
-    else if (I.bc == BC_LLKC)
-        process_tile_ls<S, TY, BC_LLKC, MODE_STEP, false>(I, tx, ty, parity, sm, acc, Fields{});
-    else
-        process_tile_ls<S, TY, BC_IMPROVED, MODE_STEP, false>(I, tx, ty, parity, sm, acc, Fields{});
+        launch_batch_f32(B, s, lp, L, diag);
+    if (diag && B.T.total() > 0 && B.ninst > 0)
+        hipLaunchKernelGGL(k_batch_diag_reduce, dim3(B.ninst), dim3(256), 0, s, B.insts, B.partials, L, B.flags);
 }
 
 // Flattened (instance, tile) pairs in instance order; within an instance
-// tiles follow the grouped order of the single-instance kernel.  With one rule
-// in the list the launch runs the kernel specialised (and register-allocated)
-// for it; with several, the kernel that holds all three.
-struct TileLists {
-    int cnt[3] = {0, 0, 0};
-    int total() const { return cnt[0] + cnt[1] + cnt[2]; }
-    int rules() const { return (cnt[0] > 0) + (cnt[1] > 0) + (cnt[2] > 0); }
-};
-
-// Tiles without a fluid node are left out (fluid_of(k): one flag per logical
-// tile of instance k): such a tile moves no population, and its workgroup
-// would only occupy a slot of the launch.
+// tiles follow the grouped order of the single-instance kernel.  Tiles without
+// a fluid node are left out (fluid_of(k): one flag per logical tile of
+// instance k): such a tile moves no population, and its workgroup would only
+// occupy a slot of the launch.  range[k] receives instance k's (first, count).
 template <typename InstOf, typename FluidOf>
-TileLists build_tiles(int n, InstOf inst_of, FluidOf fluid_of, std::vector<int2> &out) {
+TileLists build_tiles(int n, InstOf inst_of, FluidOf fluid_of, std::vector<int2> &out, std::vector<int2> &range) {
     TileLists T;
     out.clear();
+    range.assign(n, make_int2(0, 0));
     for (int k = 0; k < n; ++k) {
         const Inst *I = inst_of(k);
         if (!I) continue;
         const std::vector<uint8_t> &f = fluid_of(k);
         const int nt = I->tiles_x * I->tiles_y;
-        int kept = 0;
+        const int first = (int)out.size();
         for (int t = 0; t < nt; ++t)
-            if (f[t]) {
-                out.push_back(make_int2(k, t));
-                ++kept;
-            }
+            if (f[t]) out.push_back(make_int2(k, t));
+        const int kept = (int)out.size() - first;
+        range[k] = make_int2(first, kept);
         T.cnt[I->bc] += kept;
     }
     return T;
-}
-
-template <typename S, int TY, int BC>
-void launch_batch_bc(hipStream_t s, int lanes, int n, const Inst *insts, const int2 *tiles, int lp, long long L) {
-    if (lanes == 2)
-        hipLaunchKernelGGL((k_batch_step_ls<S, TY, BC>), dim3(n), dim3(ls_threads(TY)), 0, s, insts, tiles, lp, L);
-    else
-        hipLaunchKernelGGL((k_batch_step<S, TY, BC>), dim3(n), dim3(threads_for(TY)), 0, s, insts, tiles, lp, L);
-}
-
-template <typename S, int TY>
-void launch_batch_ty(hipStream_t s, int lanes, const TileLists &T, const Inst *insts, const int2 *tiles, int lp,
-                     long long L) {
-    if (T.rules() > 1) {
-        if (lanes == 2)
-            hipLaunchKernelGGL((k_batch_step_ls_all<S, TY>), dim3(T.total()), dim3(ls_threads(TY)), 0, s, insts, tiles,
-                               lp, L);
-        else
-            hipLaunchKernelGGL((k_batch_step_all<S, TY>), dim3(T.total()), dim3(threads_for(TY)), 0, s, insts, tiles,
-                               lp, L);
-        return;
-    }
-    if (T.cnt[0]) launch_batch_bc<S, TY, BC_MC>(s, lanes, T.cnt[0], insts, tiles, lp, L);
-    if (T.cnt[1]) launch_batch_bc<S, TY, BC_LLKC>(s, lanes, T.cnt[1], insts, tiles, lp, L);
-    if (T.cnt[2]) launch_batch_bc<S, TY, BC_IMPROVED>(s, lanes, T.cnt[2], insts, tiles, lp, L);
-}
-
-void launch_batch(int storage, int ty, int lanes, hipStream_t s, const TileLists &T, const Inst *insts,
-                  const int2 *tiles, int lp, long long L) {
-    if (storage == LBM_STORE_F16) {
-        if (ty == 4) launch_batch_ty<__half, 4>(s, lanes, T, insts, tiles, lp, L);
-        else if (ty == 16) launch_batch_ty<__half, 16>(s, lanes, T, insts, tiles, lp, L);
-        else if (ty == 32) launch_batch_ty<__half, 32>(s, lanes, T, insts, tiles, lp, L);
-        else launch_batch_ty<__half, 8>(s, lanes, T, insts, tiles, lp, L);
-    } else {
-        if (ty == 4) launch_batch_ty<float, 4>(s, lanes, T, insts, tiles, lp, L);
-        else if (ty == 16) launch_batch_ty<float, 16>(s, lanes, T, insts, tiles, lp, L);
-        else if (ty == 32) launch_batch_ty<float, 32>(s, lanes, T, insts, tiles, lp, L);
-        else launch_batch_ty<float, 8>(s, lanes, T, insts, tiles, lp, L);
-    }
 }
 
 // Device memory of one instance, carved from one block.
@@ -216,6 +124,7 @@ struct Prepared {
     uint8_t *nbr = nullptr, *cls = nullptr;
     double *partials = nullptr;
     DiagDev *dd = nullptr;
+    DiagDev dd0{};  // initial targets (the upload reads them until the stream has drained)
     float *fields = nullptr;
     int ntiles = 0;
     int ty = 8;
@@ -264,36 +173,63 @@ int prepare(Prepared &P, const lbm_params &p, int ty, char *base, const uint8_t 
     uint8_t *tflag = (uint8_t *)(base + P.m.off_tflag);
     P.partials = (double *)(base + P.m.off_part);
     P.dd = (DiagDev *)(base + P.m.off_dd);
+    P.I.dd = P.dd;
     P.fields = (float *)(base + P.m.off_fields);
     const size_t bufbytes = pop_buffer_bytes(p);
+    P.dd0 = DiagDev{};
+    P.dd0.drift_tol = p.drift_tol;
     MCLBM_HIP(hipMemsetAsync(P.I.buf[0], 0, bufbytes, s));
     MCLBM_HIP(hipMemsetAsync(P.I.buf[1], 0, bufbytes, s));
     MCLBM_HIP(hipMemsetAsync(word, 0, np * sizeof(uint16_t), s));
     MCLBM_HIP(hipMemsetAsync(word0, 0, np * sizeof(uint16_t), s));
     MCLBM_HIP(hipMemsetAsync(m25, 0, np * sizeof(uint32_t), s));
-    MCLBM_HIP(hipMemsetAsync(P.dd, 0, sizeof(DiagDev), s));
+    MCLBM_HIP(hipMemcpyAsync(P.dd, &P.dd0, sizeof(DiagDev), hipMemcpyHostToDevice, s));
     MCLBM_HIP(hipMemcpyAsync(dmask, mask, n, hipMemcpyHostToDevice, s));
     MCLBM_HIP(hipMemcpyAsync(drA, rA, n * sizeof(double), hipMemcpyHostToDevice, s));
     MCLBM_HIP(hipMemcpyAsync(drB, rB, n * sizeof(double), hipMemcpyHostToDevice, s));
     const Geometry g{P.nbr, P.cls, word, m25, tflag, word0};
     int rc = enqueue_setup(P.I, p, ty, dmask, drA, drB, g, s);
     if (rc) return rc;
-    // drift threshold off in batched forms; step-0 mass recorded by the first fields pass
-    launch_step(Launch{p.storage, ty, kernel_bc(p), MODE_FIELDS, true}, s, P.I, 0, Fields{}, P.partials, P.dd, 0);
+    // step-0 mass, recorded by the first fields pass
+    launch_step(Launch{p.storage, ty, kernel_bc(p), MODE_FIELDS, true}, s, P.I, 0, Fields{}, P.partials, P.dd);
     MCLBM_HIP(hipGetLastError());
     return LBM_OK;
 }
 
-// Fields of a prepared instance at buffer parity `parity` into host arrays.
-int read_fields(Prepared &P, int parity, long long step, hipStream_t s, double *out[4]) {
+int copy_diag(const Prepared &P, hipStream_t s, int64_t step, lbm_diag_t *out) {
+    DiagDev d;
+    MCLBM_HIP(hipMemcpyAsync(&d, P.dd, sizeof d, hipMemcpyDeviceToHost, s));
+    MCLBM_HIP(hipStreamSynchronize(s));
+    if (out) {
+        out->mass[0] = d.mass[0];
+        out->mass[1] = d.mass[1];
+        out->mass0[0] = d.mass0[0];
+        out->mass0[1] = d.mass0[1];
+        out->momentum[0] = d.mom[0];
+        out->momentum[1] = d.mom[1];
+        out->max_speed = d.max_speed;
+        out->step = step;
+        out->flags = d.flags;
+        out->pad = 0;
+    }
+    if (d.flags) {
+        set_err("numerical failure flags 0x%x at step %lld", d.flags, (long long)step);
+        return LBM_ENUMERIC;
+    }
+    return LBM_OK;
+}
+
+// Fields of a prepared instance at buffer parity `parity` into host arrays;
+// the pass also reduces the diagnostics of that state, so a broken instance
+// returns LBM_ENUMERIC (its fields are still written).
+int read_fields(Prepared &P, int parity, int64_t step, hipStream_t s, double *out[4]) {
     const size_t n = (size_t)P.p.nx * P.p.ny;
     Fields fo{};
     fo.rhoA = P.fields;
     fo.rhoB = P.fields + n;
     fo.ux = P.fields + 2 * n;
     fo.uy = P.fields + 3 * n;
-    launch_step(Launch{P.p.storage, P.ty, kernel_bc(P.p), MODE_FIELDS, true}, s, P.I, parity, fo, P.partials, P.dd,
-                step);
+    launch_step(Launch{P.p.storage, P.ty, kernel_bc(P.p), MODE_FIELDS, true}, s, P.I, parity, fo, P.partials, P.dd);
     MCLBM_HIP(hipGetLastError());
     std::vector<float> tmp(n);
     for (int q = 0; q < 4; ++q) {
@@ -302,28 +238,26 @@ int read_fields(Prepared &P, int parity, long long step, hipStream_t s, double *
         MCLBM_HIP(hipStreamSynchronize(s));
         for (size_t k = 0; k < n; ++k) out[q][k] = (double)tmp[k];
     }
-    MCLBM_HIP(hipStreamSynchronize(s));
-    return LBM_OK;
+    return copy_diag(P, s, step, nullptr);
 }
 
-int read_diag(Prepared &P, int parity, long long step, hipStream_t s, lbm_diag_t *out) {
-    launch_step(Launch{P.p.storage, P.ty, kernel_bc(P.p), MODE_FIELDS, true}, s, P.I, parity, Fields{}, P.partials, P.dd,
-                step);
+int read_diag(Prepared &P, int parity, int64_t step, hipStream_t s, lbm_diag_t *out) {
+    launch_step(Launch{P.p.storage, P.ty, kernel_bc(P.p), MODE_FIELDS, true}, s, P.I, parity, Fields{}, P.partials,
+                P.dd);
     MCLBM_HIP(hipGetLastError());
-    DiagDev d;
-    MCLBM_HIP(hipMemcpyAsync(&d, P.dd, sizeof d, hipMemcpyDeviceToHost, s));
+    return copy_diag(P, s, step, out);
+}
+
+// Raw population buffer of an instance at parity `parity`, to or from the host.
+int copy_state(Prepared &P, int parity, hipStream_t s, void *host, bool to_host) {
     MCLBM_HIP(hipStreamSynchronize(s));
-    out->mass[0] = d.mass[0];
-    out->mass[1] = d.mass[1];
-    out->mass0[0] = d.mass0[0];
-    out->mass0[1] = d.mass0[1];
-    out->momentum[0] = d.mom[0];
-    out->momentum[1] = d.mom[1];
-    out->max_speed = d.max_speed;
-    out->step = step;
-    out->flags = d.flags;
-    out->pad = 0;
-    return d.flags ? LBM_ENUMERIC : LBM_OK;
+    const size_t bytes = pop_buffer_bytes(P.p);
+    if (to_host)
+        MCLBM_HIP(hipMemcpyAsync(host, P.I.buf[parity], bytes, hipMemcpyDeviceToHost, s));
+    else
+        MCLBM_HIP(hipMemcpyAsync(P.I.buf[parity], host, bytes, hipMemcpyHostToDevice, s));
+    MCLBM_HIP(hipStreamSynchronize(s));
+    return LBM_OK;
 }
 
 // Temporary upload buffers sized for the largest instance of a create/admit call.
@@ -360,30 +294,33 @@ struct Staging {
 struct lbm_batch {
     hipStream_t stream = nullptr;
     bool own_stream = false;
-    int storage = 0, ty = 8, lanes = 1;
+    int storage = 0, ty = 8, lanes = 1, diag_every = 0;
     std::vector<Prepared> inst;
     std::vector<char *> blocks;
     Inst *d_inst = nullptr;
     int2 *d_tiles = nullptr;
-    TileLists lists;
+    double *d_part = nullptr;  // per listed tile: partials of diagnostic launches
+    BatchLaunch B;
     int64_t t = 0;
     int64_t fluid = 0;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t gexec = nullptr;
-    int glen = 0;
+    GraphPlan plan;
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    int64_t graph_run = 0, plain_run = 0;
     double *cwork = nullptr;  // lazily allocated: contour-fit work buffer
 };
 
 static void batch_release(lbm_batch *b) {
     if (!b) return;
     if (b->stream) (void)hipStreamSynchronize(b->stream);
-    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
-    if (b->graph) (void)hipGraphDestroy(b->graph);
+    for (int v = 0; v < 2; ++v) {
+        if (b->gexec[v]) (void)hipGraphExecDestroy(b->gexec[v]);
+        if (b->graph[v]) (void)hipGraphDestroy(b->graph[v]);
+    }
     for (char *q : b->blocks)
         if (q) (void)hipFree(q);
-    if (b->d_inst) (void)hipFree(b->d_inst);
-    if (b->d_tiles) (void)hipFree(b->d_tiles);
-    if (b->cwork) (void)hipFree(b->cwork);
+    for (void *q : {(void *)b->d_inst, (void *)b->d_tiles, (void *)b->d_part, (void *)b->cwork})
+        if (q) (void)hipFree(q);
     if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
     delete b;
 }
@@ -405,15 +342,20 @@ int lbm_batch_create(int32_t n, const lbm_params *params, const uint8_t *const *
             return LBM_EINVAL;
         }
         if (params[k].storage != params[0].storage || default_ty(params[k]) != default_ty(params[0]) ||
-            lanes_of(params[k]) != lanes_of(params[0])) {
-            set_err("instance %d: every instance of a batch uses the same storage, tile rows and lanes", k);
+            lanes_of(params[k]) != lanes_of(params[0]) || params[k].diag_every != params[0].diag_every) {
+            set_err("instance %d: every instance of a batch uses the same storage, tile rows, lanes and diag_every", k);
             return LBM_EINVAL;
         }
     }
+    GraphPlan plan;
+    int rc = make_graph_plan(graph_steps, params[0].diag_every, plan);
+    if (rc) return rc;
     lbm_batch *b = new lbm_batch();
     b->storage = params[0].storage;
     b->ty = default_ty(params[0]);
     b->lanes = lanes_of(params[0]);
+    b->diag_every = params[0].diag_every;
+    b->plan = plan;
     b->stream = (hipStream_t)stream;
     auto bail = [&](int code) {
         batch_release(b);
@@ -432,16 +374,14 @@ int lbm_batch_create(int32_t n, const lbm_params *params, const uint8_t *const *
         maxn = std::max(maxn, (size_t)params[k].nx * params[k].ny);
         maxp = std::max(maxp, (size_t)params[k].ny * pitch_of(params[k].nx));
     }
-    int rc = st.ensure(maxn, maxp);
+    rc = st.ensure(maxn, maxp);
     if (rc) {
         st.release();
         return bail(rc);
     }
     b->inst.resize(n);
-    std::vector<int2> tiles;
-    std::vector<Inst> host_inst(n);
     for (int k = 0; k < n; ++k) {
-        lbm_params p = params[k];
+        const lbm_params &p = params[k];
         InstMem m = layout(p, b->ty);
         char *base = nullptr;
         if (hipMalloc(&base, m.bytes) != hipSuccess) {
@@ -457,37 +397,52 @@ int lbm_batch_create(int32_t n, const lbm_params *params, const uint8_t *const *
             st.release();
             return bail(rc);
         }
-        host_inst[k] = b->inst[k].I;
         b->fluid += b->inst[k].fluid;
     }
     st.release();
-    b->lists = build_tiles(
-        n, [&](int k) { return &host_inst[k]; }, [&](int k) -> const std::vector<uint8_t> & { return b->inst[k].tile_fluid; },
-        tiles);
+    std::vector<int2> tiles, range;
+    const TileLists T = build_tiles(
+        n, [&](int k) { return &b->inst[k].I; },
+        [&](int k) -> const std::vector<uint8_t> & { return b->inst[k].tile_fluid; }, tiles, range);
+    std::vector<Inst> host_inst(n);
+    for (int k = 0; k < n; ++k) {
+        b->inst[k].I.tile0 = range[k].x;
+        b->inst[k].I.ntl = range[k].y;
+        host_inst[k] = b->inst[k].I;
+    }
+    const size_t ntl = std::max<size_t>(tiles.size(), 1);
     if (hipMalloc(&b->d_inst, sizeof(Inst) * n) != hipSuccess ||
-        hipMalloc(&b->d_tiles, sizeof(int2) * tiles.size()) != hipSuccess) {
+        hipMalloc(&b->d_tiles, sizeof(int2) * ntl) != hipSuccess ||
+        hipMalloc(&b->d_part, sizeof(double) * 6 * ntl) != hipSuccess) {
         set_err("batch tables: hipMalloc failed");
         return bail(LBM_ENOMEM);
     }
     if (hipMemcpy(b->d_inst, host_inst.data(), sizeof(Inst) * n, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(b->d_tiles, tiles.data(), sizeof(int2) * tiles.size(), hipMemcpyHostToDevice) != hipSuccess) {
+        (!tiles.empty() &&
+         hipMemcpy(b->d_tiles, tiles.data(), sizeof(int2) * tiles.size(), hipMemcpyHostToDevice) != hipSuccess)) {
         set_err("batch tables: upload failed");
         return bail(LBM_EDEVICE);
     }
-    if (graph_steps > 0) {
-        const int K = (graph_steps + 1) / 2 * 2;
+    b->B.storage = b->storage;
+    b->B.ty = b->ty;
+    b->B.lanes = b->lanes;
+    b->B.T = T;
+    b->B.insts = b->d_inst;
+    b->B.ninst = n;
+    b->B.tiles = b->d_tiles;
+    b->B.partials = b->d_part;
+    b->B.flags = nullptr;
+    for (int v = 0; v < graph_variants(plan); ++v) {
         if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeRelaxed) != hipSuccess) {
             set_err("graph capture failed");
             return bail(LBM_EDEVICE);
         }
-        for (int s = 0; s < K; ++s)
-            launch_batch(b->storage, b->ty, b->lanes, b->stream, b->lists, b->d_inst, b->d_tiles, s & 1, 0);
-        if (hipStreamEndCapture(b->stream, &b->graph) != hipSuccess ||
-            hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0) != hipSuccess) {
+        for (int s = 0; s < plan.glen; ++s) launch_batch(b->B, b->stream, s, graph_diag(plan, v, s));
+        if (hipStreamEndCapture(b->stream, &b->graph[v]) != hipSuccess ||
+            hipGraphInstantiate(&b->gexec[v], b->graph[v], nullptr, nullptr, 0) != hipSuccess) {
             set_err("graph instantiate failed");
             return bail(LBM_EDEVICE);
         }
-        b->glen = K;
     }
     *out = b;
     return LBM_OK;
@@ -495,18 +450,31 @@ int lbm_batch_create(int32_t n, const lbm_params *params, const uint8_t *const *
 
 int lbm_batch_step(lbm_batch *b, int64_t nsteps) {
     if (!b || nsteps < 0) return LBM_EINVAL;
+    const int64_t glen = b->plan.glen;
     while (nsteps > 0) {
-        if (b->gexec && (b->t & 1) == 0 && nsteps >= b->glen) {
-            MCLBM_HIP(hipGraphLaunch(b->gexec, b->stream));
-            b->t += b->glen;
-            nsteps -= b->glen;
+        const int v = next_launch(b->plan, b->t, nsteps);
+        if (v >= 0) {
+            MCLBM_HIP(hipGraphLaunch(b->gexec[v], b->stream));
+            b->t += glen;
+            b->graph_run += glen;
+            nsteps -= glen;
             continue;
         }
-        launch_batch(b->storage, b->ty, b->lanes, b->stream, b->lists, b->d_inst, b->d_tiles, (int)(b->t & 1), 0);
+        // the step kernels take the launch counter only to stop finished pool
+        // slots; batch instances never finish (t_end is the largest value)
+        launch_batch(b->B, b->stream, b->t, plain_diag(b->diag_every, b->t));
         b->t += 1;
+        b->plain_run += 1;
         nsteps -= 1;
     }
     MCLBM_HIP(hipGetLastError());
+    return LBM_OK;
+}
+
+int lbm_batch_launch_counts(const lbm_batch *b, int64_t *graph_steps, int64_t *plain_steps) {
+    if (!b) return LBM_EINVAL;
+    if (graph_steps) *graph_steps = b->graph_run;
+    if (plain_steps) *plain_steps = b->plain_run;
     return LBM_OK;
 }
 
@@ -521,6 +489,16 @@ int lbm_batch_diag(lbm_batch *b, int32_t idx, lbm_diag_t *out) {
     return read_diag(b->inst[idx], (int)(b->t & 1), b->t, b->stream, out);
 }
 
+int lbm_batch_get_state(lbm_batch *b, int32_t idx, void *host) {
+    if (!b || !host || idx < 0 || idx >= (int)b->inst.size()) return LBM_EINVAL;
+    return copy_state(b->inst[idx], (int)(b->t & 1), b->stream, host, true);
+}
+
+int lbm_batch_set_state(lbm_batch *b, int32_t idx, const void *host) {
+    if (!b || !host || idx < 0 || idx >= (int)b->inst.size()) return LBM_EINVAL;
+    return copy_state(b->inst[idx], (int)(b->t & 1), b->stream, const_cast<void *>(host), false);
+}
+
 int lbm_batch_contour_fit(lbm_batch *b, int32_t idx, const lbm_contour_req *req, lbm_circle_t *out) {
     if (!b || idx < 0 || idx >= (int)b->inst.size()) return LBM_EINVAL;
     if (!b->cwork) MCLBM_HIP(hipMalloc(&b->cwork, sizeof(double) * CONTOUR_WORK_DOUBLES));
@@ -528,7 +506,7 @@ int lbm_batch_contour_fit(lbm_batch *b, int32_t idx, const lbm_contour_req *req,
     Fields fo{};
     fo.rhoA = P.fields;
     launch_step(Launch{P.p.storage, P.ty, kernel_bc(P.p), MODE_FIELDS, true}, b->stream, P.I, (int)(b->t & 1), fo,
-                P.partials, P.dd, b->t);
+                P.partials, P.dd);
     MCLBM_HIP(hipGetLastError());
     return contour_fit(P.fields, P.cls, P.p.nx, P.p.ny, req, b->cwork, b->stream, out);
 }
@@ -538,6 +516,11 @@ int64_t lbm_batch_fluid_nodes(const lbm_batch *b) { return b ? b->fluid : -1; }
 int lbm_batch_destroy(lbm_batch *b) {
     batch_release(b);
     return LBM_OK;
+}
+
+size_t lbm_params_state_bytes(const lbm_params *p) {
+    if (!p || p->nx < 1 || p->ny < 1) return 0;
+    return pop_buffer_bytes(*p);
 }
 
 }  // extern "C"
@@ -590,11 +573,12 @@ struct Arena {
 struct Slot {
     bool used = false;
     bool joined = false;    // part of the launched tile list
-    bool released = true;
+    bool broken = false;    // a diagnostic reduction flagged it; stopped
     Prepared P;
     size_t off = 0, bytes = 0;
     int64_t nsteps = 0;
-    int64_t L0 = 0;         // pool launch counter at which the slot joined
+    int64_t L0 = 0;          // pool launch counter at which the slot joined
+    int64_t flags_from = 0;  // its host flag copy is its own once launches up to here have completed
     hipEvent_t ready = nullptr;  // set-up finished on the init stream
 };
 
@@ -603,14 +587,15 @@ struct Slot {
 struct lbm_pool {
     hipStream_t stream = nullptr, init_stream = nullptr;
     bool own_stream = false;
-    int storage = 0, ty = 8, max_slots = 0;
+    int storage = 0, ty = 8, max_slots = 0, diag_every = 0;
     Arena arena;
     size_t in_use = 0;
     std::vector<Slot> slots;
     Inst *d_inst = nullptr;
     int2 *d_tiles = nullptr;
+    double *d_part = nullptr;  // per listed tile: partials of diagnostic launches
     size_t tiles_cap = 0;
-    TileLists lists;
+    BatchLaunch B;
     bool dirty = false;
     int64_t L = 0;  // launches enqueued so far
     std::deque<std::pair<int64_t, hipEvent_t>> marks;  // (launch count reached, event)
@@ -618,6 +603,8 @@ struct lbm_pool {
     Staging st;
     Inst *h_inst = nullptr;   // pinned staging of the slot table
     int2 *h_tiles = nullptr;  // pinned staging of the tile list
+    int *d_flags = nullptr;   // per slot: flags left by the last diagnostic reduction
+    int *h_flags = nullptr;   // pinned copy of d_flags, refreshed after each diagnostic launch
     hipEvent_t upload_done = nullptr;
 };
 
@@ -630,11 +617,11 @@ static void pool_release_all(lbm_pool *P) {
         if (s.ready) (void)hipEventDestroy(s.ready);
     if (P->upload_done) (void)hipEventDestroy(P->upload_done);
     P->st.release();
-    if (P->arena.base) (void)hipFree(P->arena.base);
-    if (P->d_inst) (void)hipFree(P->d_inst);
-    if (P->d_tiles) (void)hipFree(P->d_tiles);
-    if (P->h_inst) (void)hipHostFree(P->h_inst);
-    if (P->h_tiles) (void)hipHostFree(P->h_tiles);
+    for (void *q : {(void *)P->arena.base, (void *)P->d_inst, (void *)P->d_tiles, (void *)P->d_part,
+                    (void *)P->d_flags})
+        if (q) (void)hipFree(q);
+    for (void *q : {(void *)P->h_inst, (void *)P->h_tiles, (void *)P->h_flags})
+        if (q) (void)hipHostFree(q);
     if (P->init_stream) (void)hipStreamDestroy(P->init_stream);
     if (P->own_stream && P->stream) (void)hipStreamDestroy(P->stream);
     delete P;
@@ -642,25 +629,36 @@ static void pool_release_all(lbm_pool *P) {
 
 // Re-uploads the slot table and tile list, in stream order after all launches
 // already enqueued (they keep reading the previous contents until then).
+// Slots not in the list get an empty table entry (no tiles, finished).
 static int pool_upload(lbm_pool *P) {
     MCLBM_HIP(hipEventSynchronize(P->upload_done));  // previous upload has left the staging buffers
-    std::vector<int2> tiles;
+    std::vector<int2> tiles, range;
+    auto listed = [&](int k) { return P->slots[k].used && P->slots[k].joined; };
+    const TileLists T = build_tiles(
+        P->max_slots, [&](int k) { return listed(k) ? &P->slots[k].P.I : nullptr; },
+        [&](int k) -> const std::vector<uint8_t> & { return P->slots[k].P.tile_fluid; }, tiles, range);
     for (int k = 0; k < P->max_slots; ++k) {
         Slot &s = P->slots[k];
-        if (s.used && s.joined) P->h_inst[k] = s.P.I;
+        if (listed(k)) {
+            s.P.I.tile0 = range[k].x;
+            s.P.I.ntl = range[k].y;
+            P->h_inst[k] = s.P.I;
+        } else {
+            std::memset((void *)&P->h_inst[k], 0, sizeof(Inst));
+        }
     }
-    const TileLists T = build_tiles(
-        P->max_slots, [&](int k) { return (P->slots[k].used && P->slots[k].joined) ? &P->slots[k].P.I : nullptr; },
-        [&](int k) -> const std::vector<uint8_t> & { return P->slots[k].P.tile_fluid; }, tiles);
     if (tiles.size() > P->tiles_cap) {
         // grow: wait for launches that read the old list, then reallocate
         MCLBM_HIP(hipStreamSynchronize(P->stream));
-        if (P->d_tiles) (void)hipFree(P->d_tiles);
+        for (void *q : {(void *)P->d_tiles, (void *)P->d_part})
+            if (q) (void)hipFree(q);
         if (P->h_tiles) (void)hipHostFree(P->h_tiles);
         P->d_tiles = nullptr;
+        P->d_part = nullptr;
         P->h_tiles = nullptr;
         const size_t cap = std::max(tiles.size() * 2, (size_t)4096);
         MCLBM_HIP(hipMalloc(&P->d_tiles, cap * sizeof(int2)));
+        MCLBM_HIP(hipMalloc(&P->d_part, cap * 6 * sizeof(double)));
         MCLBM_HIP(hipHostMalloc((void **)&P->h_tiles, cap * sizeof(int2), hipHostMallocDefault));
         P->tiles_cap = cap;
     }
@@ -670,7 +668,9 @@ static int pool_upload(lbm_pool *P) {
         MCLBM_HIP(hipMemcpyAsync(P->d_tiles, P->h_tiles, sizeof(int2) * tiles.size(), hipMemcpyHostToDevice,
                                  P->stream));
     MCLBM_HIP(hipEventRecord(P->upload_done, P->stream));
-    P->lists = T;
+    P->B.T = T;
+    P->B.tiles = P->d_tiles;
+    P->B.partials = P->d_part;
     P->dirty = false;
     return LBM_OK;
 }
@@ -683,6 +683,23 @@ static void pool_reap_marks(lbm_pool *P) {
     }
 }
 
+// The launch count reached just after the first diagnostic launch at or
+// after counter L (the launch at counter x runs diagnostics when
+// (x + 1) % diag_every == 0): once the launches up to it have completed, the
+// slot's entry in the host flag copy is its own.
+static int64_t first_diag_end(const lbm_pool *P, int64_t L) {
+    const int64_t d = P->diag_every;
+    return (L + d) / d * d;
+}
+
+// Buffer parity holding a slot's state after the launches enqueued so far
+// (before it joins: buffer 0, written by the set-up).
+static int slot_parity(const lbm_pool *P, const Slot &s) {
+    if (!s.joined) return 0;
+    const int64_t Lr = std::min(P->L, s.P.I.t_end);
+    return (int)((s.P.I.parity0 ^ (Lr & 1)) & 1);
+}
+
 extern "C" {
 
 size_t lbm_pool_footprint(const lbm_params *p) {
@@ -690,8 +707,9 @@ size_t lbm_pool_footprint(const lbm_params *p) {
     return layout(*p, default_ty(*p)).bytes;
 }
 
-int lbm_pool_create(size_t hbm_budget, int32_t max_slots, int32_t storage, void *stream, lbm_pool **out) {
-    if (!out || max_slots < 1 || hbm_budget < 4096 || storage < 0 || storage > 1) {
+int lbm_pool_create(size_t hbm_budget, int32_t max_slots, int32_t storage, int32_t diag_every, void *stream,
+                    lbm_pool **out) {
+    if (!out || max_slots < 1 || hbm_budget < 4096 || storage < 0 || storage > 1 || diag_every < 0) {
         set_err("bad pool arguments");
         return LBM_EINVAL;
     }
@@ -699,6 +717,7 @@ int lbm_pool_create(size_t hbm_budget, int32_t max_slots, int32_t storage, void 
     lbm_pool *P = new lbm_pool();
     P->storage = storage;
     P->max_slots = max_slots;
+    P->diag_every = diag_every;
     P->slots.resize(max_slots);
     P->stream = (hipStream_t)stream;
     auto bail = [&](int code) {
@@ -714,6 +733,11 @@ int lbm_pool_create(size_t hbm_budget, int32_t max_slots, int32_t storage, void 
         set_err("pool streams/events failed");
         return bail(LBM_EDEVICE);
     }
+    for (auto &s : P->slots)
+        if (hipEventCreateWithFlags(&s.ready, hipEventDisableTiming) != hipSuccess) {
+            set_err("pool slot events failed");
+            return bail(LBM_EDEVICE);
+        }
     char *base = nullptr;
     if (hipMalloc(&base, hbm_budget) != hipSuccess) {
         set_err("pool arena hipMalloc(%zu) failed", hbm_budget);
@@ -721,12 +745,23 @@ int lbm_pool_create(size_t hbm_budget, int32_t max_slots, int32_t storage, void 
     }
     P->arena.init(base, hbm_budget);
     if (hipMalloc(&P->d_inst, sizeof(Inst) * max_slots) != hipSuccess ||
-        hipHostMalloc((void **)&P->h_inst, sizeof(Inst) * max_slots, hipHostMallocDefault) != hipSuccess) {
+        hipHostMalloc((void **)&P->h_inst, sizeof(Inst) * max_slots, hipHostMallocDefault) != hipSuccess ||
+        hipMalloc(&P->d_flags, sizeof(int) * max_slots) != hipSuccess ||
+        hipHostMalloc((void **)&P->h_flags, sizeof(int) * max_slots, hipHostMallocDefault) != hipSuccess) {
         set_err("pool tables failed");
         return bail(LBM_ENOMEM);
     }
     std::memset((void *)P->h_inst, 0, sizeof(Inst) * max_slots);
-    if (hipEventRecord(P->upload_done, P->stream) != hipSuccess) return bail(LBM_EDEVICE);
+    std::memset((void *)P->h_flags, 0, sizeof(int) * max_slots);
+    if (hipMemsetAsync(P->d_flags, 0, sizeof(int) * max_slots, P->stream) != hipSuccess ||
+        hipEventRecord(P->upload_done, P->stream) != hipSuccess)
+        return bail(LBM_EDEVICE);
+    P->B.storage = storage;
+    P->B.ty = P->ty;
+    P->B.lanes = 1;
+    P->B.insts = P->d_inst;
+    P->B.ninst = max_slots;
+    P->B.flags = P->d_flags;
     *out = P;
     return LBM_OK;
 }
@@ -779,13 +814,12 @@ int lbm_pool_admit(lbm_pool *P, const lbm_params *p, const uint8_t *mask, const 
         P->arena.release(off, m.bytes);
         return rc;
     }
-    if (!s.ready) MCLBM_HIP(hipEventCreateWithFlags(&s.ready, hipEventDisableTiming));
     MCLBM_HIP(hipEventRecord(s.ready, P->init_stream));
     // host inputs were copied with pageable memcpy: wait until they are read before returning
     MCLBM_HIP(hipStreamSynchronize(P->init_stream));
     s.used = true;
     s.joined = false;
-    s.released = false;
+    s.broken = false;
     s.off = off;
     s.bytes = m.bytes;
     s.nsteps = nsteps;
@@ -805,6 +839,7 @@ int lbm_pool_advance(lbm_pool *P, int64_t chunk) {
         s.L0 = P->L;
         s.P.I.parity0 = (int)(P->L & 1);
         s.P.I.t_end = P->L + s.nsteps;
+        s.flags_from = P->diag_every > 0 ? first_diag_end(P, P->L) : INT64_MAX;
         s.joined = true;
         P->dirty = true;
     }
@@ -818,8 +853,11 @@ int lbm_pool_advance(lbm_pool *P, int64_t chunk) {
         if (s.used && s.joined) last_end = std::max(last_end, s.P.I.t_end);
     const int64_t n = std::min(chunk, last_end - P->L);
     for (int64_t q = 0; q < n; ++q) {
-        launch_batch(P->storage, P->ty, 1, P->stream, P->lists, P->d_inst, P->d_tiles, (int)(P->L & 1),
-                     (long long)P->L);
+        const bool diag = plain_diag(P->diag_every, P->L);
+        launch_batch(P->B, P->stream, P->L, diag);
+        if (diag)
+            MCLBM_HIP(hipMemcpyAsync(P->h_flags, P->d_flags, sizeof(int) * P->max_slots, hipMemcpyDeviceToHost,
+                                     P->stream));
         P->L += 1;
     }
     MCLBM_HIP(hipGetLastError());
@@ -837,11 +875,25 @@ int lbm_pool_poll(lbm_pool *P, int32_t *slots, int32_t max, int32_t *n) {
     pool_reap_marks(P);
     int c = 0;
     for (int k = 0; k < P->max_slots && c < max; ++k) {
-        const Slot &s = P->slots[k];
-        if (s.used && s.joined && s.P.I.t_end <= P->L_done) slots[c++] = k;
+        Slot &s = P->slots[k];
+        if (!s.used || !s.joined) continue;
+        if (!s.broken && s.P.I.t_end > P->L_done && P->L_done >= s.flags_from && P->h_flags[k] != 0) {
+            // flagged by a diagnostic launch: stop advancing it from the next launch on
+            s.broken = true;
+            s.P.I.t_end = std::min(s.P.I.t_end, P->L);
+            P->dirty = true;
+        }
+        if (s.broken || s.P.I.t_end <= P->L_done) slots[c++] = k;
     }
     *n = c;
     return LBM_OK;
+}
+
+int lbm_pool_status(const lbm_pool *P, int32_t k) {
+    if (!P || k < 0 || k >= P->max_slots) return LBM_EINVAL;
+    const Slot &s = P->slots[k];
+    if (!s.used) return LBM_ENOTFOUND;
+    return s.broken ? LBM_ENUMERIC : LBM_OK;
 }
 
 int lbm_pool_fields(lbm_pool *P, int32_t k, double *rhoA, double *rhoB, double *ux, double *uy) {
@@ -850,9 +902,35 @@ int lbm_pool_fields(lbm_pool *P, int32_t k, double *rhoA, double *rhoB, double *
     if (!s.used || !s.joined) return LBM_ENOTFOUND;
     // finished: the final buffer is the one the launch at t_end would read; else the current one
     const int64_t Lr = std::min(P->L, s.P.I.t_end);
-    const int parity = (int)((s.P.I.parity0 ^ (Lr & 1)) & 1);
     double *outs[4] = {rhoA, rhoB, ux, uy};
-    return read_fields(s.P, parity, (long long)(Lr - s.L0), P->stream, outs);
+    const int rc = read_fields(s.P, slot_parity(P, s), Lr - s.L0, P->stream, outs);
+    return s.broken && rc == LBM_OK ? LBM_ENUMERIC : rc;
+}
+
+int lbm_pool_diag(lbm_pool *P, int32_t k, lbm_diag_t *out) {
+    if (!P || !out || k < 0 || k >= P->max_slots) return LBM_EINVAL;
+    Slot &s = P->slots[k];
+    if (!s.used) return LBM_ENOTFOUND;
+    MCLBM_HIP(hipStreamSynchronize(P->init_stream));
+    const int64_t step = s.joined ? std::min(P->L, s.P.I.t_end) - s.L0 : 0;
+    const int rc = read_diag(s.P, slot_parity(P, s), step, P->stream, out);
+    return s.broken && rc == LBM_OK ? LBM_ENUMERIC : rc;
+}
+
+int lbm_pool_get_state(lbm_pool *P, int32_t k, void *host) {
+    if (!P || !host || k < 0 || k >= P->max_slots) return LBM_EINVAL;
+    Slot &s = P->slots[k];
+    if (!s.used) return LBM_ENOTFOUND;
+    MCLBM_HIP(hipStreamSynchronize(P->init_stream));
+    return copy_state(s.P, slot_parity(P, s), P->stream, host, true);
+}
+
+int lbm_pool_set_state(lbm_pool *P, int32_t k, const void *host) {
+    if (!P || !host || k < 0 || k >= P->max_slots) return LBM_EINVAL;
+    Slot &s = P->slots[k];
+    if (!s.used) return LBM_ENOTFOUND;
+    MCLBM_HIP(hipStreamSynchronize(P->init_stream));
+    return copy_state(s.P, slot_parity(P, s), P->stream, const_cast<void *>(host), false);
 }
 
 int lbm_pool_release(lbm_pool *P, int32_t k) {
@@ -860,7 +938,7 @@ int lbm_pool_release(lbm_pool *P, int32_t k) {
     Slot &s = P->slots[k];
     if (!s.used) return LBM_ENOTFOUND;
     if (!(s.joined && s.P.I.t_end <= P->L_done)) {
-        // cancelling a running solve: its blocks may still be in flight
+        // cancelling a running (or stopped but still enqueued) solve: its blocks may still be in flight
         MCLBM_HIP(hipStreamSynchronize(P->stream));
         MCLBM_HIP(hipStreamSynchronize(P->init_stream));
     }
@@ -868,7 +946,7 @@ int lbm_pool_release(lbm_pool *P, int32_t k) {
     P->in_use -= al(s.bytes);
     s.used = false;
     s.joined = false;
-    s.released = true;
+    s.broken = false;
     P->dirty = true;
     return LBM_OK;
 }

@@ -15,6 +15,7 @@
 
 #include "../../include/mclbm.h"
 #include "lbm_device.hpp"
+#include "lbm_plan.hpp"
 #include "lbm_pair.hpp"
 #include "lbm_sc1.hpp"
 
@@ -217,6 +218,14 @@ inline void fill_inst(Inst &I, const lbm_params &p, const double rref[2], int ty
     I.nt = 1;
     I.parity0 = 0;
     I.t_end = INT64_MAX;
+}
+
+// Graph replay plan (lbm_plan.hpp) with the refusal reported through set_err.
+inline int make_graph_plan(int graph_steps, int diag_every, GraphPlan &g) {
+    if (graph_plan(graph_steps, diag_every, g)) return LBM_OK;
+    set_err("graph_steps %d (%d rounded up to even) and diag_every %d: one must divide the other", graph_steps,
+            (graph_steps + 1) / 2 * 2, diag_every);
+    return LBM_EINVAL;
 }
 
 // ---------------------------------------------------------------- set-up kernels
@@ -478,9 +487,9 @@ __global__ __launch_bounds__(threads_for(TY)) void k_step_sc1(Inst I, int parity
 }
 
 // Final FP64 reduction of the per-tile partials in a fixed order, the drift
-// check against step 0 and the sticky failure flags.  One block.
-static __global__ __launch_bounds__(256) void k_diag_reduce(const double *__restrict__ partials, int nblocks,
-                                                            DiagDev *dd, long long step) {
+// check against step 0 and the sticky failure flags, by one block of 256
+// threads; returns the flags in thread 0.
+__device__ __forceinline__ int diag_reduce_block(const double *__restrict__ partials, int nblocks, DiagDev *dd) {
     __shared__ double red[256][5];
     __shared__ int redi[256];
     double s[4] = {0, 0, 0, 0}, m = 0.0;
@@ -510,7 +519,6 @@ static __global__ __launch_bounds__(256) void k_diag_reduce(const double *__rest
         dd->mom[0] = red[0][2];
         dd->mom[1] = red[0][3];
         dd->max_speed = sqrt(red[0][4]);
-        if (step >= 0) dd->step = step;
         if (!dd->have_mass0) {
             dd->mass0[0] = red[0][0];
             dd->mass0[1] = red[0][1];
@@ -522,7 +530,14 @@ static __global__ __launch_bounds__(256) void k_diag_reduce(const double *__rest
                 if (m0 > 0.0 && fabs(red[0][c] - m0) > dd->drift_tol * m0) ff |= 4;
             }
         dd->flags |= ff;
+        return dd->flags;
     }
+    return 0;
+}
+
+static __global__ __launch_bounds__(256) void k_diag_reduce(const double *__restrict__ partials, int nblocks,
+                                                            DiagDev *dd) {
+    (void)diag_reduce_block(partials, nblocks, dd);
 }
 
 // Runtime dispatch over (storage, tile rows, BC, mode, diag, model).
@@ -591,9 +606,9 @@ inline void launch1(const Launch &L, dim3 g, hipStream_t s, const Inst &I, int p
 }
 
 // One step (or fields pass) of one simulation; with diagnostics, followed by
-// the one-block reduction (step < 0 leaves the recorded time unchanged).
+// the one-block reduction.
 inline void launch_step(const Launch &L, hipStream_t s, const Inst &I, int parity, const Fields &fo,
-                        double *partials, DiagDev *dd, long long step) {
+                        double *partials, DiagDev *dd) {
     const int nt = I.tiles_x * I.tiles_y;
     dim3 g((unsigned)nt);
     if (L.storage == LBM_STORE_F16)
@@ -601,7 +616,7 @@ inline void launch_step(const Launch &L, hipStream_t s, const Inst &I, int parit
     else
         launch1<float>(L, g, s, I, parity, fo, partials);
     if (L.diag || L.mode == MODE_FIELDS)
-        hipLaunchKernelGGL(k_diag_reduce, dim3(1), dim3(256), 0, s, partials, nt, dd, step);
+        hipLaunchKernelGGL(k_diag_reduce, dim3(1), dim3(256), 0, s, partials, nt, dd);
 }
 
 }  // namespace mclbm

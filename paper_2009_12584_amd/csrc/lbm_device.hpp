@@ -207,6 +207,17 @@ __device__ __forceinline__ double dsum9(const float d[9]) {
 // is its rounding.  Summed in FP32 in direction order by every step kernel.
 __device__ __forceinline__ float remainder_term(float d, float q) { return d - q; }
 
+// FP64 reduction targets of one simulation.
+struct DiagDev {
+    double mass[2];
+    double mass0[2];
+    double mom[2];
+    double max_speed;
+    int flags;
+    int have_mass0;
+    double drift_tol;
+};
+
 // Everything one simulation needs on the device.  The single-instance kernels
 // take it by value; the batched kernels read it from a table.
 struct Inst {
@@ -228,18 +239,8 @@ struct Inst {
     int nt;                   // streaming (non-temporal) stores
     int parity0;              // pool: parity of the buffer read at launch counter 0
     int64_t t_end;            // pool: launch counter at which this instance stops
-};
-
-// FP64 reduction targets of one simulation.
-struct DiagDev {
-    double mass[2];
-    double mass0[2];
-    double mom[2];
-    double max_speed;
-    long long step;
-    int flags;
-    int have_mass0;
-    double drift_tol;
+    DiagDev *dd;              // batch and pool: this instance's FP64 reduction targets
+    int tile0, ntl;           // batch and pool: its tiles' range in the flattened tile list
 };
 
 struct Fields {  // fields mode outputs, unpadded nx * ny planes, any may be null

@@ -22,9 +22,10 @@ struct lbm_handle {
     int64_t t = 0;
     int sticky = LBM_OK;
     std::string err;
-    hipGraphExec_t gexec = nullptr;
-    hipGraph_t graph = nullptr;
-    int glen = 0;
+    GraphPlan plan;
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    int64_t graph_run = 0, plain_run = 0;  // steps run by graph replays and by plain launches
 };
 
 namespace {
@@ -37,8 +38,10 @@ int fail(lbm_handle *h, int code) {
 void release(lbm_handle *h) {
     if (!h) return;
     if (h->stream) (void)hipStreamSynchronize(h->stream);
-    if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
-    if (h->graph) (void)hipGraphDestroy(h->graph);
+    for (int v = 0; v < 2; ++v) {
+        if (h->gexec[v]) (void)hipGraphExecDestroy(h->gexec[v]);
+        if (h->graph[v]) (void)hipGraphDestroy(h->graph[v]);
+    }
     for (void *q : {(void *)h->I.buf[0], (void *)h->I.buf[1], (void *)h->word, (void *)h->m25, (void *)h->tflag,
                     (void *)h->nbr, (void *)h->cls, (void *)h->partials, (void *)h->dd, (void *)h->fields,
                     (void *)h->cwork, (void *)h->rho1})
@@ -52,8 +55,7 @@ Launch launch_of(const lbm_handle *h, int mode, bool diag) {
 }
 
 int run_fields(lbm_handle *h, const Fields &fo) {
-    launch_step(launch_of(h, MODE_FIELDS, true), h->stream, h->I, (int)(h->t & 1), fo, h->partials, h->dd,
-                (long long)h->t);
+    launch_step(launch_of(h, MODE_FIELDS, true), h->stream, h->I, (int)(h->t & 1), fo, h->partials, h->dd);
     MCLBM_HIP(hipGetLastError());
     return LBM_OK;
 }
@@ -71,17 +73,18 @@ Fields fields_at(float *base, size_t n) {
     return f;
 }
 
-int build_graph(lbm_handle *h) {
-    const int K = (h->p.graph_steps + 1) / 2 * 2;
-    MCLBM_HIP(hipStreamBeginCapture(h->stream, hipStreamCaptureModeRelaxed));
+// Captures the step graphs of the replay plan (graph_plan in lbm_common.hpp).
+int build_graphs(lbm_handle *h) {
     Fields none{};
-    for (int s = 0; s < K; ++s) {
-        const bool diag = h->p.diag_every > 0 && s == K - 1;
-        launch_step(launch_of(h, MODE_STEP, diag), h->stream, h->I, s & 1, none, h->partials, h->dd, -1);
+    const GraphPlan &g = h->plan;
+    for (int v = 0; v < graph_variants(g); ++v) {
+        MCLBM_HIP(hipStreamBeginCapture(h->stream, hipStreamCaptureModeRelaxed));
+        for (int s = 0; s < g.glen; ++s)
+            launch_step(launch_of(h, MODE_STEP, graph_diag(g, v, s)), h->stream, h->I, s & 1, none, h->partials,
+                        h->dd);
+        MCLBM_HIP(hipStreamEndCapture(h->stream, &h->graph[v]));
+        MCLBM_HIP(hipGraphInstantiate(&h->gexec[v], h->graph[v], nullptr, nullptr, 0));
     }
-    MCLBM_HIP(hipStreamEndCapture(h->stream, &h->graph));
-    MCLBM_HIP(hipGraphInstantiate(&h->gexec, h->graph, nullptr, nullptr, 0));
-    h->glen = K;
     return LBM_OK;
 }
 
@@ -113,8 +116,12 @@ int lbm_create(const lbm_params *p, const uint8_t *mask, const double *rhoA0, co
     *out = nullptr;
     int rc = validate(p, mask, rhoA0, rhoB0);
     if (rc) return rc;
+    GraphPlan plan;
+    rc = make_graph_plan(p->graph_steps, p->diag_every, plan);
+    if (rc) return rc;
     lbm_handle *h = new lbm_handle();
     h->p = *p;
+    h->plan = plan;
     h->ty = default_ty(*p);
     h->stream = (hipStream_t)stream;
     auto bail = [&](int code) {
@@ -178,8 +185,8 @@ int lbm_create(const lbm_params *p, const uint8_t *mask, const double *rhoA0, co
     for (void *q : {(void *)dmask, (void *)word0, (void *)drA, (void *)drB})
         if (q) (void)hipFree(q);
     if (rc) return bail(rc);
-    if (p->graph_steps > 0) {
-        rc = build_graph(h);
+    if (plan.glen > 0) {
+        rc = build_graphs(h);
         if (rc) return bail(rc);
     }
     *out = h;
@@ -193,17 +200,20 @@ int lbm_step(lbm_handle *h, int64_t nsteps) {
     }
     if (h->sticky) return h->sticky;
     Fields none{};
+    const int64_t glen = h->plan.glen;
     while (nsteps > 0) {
-        if (h->gexec && (h->t & 1) == 0 && nsteps >= h->glen) {
-            MCLBM_HIP(hipGraphLaunch(h->gexec, h->stream));
-            h->t += h->glen;
-            nsteps -= h->glen;
+        const int v = next_launch(h->plan, h->t, nsteps);
+        if (v >= 0) {
+            MCLBM_HIP(hipGraphLaunch(h->gexec[v], h->stream));
+            h->t += glen;
+            h->graph_run += glen;
+            nsteps -= glen;
             continue;
         }
-        const bool diag = h->p.diag_every > 0 && ((h->t + 1) % h->p.diag_every) == 0;
-        launch_step(launch_of(h, MODE_STEP, diag), h->stream, h->I, (int)(h->t & 1), none, h->partials, h->dd,
-                    (long long)h->t);
+        launch_step(launch_of(h, MODE_STEP, plain_diag(h->p.diag_every, h->t)), h->stream, h->I, (int)(h->t & 1),
+                    none, h->partials, h->dd);
         h->t += 1;
+        h->plain_run += 1;
         nsteps -= 1;
     }
     hipError_t e = hipGetLastError();
@@ -215,6 +225,13 @@ int lbm_step(lbm_handle *h, int64_t nsteps) {
 }
 
 int64_t lbm_time(const lbm_handle *h) { return h ? h->t : -1; }
+
+int lbm_launch_counts(const lbm_handle *h, int64_t *graph_steps, int64_t *plain_steps) {
+    if (!h) return LBM_EINVAL;
+    if (graph_steps) *graph_steps = h->graph_run;
+    if (plain_steps) *plain_steps = h->plain_run;
+    return LBM_OK;
+}
 
 int lbm_fields_device(lbm_handle *h, float *rhoA, float *rhoB, float *ux, float *uy) {
     if (!h) return LBM_EINVAL;

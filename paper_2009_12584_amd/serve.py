@@ -6,8 +6,11 @@ whenever the pool has a free slot and HBM budget (lbm_pool_admit), advances
 every active slot together in chunks of time steps (lbm_pool_advance: one
 batched launch per step; new slots join at the next chunk while older ones
 keep running), and retires finished slots (lbm_pool_poll / fields / release)
-without stopping the others.  Completion latency = retirement time - arrival
-time.  All stepping happens in the HIP library; this loop only schedules.
+without stopping the others.  With diag_every > 0 the pool's fused
+diagnostics flag a solve that breaks (non-finite or negative density, mass
+drift); it is retired at once, marked failed, and the others go on.
+Completion latency = retirement time - arrival time.  All stepping happens in
+the HIP library; this loop only schedules.
 """
 from __future__ import annotations
 
@@ -40,6 +43,7 @@ class Done:
     steps: int
     fluid: int
     fields: tuple | None = field(default=None, repr=False)
+    failed: bool = False
 
     @property
     def latency(self) -> float:
@@ -47,7 +51,8 @@ class Done:
 
 
 def serve(requests, *, hbm_budget, max_slots, storage="f32", chunk=200, depth=2, keep_fields=False, stream=None,
-          time_scale=1.0, idle_sleep=0.0002, policy="fifo", pool_factory=None, clock=None, sleep=None):
+          time_scale=1.0, idle_sleep=0.0002, policy="fifo", pool_factory=None, clock=None, sleep=None,
+          diag_every=0):
     """Run the trace; returns (list of Done, makespan seconds).
 
     At most `depth` chunks are in flight on the device, so a new solve waits
@@ -68,7 +73,7 @@ def serve(requests, *, hbm_budget, max_slots, storage="f32", chunk=200, depth=2,
     for r in reqs:
         if not r.fluid:
             r.fluid = int((np.asarray(r.mask) == 0).sum())
-    pool = (pool_factory or Pool)(hbm_budget, max_slots, storage=storage, stream=stream)
+    pool = (pool_factory or Pool)(hbm_budget, max_slots, storage=storage, diag_every=diag_every, stream=stream)
     queue = []
     live = {}
     done = []
@@ -100,9 +105,10 @@ def serve(requests, *, hbm_budget, max_slots, storage="f32", chunk=200, depth=2,
             finished = pool.poll() if live else []
             for slot in finished:
                 r, ta = live.pop(slot)
-                f = pool.fields(slot) if keep_fields else None
+                failed = pool.status(slot) != 0
+                f = pool.fields(slot, raise_on_flags=False) if keep_fields else None
                 pool.release(slot)
-                done.append(Done(r.tag, r.arrival * time_scale, ta, now_fn() - t0, r.steps, r.fluid, f))
+                done.append(Done(r.tag, r.arrival * time_scale, ta, now_fn() - t0, r.steps, r.fluid, f, failed))
             if not finished and not queue and nxt < len(reqs) and not live:
                 # nothing to do until the next arrival
                 sleep_fn(max(0.0, min(0.01, reqs[nxt].arrival * time_scale - (now_fn() - t0))))
@@ -114,9 +120,15 @@ def serve(requests, *, hbm_budget, max_slots, storage="f32", chunk=200, depth=2,
     return done, makespan
 
 
+def percentile(values, q):
+    """The percentile rule every latency summary here uses: linear
+    interpolation between order statistics (numpy's default)."""
+    return float(np.percentile(np.asarray(values, dtype=float), q))
+
+
 def summarize(done, makespan):
-    lat = np.array([d.latency for d in done])
-    lu = float(sum(d.fluid * d.steps for d in done))
-    return dict(requests=len(done), makespan_s=makespan, p50_latency_s=float(np.percentile(lat, 50)),
-                p99_latency_s=float(np.percentile(lat, 99)), mean_latency_s=float(lat.mean()),
-                fluid_mlups=lu / makespan / 1e6)
+    lat = [d.latency for d in done]
+    lu = float(sum(d.fluid * d.steps for d in done if not d.failed))
+    return dict(requests=len(done), failed=sum(1 for d in done if d.failed), makespan_s=makespan,
+                p50_latency_s=percentile(lat, 50), p99_latency_s=percentile(lat, 99),
+                mean_latency_s=float(np.mean(lat)), fluid_mlups=lu / makespan / 1e6)

@@ -24,6 +24,24 @@ def _host(a, dtype, shape):
     return a
 
 
+def _diag_dict(d) -> dict:
+    return dict(mass=(d.mass[0], d.mass[1]), mass0=(d.mass0[0], d.mass0[1]),
+                momentum=(d.momentum[0], d.momentum[1]), max_speed=d.max_speed, step=d.step, flags=d.flags)
+
+
+def _checked(code, handle=None, raise_on_flags=True):
+    """check(), except that LBM_ENUMERIC may be returned instead of raised."""
+    if code == capi.LBM_ENUMERIC and not raise_on_flags:
+        return code
+    return check(code, handle)
+
+
+def state_bytes(nx, ny, storage="f32", **prm) -> int:
+    """Bytes of one simulation's raw state (lbm_params_state_bytes)."""
+    p = capi.make_params(nx, ny, storage=storage, **prm)
+    return int(lib().lbm_params_state_bytes(ctypes.byref(p)))
+
+
 def _circle(c) -> dict:
     return dict(n=int(c.n), xc=c.xc, yc=c.yc, R=c.R, rms=c.rms, max_dev=c.max_dev)
 
@@ -93,6 +111,12 @@ class Simulation:
     def step(self, n: int = 1):
         check(lib().lbm_step(self._h, int(n)), self._h)
 
+    def launch_counts(self) -> dict:
+        """Steps run so far by graph replays and by plain launches."""
+        g, p = ctypes.c_int64(), ctypes.c_int64()
+        check(lib().lbm_launch_counts(self._h, ctypes.byref(g), ctypes.byref(p)), self._h)
+        return {"graph_steps": int(g.value), "plain_steps": int(p.value)}
+
     def _grids(self, k):
         return [np.zeros((self.ny, self.nx)) for _ in range(k)]
 
@@ -116,11 +140,8 @@ class Simulation:
 
     def diag(self, raise_on_flags=True) -> dict:
         d = capi.LbmDiag()
-        code = lib().lbm_diag(self._h, ctypes.byref(d))
-        if code != capi.LBM_ENUMERIC or raise_on_flags:
-            check(code, self._h)
-        return dict(mass=(d.mass[0], d.mass[1]), mass0=(d.mass0[0], d.mass0[1]),
-                    momentum=(d.momentum[0], d.momentum[1]), max_speed=d.max_speed, step=d.step, flags=d.flags)
+        _checked(lib().lbm_diag(self._h, ctypes.byref(d)), self._h, raise_on_flags)
+        return _diag_dict(d)
 
     def contour_fit(self, level=0.5, skip=3, roi=None) -> dict:
         """Circle through the interface rho^A = level (lbm_contour_fit)."""
@@ -176,6 +197,7 @@ class Batch:
             P[k] = capi.make_params(nx, ny, storage=storage, tile_y=tile_y, lanes=lanes, **prm)
             masks[k], ras[k], rbs[k] = mask.ctypes.data, rA.ctypes.data, rB.ctypes.data
             self.shapes.append((ny, nx))
+        self._state_bytes = [int(lib().lbm_params_state_bytes(ctypes.byref(P[k]))) for k in range(n)]
         h = ctypes.c_void_p()
         check(lib().lbm_batch_create(n, P, masks, ras, rbs, _stream_handle(stream), int(graph_steps),
                                      ctypes.byref(h)))
@@ -189,17 +211,35 @@ class Batch:
     def step(self, n=1):
         check(lib().lbm_batch_step(self._h, int(n)))
 
-    def fields(self, idx, which=(True, True, True, True)):
+    def launch_counts(self) -> dict:
+        """Steps run so far by graph replays and by plain launches."""
+        g, p = ctypes.c_int64(), ctypes.c_int64()
+        check(lib().lbm_batch_launch_counts(self._h, ctypes.byref(g), ctypes.byref(p)))
+        return {"graph_steps": int(g.value), "plain_steps": int(p.value)}
+
+    def fields(self, idx, which=(True, True, True, True), raise_on_flags=True):
         """(rhoA, rhoB, ux, uy) of instance idx; entries not in `which` are None."""
         ny, nx = self.shapes[idx]
         a = [np.zeros((ny, nx)) if w else None for w in which]
-        check(lib().lbm_batch_fields(self._h, int(idx), *[_p(x) if x is not None else None for x in a]))
+        _checked(lib().lbm_batch_fields(self._h, int(idx), *[_p(x) if x is not None else None for x in a]),
+                 raise_on_flags=raise_on_flags)
         return tuple(a)
 
-    def diag(self, idx):
+    def diag(self, idx, raise_on_flags=True):
         d = capi.LbmDiag()
-        check(lib().lbm_batch_diag(self._h, int(idx), ctypes.byref(d)))
-        return dict(mass=(d.mass[0], d.mass[1]), mass0=(d.mass0[0], d.mass0[1]), step=d.step, flags=d.flags)
+        _checked(lib().lbm_batch_diag(self._h, int(idx), ctypes.byref(d)), raise_on_flags=raise_on_flags)
+        return _diag_dict(d)
+
+    def get_state(self, idx):
+        ny, nx = self.shapes[idx]
+        buf = np.zeros(self._state_bytes[idx], np.uint8)
+        check(lib().lbm_batch_get_state(self._h, int(idx), _p(buf)))
+        return buf
+
+    def set_state(self, idx, buf):
+        buf = np.ascontiguousarray(buf, np.uint8)
+        assert buf.size == self._state_bytes[idx]
+        check(lib().lbm_batch_set_state(self._h, int(idx), _p(buf)))
 
     def contour_fit(self, idx, level=0.5, skip=3, roi=None) -> dict:
         c = capi.LbmCircle()
@@ -223,13 +263,15 @@ class Batch:
 class Pool:
     """Resident slots with continuous batching (lbm_pool_*)."""
 
-    def __init__(self, hbm_budget, max_slots, *, storage="f32", stream=None):
+    def __init__(self, hbm_budget, max_slots, *, storage="f32", diag_every=0, stream=None):
         h = ctypes.c_void_p()
         st = capi.STORE_F16 if storage in ("f16", capi.STORE_F16) else capi.STORE_F32
         self.storage = st
-        check(lib().lbm_pool_create(int(hbm_budget), int(max_slots), st, _stream_handle(stream), ctypes.byref(h)))
+        check(lib().lbm_pool_create(int(hbm_budget), int(max_slots), st, int(diag_every), _stream_handle(stream),
+                                    ctypes.byref(h)))
         self._h = h
         self.shapes = {}
+        self._state_bytes = {}
 
     @staticmethod
     def footprint(nx, ny, storage="f32", **prm):
@@ -250,6 +292,7 @@ class Pool:
             return None
         check(code)
         self.shapes[slot.value] = (ny, nx)
+        self._state_bytes[slot.value] = int(lib().lbm_params_state_bytes(ctypes.byref(p)))
         return slot.value
 
     def advance(self, chunk):
@@ -261,15 +304,38 @@ class Pool:
         check(lib().lbm_pool_poll(self._h, out, int(max_n), ctypes.byref(n)))
         return [out[i] for i in range(n.value)]
 
-    def fields(self, slot):
+    def fields(self, slot, raise_on_flags=True):
         ny, nx = self.shapes[slot]
         a = [np.zeros((ny, nx)) for _ in range(4)]
-        check(lib().lbm_pool_fields(self._h, int(slot), *[_p(x) for x in a]))
+        _checked(lib().lbm_pool_fields(self._h, int(slot), *[_p(x) for x in a]), raise_on_flags=raise_on_flags)
         return tuple(a)
+
+    def status(self, slot) -> int:
+        """LBM_OK, or LBM_ENUMERIC once poll() has reported the slot broken (no device wait)."""
+        code = int(lib().lbm_pool_status(self._h, int(slot)))
+        if code not in (capi.LBM_OK, capi.LBM_ENUMERIC):
+            check(code)
+        return code
+
+    def diag(self, slot, raise_on_flags=True):
+        d = capi.LbmDiag()
+        _checked(lib().lbm_pool_diag(self._h, int(slot), ctypes.byref(d)), raise_on_flags=raise_on_flags)
+        return _diag_dict(d)
+
+    def get_state(self, slot):
+        buf = np.zeros(self._state_bytes[slot], np.uint8)
+        check(lib().lbm_pool_get_state(self._h, int(slot), _p(buf)))
+        return buf
+
+    def set_state(self, slot, buf):
+        buf = np.ascontiguousarray(buf, np.uint8)
+        assert buf.size == self._state_bytes[slot]
+        check(lib().lbm_pool_set_state(self._h, int(slot), _p(buf)))
 
     def release(self, slot):
         check(lib().lbm_pool_release(self._h, int(slot)))
         self.shapes.pop(slot, None)
+        self._state_bytes.pop(slot, None)
 
     def progress(self):
         """(launches enqueued, launches completed on the device)."""

@@ -58,6 +58,8 @@ def _sim(**kw):
     (dict(model=1, rho0=0.0), "single-component"),
     (dict(model=0, rB=None), "rhoB0"),
     (dict(lanes=3), "lanes"),
+    (dict(graph_steps=16, diag_every=6), "divide"),
+    (dict(graph_steps=7, diag_every=12), "divide"),
 ])
 def test_invalid_problems_rejected_on_host(kw, needle):
     import paper_2009_12584_amd as M
@@ -73,6 +75,16 @@ def test_strerror_names_codes():
 
     for code in (0, -1, -2, -3, -4, -5, -6):
         assert capi.lib().lbm_strerror(code).decode() != "unknown error"
+
+
+def test_state_bytes_of_a_parameter_set():
+    """The raw state is one population buffer: 9 planes of (A, B) pairs at a
+    row pitch rounded up to 64 nodes, FP32; FP16 adds the FP32 rest plane."""
+    from paper_2009_12584_amd.sim import state_bytes
+
+    assert state_bytes(100, 30) == 9 * 30 * 128 * 8
+    assert state_bytes(100, 30, storage="f16") == 30 * 128 * (9 * 4 + 8)
+    assert state_bytes(0, 30) == 0
 
 
 def test_pool_footprint_counts_both_buffers():

@@ -135,14 +135,16 @@ def test_fp16_batch_and_pool_match_single_fp16(M):
     b.close()
 
 
-def test_pool_results_same_alone_and_in_the_mix(M):
+def test_pool_results_same_alone_and_in_the_mix(M, ora):
     """Continuous batching: requests join while others run, each stops at its own
-    step count, and each result equals the same solve run alone."""
+    step count, and each result equals the same solve run alone (bit for bit)
+    and the FP64 oracle within the FP32 bar.  The pool runs its fused
+    diagnostics every 7 launches, which must not change any result."""
     cases = small_cases(6, seed=11)
     masks = masks_of(M, cases)
     steps = [37, 80, 15, 64, 101, 50]
     budget = sum(M.Pool.footprint(c.nx, c.ny) for c in cases[:3]) + 4096
-    pool = M.Pool(budget, 4)
+    pool = M.Pool(budget, 4, diag_every=7)
     slots = {}
     pending = list(range(len(cases)))
     done = {}
@@ -177,6 +179,125 @@ def test_pool_results_same_alone_and_in_the_mix(M):
         s.close()
         for x, y in zip(done[k], ref):
             assert np.array_equal(x, y), k
+        o = ora.Oracle(masks[k], c.rhoA0, c.rhoB0, **c.params())
+        o.step(steps[k])
+        of = o.fields()
+        fl = masks[k] == 0
+        got = done[k]
+        er = max(np.max(np.abs(got[0] - of[0])[fl] / of[0][fl]), np.max(np.abs(got[1] - of[1])[fl] / of[1][fl]))
+        eu = max(np.max(np.abs(got[2] - of[2])[fl]), np.max(np.abs(got[3] - of[3])[fl]))
+        say("pooled request %d (%dx%d, rule %d, %d steps) vs oracle: rel rho %.2e abs u %.2e"
+            % (k, c.nx, c.ny, c.bc, steps[k], er, eu))
+        assert er <= 1e-5 and eu <= 1e-6, (k, er, eu)
+
+
+def nan_state(nbytes):
+    return np.full(nbytes // 4, np.nan, np.float32).view(np.uint8)
+
+
+def test_batch_flags_one_broken_instance_and_the_others_go_on(M):
+    """Failure handling forced from the host: a state of NaNs written into one
+    instance of a batch (graphs of 10 steps, diagnostics every 10) makes that
+    instance's diagnostics and fields return LBM_ENUMERIC; the other
+    instances stay bit-identical to a batch without the broken one."""
+    from paper_2009_12584_amd.capi import LBM_ENUMERIC, LbmError
+
+    cases = small_cases(3, seed=31)
+    masks = masks_of(M, cases)
+    items = [(m, c.rhoA0, c.rhoB0, dict(c.params(), diag_every=10, drift_tol=1e-4)) for m, c in zip(masks, cases)]
+    b = M.Batch(items, graph_steps=10)
+    ref = M.Batch(items, graph_steps=10)
+    b.step(20)
+    ref.step(20)
+    b.set_state(1, nan_state(b.get_state(1).size))
+    b.step(30)
+    ref.step(30)
+    with pytest.raises(LbmError) as e:
+        b.diag(1)
+    assert e.value.code == LBM_ENUMERIC
+    assert b.diag(1, raise_on_flags=False)["flags"] & 1
+    with pytest.raises(LbmError) as e:
+        b.fields(1)
+    assert e.value.code == LBM_ENUMERIC
+    for k in (0, 2):
+        assert b.diag(k)["flags"] == 0
+        for x, y in zip(b.fields(k), ref.fields(k)):
+            assert np.array_equal(x, y), k
+    assert b.launch_counts() == {"graph_steps": 50, "plain_steps": 0}
+    b.close()
+    ref.close()
+
+
+def test_pool_reports_a_broken_slot_and_the_others_finish(M):
+    """A slot whose state is made of NaNs (written from the host before it
+    runs) is flagged by the pool's cadence diagnostics: poll reports it long
+    before its step count, its status and fields say LBM_ENUMERIC, and the
+    other slots finish with the results of the same solves run alone."""
+    from paper_2009_12584_amd.capi import LBM_ENUMERIC, LbmError
+
+    cases = small_cases(3, seed=41)
+    masks = masks_of(M, cases)
+    steps = [60, 400, 45]
+    pool = M.Pool(1 << 30, 4, diag_every=5)
+    slots = {}
+    for k, (m, c) in enumerate(zip(masks, cases)):
+        slots[pool.admit(m, c.rhoA0, c.rhoB0, steps[k], **c.params())] = k
+    broken = [s for s, k in slots.items() if k == 1][0]
+    pool.set_state(broken, nan_state(pool.get_state(broken).size))
+    done, flagged_at = {}, None
+    for _ in range(20000):
+        pool.advance(5)
+        for s in pool.poll():
+            k = slots.pop(s)
+            if k == 1:
+                flagged_at = pool.progress()[0]
+                assert pool.status(s) == LBM_ENUMERIC
+                with pytest.raises(LbmError) as e:
+                    pool.fields(s)
+                assert e.value.code == LBM_ENUMERIC
+                assert pool.diag(s, raise_on_flags=False)["flags"] & 1
+            else:
+                assert pool.status(s) == 0
+                done[k] = pool.fields(s)
+            pool.release(s)
+        if not slots:
+            break
+        time.sleep(0.001)
+    assert not slots and flagged_at is not None and flagged_at < steps[1]
+    say("broken slot reported after %d launches (its step count: %d)" % (flagged_at, steps[1]))
+    pool.close()
+    for k in (0, 2):
+        c = cases[k]
+        s = M.Simulation(masks[k], c.rhoA0, c.rhoB0, **c.params())
+        s.step(steps[k])
+        for x, y in zip(done[k], s.fields()):
+            assert np.array_equal(x, y), k
+        s.close()
+
+
+def test_pool_checkpoint_resume_bit_exact(M):
+    """A slot's state taken mid-run and written into a fresh slot admitted for
+    the remaining steps resumes bit for bit."""
+    c = small_cases(1, seed=51)[0]
+    m = masks_of(M, [c])[0]
+    pool = M.Pool(1 << 30, 2)
+    a = pool.admit(m, c.rhoA0, c.rhoB0, 90, **c.params())
+    pool.advance(33)
+    st = pool.get_state(a)
+    b = pool.admit(m, c.rhoA0, c.rhoB0, 57, **c.params())
+    pool.set_state(b, st)
+    results = {}
+    for _ in range(20000):
+        pool.advance(20)
+        for s in pool.poll():
+            results[s] = pool.fields(s)
+            pool.release(s)
+        if len(results) == 2:
+            break
+        time.sleep(0.001)
+    pool.close()
+    for x, y in zip(results[a], results[b]):
+        assert np.array_equal(x, y)
 
 
 def test_pool_admission_limits(M):

@@ -248,11 +248,15 @@ def test_graph_replay_matches_plain_launches(gpu, ora):
     mask = gpu_mask(gpu, c)
     a = gpu.Simulation(mask, c.rhoA0, c.rhoB0, **c.params())
     b = gpu.Simulation(mask, c.rhoA0, c.rhoB0, graph_steps=16, diag_every=1, lanes=2, **c.params())
-    for n in (1, 40, 33, 64):  # odd counts fall back to plain launches until even again
+    # graphs replay from multiples of 16 only, plain launches in between:
+    # 1 plain; 15 plain, 16 graph, 9 plain; 7, 16, 10; 6, 48, 10
+    for n in (1, 40, 33, 64):
         a.step(n)
         b.step(n)
         for x, y in zip(a.fields(), b.fields()):
             assert np.array_equal(x, y)
+    assert b.launch_counts() == {"graph_steps": 80, "plain_steps": 58}
+    assert a.launch_counts() == {"graph_steps": 0, "plain_steps": 138}
     a.close()
     b.close()
 

@@ -40,7 +40,8 @@ class FakePool:
             return None
         s = self.next_id
         self.next_id += 1
-        self.slots[s] = dict(L0=self.launched, steps=nsteps, bytes=need, done=False, tag=prm.get("tag"))
+        self.slots[s] = dict(L0=self.launched, steps=nsteps, bytes=need, done=False, tag=prm.get("tag"),
+                             fail_at=prm.get("fail_at"), broken=False)
         self.used += need
         assert self.used <= self.budget
         self.admitted.append(s)
@@ -66,12 +67,21 @@ class FakePool:
         c = self.completed()
         out = []
         for s, v in self.slots.items():
-            if not v["done"] and v["L0"] + v["steps"] <= c:
+            if v["done"]:
+                continue
+            if v["fail_at"] is not None and v["L0"] + v["fail_at"] <= c:
+                # the library reports a slot its diagnostics flagged, and stops it
+                v["done"] = v["broken"] = True
+                out.append(s)
+            elif v["L0"] + v["steps"] <= c:
                 v["done"] = True
                 out.append(s)
         return out[:max_n]
 
-    def fields(self, slot):
+    def status(self, slot):
+        return -5 if self.slots[slot]["broken"] else 0
+
+    def fields(self, slot, raise_on_flags=True):
         return None
 
     def release(self, slot):
@@ -160,3 +170,19 @@ def test_a_request_larger_than_the_pool_is_refused():
     with pytest.raises(ValueError, match="does not fit an empty pool"):
         run(reqs, clock, budget=1000)
     assert FakePool.instances[-1].closed
+
+
+def test_a_solve_flagged_broken_is_retired_failed_and_the_others_finish():
+    """A request whose slot the pool's diagnostics flag (a non-finite density)
+    is retired as soon as the pool reports it, marked failed, and counted out
+    of the throughput; the other requests complete at their own step counts."""
+    clock = Clock()
+    reqs = make_requests([(0.0, 8, 8, 400, "a"), (0.0, 8, 8, 400, "bad"), (0.0, 8, 8, 400, "c")])
+    reqs[1].params = {"fail_at": 50}
+    done, makespan, _ = run(reqs, clock)
+    by = {d.tag: d for d in done}
+    assert by["bad"].failed and not by["a"].failed and not by["c"].failed
+    assert by["bad"].finished < by["a"].finished
+    s = summarize(done, makespan)
+    assert s["requests"] == 3 and s["failed"] == 1
+    assert s["fluid_mlups"] == pytest.approx(2 * 64 * 400 / makespan / 1e6)
