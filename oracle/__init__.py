@@ -108,6 +108,7 @@ def lib():
         L.ora_equilibrium.argtypes = [D, D, D, P]
         L.ora_guo_source.argtypes = [D, D, D, D, D, P]
         L.ora_threads.restype = I
+        L.ora_set_threads.argtypes = [I]
         _lib = L
     return _lib
 
@@ -118,6 +119,11 @@ def _ptr(a: np.ndarray):
 
 def threads() -> int:
     return int(lib().ora_threads())
+
+
+def set_threads(n: int) -> None:
+    """Threads of the following oracle calls in this process."""
+    lib().ora_set_threads(int(n))
 
 
 def lattice():

@@ -597,3 +597,11 @@ int ora_threads(void) {
     return 1;
 #endif
 }
+
+void ora_set_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}

@@ -59,6 +59,8 @@ void ora_lattice(double *w9, int *cx, int *cy, int *opp, double *w25, int *ex, i
 void ora_equilibrium(double rho, double ux, double uy, double *feq);
 void ora_guo_source(double tau, double ux, double uy, double Fx, double Fy, double *S);
 int ora_threads(void);
+/* threads of the following oracle calls in this process (n > 0) */
+void ora_set_threads(int n);
 
 #ifdef __cplusplus
 }

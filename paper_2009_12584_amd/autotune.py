@@ -105,6 +105,8 @@ def launch_config_for_batch(items, *, storage="f32", steps=50, stream=None):
     """Fastest {"tile_y", "lanes"} for a batch (one shape for all its instances)."""
     import torch
 
+    # timed without the fused diagnostics (their cadence need not fit these graphs)
+    items = [(m, a, b, dict(p, diag_every=0)) for m, a, b, p in items]
     best, best_t = CANDIDATES[0], float("inf")
     for ty, lanes in CANDIDATES:
         b = Batch(items, storage=storage, tile_y=ty, lanes=lanes, stream=stream, graph_steps=steps)

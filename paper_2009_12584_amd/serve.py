@@ -52,7 +52,7 @@ class Done:
 
 def serve(requests, *, hbm_budget, max_slots, storage="f32", chunk=200, depth=2, keep_fields=False, stream=None,
           time_scale=1.0, idle_sleep=0.0002, policy="fifo", pool_factory=None, clock=None, sleep=None,
-          diag_every=0):
+          diag_every=0, keep_tags=None):
     """Run the trace; returns (list of Done, makespan seconds).
 
     At most `depth` chunks are in flight on the device, so a new solve waits
@@ -64,7 +64,8 @@ def serve(requests, *, hbm_budget, max_slots, storage="f32", chunk=200, depth=2,
     the device among everything that has arrived.  pool_factory, clock and
     sleep replace the device pool (Pool's constructor and methods), the wall
     clock (time.perf_counter) and time.sleep, so that the scheduling logic
-    can run against a simulated device and clock."""
+    can run against a simulated device and clock.  Fields are read back for
+    every request with keep_fields, else only for the tags in keep_tags."""
     if policy not in ("fifo", "sjf"):
         raise ValueError("policy must be 'fifo' or 'sjf'")
     now_fn = clock or time.perf_counter
@@ -106,7 +107,8 @@ def serve(requests, *, hbm_budget, max_slots, storage="f32", chunk=200, depth=2,
             for slot in finished:
                 r, ta = live.pop(slot)
                 failed = pool.status(slot) != 0
-                f = pool.fields(slot, raise_on_flags=False) if keep_fields else None
+                keep = keep_fields or (keep_tags is not None and r.tag in keep_tags)
+                f = pool.fields(slot, raise_on_flags=False) if keep else None
                 pool.release(slot)
                 done.append(Done(r.tag, r.arrival * time_scale, ta, now_fn() - t0, r.steps, r.fluid, f, failed))
             if not finished and not queue and nxt < len(reqs) and not live:

@@ -24,7 +24,6 @@ steps).  The c3 run takes about 20 minutes on 8 cores.
 """
 from __future__ import annotations
 
-import hashlib
 import math
 import os
 import sys
@@ -43,13 +42,7 @@ WIN = 24
 NSAMPLE = 2048
 
 
-def input_hash(c, mask) -> str:
-    h = hashlib.sha256()
-    h.update(np.ascontiguousarray(mask, np.uint8).tobytes())
-    h.update(np.ascontiguousarray(c.rhoA0, np.float64).tobytes())
-    h.update(np.ascontiguousarray(c.rhoB0, np.float64).tobytes())
-    h.update(repr(sorted(c.params().items())).encode())
-    return h.hexdigest()[:16]
+input_hash = W.input_hash
 
 
 def ora_mask(c):

@@ -12,6 +12,7 @@ the two rasters receive the same double.
 """
 from __future__ import annotations
 
+import hashlib
 import math
 from dataclasses import dataclass, field
 
@@ -240,3 +241,23 @@ def roofline_case(nx=5600, ny=4000, seed=7, G=3.0) -> Case:
     return Case("r-periodic-%dx%d" % (nx, ny), nx, ny, periodic=3, tau=1.0, G=G, bc=MC, Gw=0.0,
                 steps=1000, geometry=("none",), rhoA0=rA, rhoB0=rB,
                 mask_user=np.zeros((ny, nx), np.uint8))
+
+
+def roofline_plane_case(bc, nx=5600, ny=4000, beta_deg=30.0, R0=400.0) -> Case:
+    """The paper's largest grid (Section 4) with the Section 3.1 set-up: a drop
+    of radius 400 at rest on a 30-degree stair plane, G = 3, rho 1.0/0.055, in
+    each wetting rule (Martys-Chen G_w = -0.2, LLKC G_w = -0.5, improved scheme
+    chi^A = 1.2, chi^B = 0.8): the out-of-cache rows of the wall rules."""
+    return plane_drop(nx, ny, beta_deg, R0, bc, G=3.0, rho_out=0.055, chi=(1.2, 0.8),
+                      name="r-plane%g-%dx%d-%s" % (beta_deg, nx, ny, BC_NAMES[bc]))
+
+
+def input_hash(c: Case, mask) -> str:
+    """Fingerprint of a case's inputs (wall mask, initial densities,
+    parameters), so that stored expected values can be matched to them."""
+    h = hashlib.sha256()
+    h.update(np.ascontiguousarray(mask, np.uint8).tobytes())
+    h.update(np.ascontiguousarray(c.rhoA0, np.float64).tobytes())
+    h.update(np.ascontiguousarray(c.rhoB0, np.float64).tobytes())
+    h.update(repr(sorted(c.params().items())).encode())
+    return h.hexdigest()[:16]
