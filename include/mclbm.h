@@ -311,6 +311,20 @@ size_t lbm_pool_footprint(const lbm_params *p);
  * nor enough budget is free; *slot receives the slot id otherwise. */
 int lbm_pool_admit(lbm_pool *pool, const lbm_params *p, const uint8_t *mask, const double *rhoA0,
                    const double *rhoB0, int64_t nsteps, int32_t *slot);
+/* lbm_pool_admit for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same admission, bit-identical results, but the request's staging (its
+ * mask, the node-word scratch of the classification and its FP64 initial
+ * densities) lives in a 40 MiB array the library reserves on each GPU it runs
+ * on, held until the process ends, instead of buffers the pool grows with
+ * hipMalloc; it calls no hipMalloc, hipFree or other allocating routine.
+ * Grids whose staging exceeds the array (more than 2048 x 1024 nodes, or
+ * another shape of the same size) return LBM_EINVAL.  Every call on a GPU
+ * shares that GPU's array: calls that overlap on one GPU (from several
+ * threads, or pools of one device) race; consecutive calls do not, as each
+ * returns only once its set-up has read the staging. */
+int lbm_pool_admit_noalloc(lbm_pool *pool, const lbm_params *p, const uint8_t *mask,
+                           const double *rhoA0, const double *rhoB0, int64_t nsteps, int32_t *slot);
 /* Advances every active, unfinished slot by up to chunk steps in one batched
  * launch per step; a slot stops exactly at its own step count. */
 int lbm_pool_advance(lbm_pool *pool, int64_t chunk);

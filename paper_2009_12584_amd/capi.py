@@ -26,7 +26,7 @@ EXPORTS = [
     "lbm_contour_fit", "lbm_batch_contour_fit", "lbm_line_probe",
     "lbm_params_state_bytes", "lbm_batch_create", "lbm_batch_step", "lbm_batch_launch_counts", "lbm_batch_fields",
     "lbm_batch_diag", "lbm_batch_get_state", "lbm_batch_set_state", "lbm_batch_fluid_nodes", "lbm_batch_destroy",
-    "lbm_pool_create", "lbm_pool_footprint", "lbm_pool_admit", "lbm_pool_advance", "lbm_pool_poll",
+    "lbm_pool_create", "lbm_pool_footprint", "lbm_pool_admit", "lbm_pool_admit_noalloc", "lbm_pool_advance", "lbm_pool_poll",
     "lbm_pool_status", "lbm_pool_fields", "lbm_pool_diag", "lbm_pool_get_state", "lbm_pool_set_state", "lbm_pool_release",
     "lbm_pool_stats", "lbm_pool_progress", "lbm_pool_destroy",
 ]
@@ -119,6 +119,7 @@ def lib():
             "lbm_pool_create": (I32, [SZ, I32, I32, I32, P, ctypes.POINTER(P)]),
             "lbm_pool_footprint": (SZ, [PP]),
             "lbm_pool_admit": (I32, [P, PP, P, P, P, I64, ctypes.POINTER(I32)]),
+            "lbm_pool_admit_noalloc": (I32, [P, PP, P, P, P, I64, ctypes.POINTER(I32)]),
             "lbm_pool_advance": (I32, [P, I64]),
             "lbm_pool_poll": (I32, [P, P, I32, ctypes.POINTER(I32)]),
             "lbm_pool_fields": (I32, [P, I32, P, P, P, P]),

@@ -24,6 +24,7 @@
 #include <algorithm>
 #include <deque>
 #include <map>
+#include <mutex>
 
 #include "lbm_analysis.hpp"
 #include "lbm_batch_kernels.hpp"
@@ -587,6 +588,8 @@ struct Slot {
 struct lbm_pool {
     hipStream_t stream = nullptr, init_stream = nullptr;
     bool own_stream = false;
+    int device = 0;
+    unsigned char *scratch = nullptr;  // this device's allocation-free staging (noalloc_scratch)
     int storage = 0, ty = 8, max_slots = 0, diag_every = 0;
     Arena arena;
     size_t in_use = 0;
@@ -607,6 +610,55 @@ struct lbm_pool {
     int *h_flags = nullptr;   // pinned copy of d_flags, refreshed after each diagnostic launch
     hipEvent_t upload_done = nullptr;
 };
+
+// Staging of lbm_pool_admit_noalloc: the mask, the classification's node-word
+// scratch and the FP64 initial densities of one request, in device memory
+// reserved with the code object (each GPU the library runs on holds its own
+// copy until the process ends).  In host code the name stands for the array
+// but is no device address: host code uses the address hipGetSymbolAddress
+// gives for the device (noalloc_scratch), never the name.
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)40 << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+// Device address of the scratch array on device dev, looked up once per
+// device with that device current, then kept.
+static int noalloc_scratch(int dev, unsigned char **out) {
+    static std::mutex mu;
+    static std::map<int, unsigned char *> addr;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = addr.find(dev);
+    if (it != addr.end()) {
+        *out = it->second;
+        return LBM_OK;
+    }
+    int cur = -1;
+    MCLBM_HIP(hipGetDevice(&cur));
+    if (cur != dev) MCLBM_HIP(hipSetDevice(dev));
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (cur != dev) (void)hipSetDevice(cur);
+    if (e != hipSuccess || !ptr) {
+        set_err("hipGetSymbolAddress of the admission scratch failed: %s", hipGetErrorString(e));
+        return LBM_EDEVICE;
+    }
+    addr[dev] = (unsigned char *)ptr;
+    *out = (unsigned char *)ptr;
+    return LBM_OK;
+}
+
+// Carves the staging of an nx x ny request out of the scratch array; false
+// when it does not fit.
+static bool scratch_staging(unsigned char *base, int nx, int ny, uint8_t **mask, uint16_t **word0, double **rA,
+                            double **rB) {
+    const size_t n = (size_t)nx * ny, np = (size_t)ny * pitch_of(nx);
+    const size_t o_word = al(n), o_rA = o_word + al(np * sizeof(uint16_t)), o_rB = o_rA + al(n * sizeof(double));
+    if (o_rB + n * sizeof(double) > NOALLOC_SCRATCH_BYTES) return false;
+    *mask = (uint8_t *)base;
+    *word0 = (uint16_t *)(base + o_word);
+    *rA = (double *)(base + o_rA);
+    *rB = (double *)(base + o_rB);
+    return true;
+}
 
 static void pool_release_all(lbm_pool *P) {
     if (!P) return;
@@ -724,6 +776,10 @@ int lbm_pool_create(size_t hbm_budget, int32_t max_slots, int32_t storage, int32
         pool_release_all(P);
         return code;
     };
+    if (hipGetDevice(&P->device) != hipSuccess) return bail(LBM_EDEVICE);
+    // the allocation-free admission's staging on this device (kept null, and
+    // that entry point refused, should the lookup fail)
+    if (noalloc_scratch(P->device, &P->scratch) != LBM_OK) P->scratch = nullptr;
     if (!P->stream) {
         if (hipStreamCreate(&P->stream) != hipSuccess) return bail(LBM_EDEVICE);
         P->own_stream = true;
@@ -766,8 +822,13 @@ int lbm_pool_create(size_t hbm_budget, int32_t max_slots, int32_t storage, int32
     return LBM_OK;
 }
 
-int lbm_pool_admit(lbm_pool *P, const lbm_params *p, const uint8_t *mask, const double *rhoA0, const double *rhoB0,
-                   int64_t nsteps, int32_t *slot) {
+}  // extern "C"
+
+// Admission of one solve; with noalloc the staging comes from the scratch
+// array (grids whose staging exceeds it are refused) instead of the pool's
+// own buffers, which grow with hipMalloc for a larger request.
+static int pool_admit(lbm_pool *P, const lbm_params *p, const uint8_t *mask, const double *rhoA0,
+                      const double *rhoB0, int64_t nsteps, int32_t *slot, bool noalloc) {
     if (!P || !slot || nsteps < 0) return LBM_EINVAL;
     int rc = validate(p, mask, rhoA0, rhoB0);
     if (rc) return rc;
@@ -782,6 +843,20 @@ int lbm_pool_admit(lbm_pool *P, const lbm_params *p, const uint8_t *mask, const 
     if (default_ty(*p) != P->ty) {
         set_err("pool tiles have %d rows", P->ty);
         return LBM_EINVAL;
+    }
+    uint8_t *st_mask = nullptr;
+    uint16_t *st_word0 = nullptr;
+    double *st_rA = nullptr, *st_rB = nullptr;
+    if (noalloc) {
+        if (!P->scratch) {
+            set_err("the admission scratch of device %d is not available", P->device);
+            return LBM_EDEVICE;
+        }
+        if (!scratch_staging(P->scratch, p->nx, p->ny, &st_mask, &st_word0, &st_rA, &st_rB)) {
+            set_err("grid %d x %d: its staging exceeds the %zu-byte admission scratch (at most 2048 x 1024 nodes)",
+                    p->nx, p->ny, NOALLOC_SCRATCH_BYTES);
+            return LBM_EINVAL;
+        }
     }
     int k = -1;
     for (int q = 0; q < P->max_slots; ++q)
@@ -800,23 +875,33 @@ int lbm_pool_admit(lbm_pool *P, const lbm_params *p, const uint8_t *mask, const 
         return LBM_EAGAIN;
     }
     Slot &s = P->slots[k];
-    // set-up on the init stream overlaps the running batch
-    const size_t n = (size_t)p->nx * p->ny;
-    MCLBM_HIP(hipStreamSynchronize(P->init_stream));  // staging reuse
-    rc = P->st.ensure(n, (size_t)p->ny * pitch_of(p->nx));
-    if (rc) {
+    auto fail = [&](int code) {
         P->arena.release(off, m.bytes);
-        return rc;
+        return code;
+    };
+    // set-up on the init stream overlaps the running batch; the previous
+    // admission has drained its staging already (it synchronises below)
+    if (hipStreamSynchronize(P->init_stream) != hipSuccess) {
+        set_err("init stream synchronisation failed");
+        return fail(LBM_EDEVICE);
     }
-    rc = prepare(s.P, *p, P->ty, P->arena.base + off, mask, rhoA0, rhoB0, P->init_stream, P->st.mask, P->st.word0,
-                 P->st.rA, P->st.rB);
-    if (rc) {
-        P->arena.release(off, m.bytes);
-        return rc;
+    if (!noalloc) {
+        rc = P->st.ensure((size_t)p->nx * p->ny, (size_t)p->ny * pitch_of(p->nx));
+        if (rc) return fail(rc);
+        st_mask = P->st.mask;
+        st_word0 = P->st.word0;
+        st_rA = P->st.rA;
+        st_rB = P->st.rB;
     }
-    MCLBM_HIP(hipEventRecord(s.ready, P->init_stream));
-    // host inputs were copied with pageable memcpy: wait until they are read before returning
-    MCLBM_HIP(hipStreamSynchronize(P->init_stream));
+    rc = prepare(s.P, *p, P->ty, P->arena.base + off, mask, rhoA0, rhoB0, P->init_stream, st_mask, st_word0, st_rA,
+                 st_rB);
+    if (rc) return fail(rc);
+    // host inputs were copied with pageable memcpy, and the staging is reused:
+    // wait until the set-up has read them before returning
+    if (hipEventRecord(s.ready, P->init_stream) != hipSuccess || hipStreamSynchronize(P->init_stream) != hipSuccess) {
+        set_err("admission set-up failed on the device");
+        return fail(LBM_EDEVICE);
+    }
     s.used = true;
     s.joined = false;
     s.broken = false;
@@ -826,6 +911,18 @@ int lbm_pool_admit(lbm_pool *P, const lbm_params *p, const uint8_t *mask, const 
     P->in_use += al(m.bytes);
     *slot = k;
     return LBM_OK;
+}
+
+extern "C" {
+
+int lbm_pool_admit(lbm_pool *P, const lbm_params *p, const uint8_t *mask, const double *rhoA0, const double *rhoB0,
+                   int64_t nsteps, int32_t *slot) {
+    return pool_admit(P, p, mask, rhoA0, rhoB0, nsteps, slot, false);
+}
+
+int lbm_pool_admit_noalloc(lbm_pool *P, const lbm_params *p, const uint8_t *mask, const double *rhoA0,
+                           const double *rhoB0, int64_t nsteps, int32_t *slot) {
+    return pool_admit(P, p, mask, rhoA0, rhoB0, nsteps, slot, true);
 }
 
 int lbm_pool_advance(lbm_pool *P, int64_t chunk) {

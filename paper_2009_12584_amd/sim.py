@@ -278,16 +278,17 @@ class Pool:
         p = capi.make_params(nx, ny, storage=storage, **prm)
         return int(lib().lbm_pool_footprint(ctypes.byref(p)))
 
-    def admit(self, mask, rhoA0, rhoB0, nsteps, **prm):
-        """Returns the slot id, or None when no slot or budget is free (LBM_EAGAIN)."""
+    def admit(self, mask, rhoA0, rhoB0, nsteps, noalloc=False, **prm):
+        """Returns the slot id, or None when no slot or budget is free (LBM_EAGAIN).
+        noalloc=True uses lbm_pool_admit_noalloc (no device allocation)."""
         mask = np.ascontiguousarray(mask, np.uint8)
         ny, nx = mask.shape
         p = capi.make_params(nx, ny, storage=self.storage, **prm)
         rA = _host(rhoA0, np.float64, mask.shape)
         rB = _host(rhoB0, np.float64, mask.shape)
         slot = ctypes.c_int32()
-        code = lib().lbm_pool_admit(self._h, ctypes.byref(p), _p(mask), _p(rA), _p(rB), int(nsteps),
-                                    ctypes.byref(slot))
+        fn = lib().lbm_pool_admit_noalloc if noalloc else lib().lbm_pool_admit
+        code = fn(self._h, ctypes.byref(p), _p(mask), _p(rA), _p(rB), int(nsteps), ctypes.byref(slot))
         if code == capi.LBM_EAGAIN:
             return None
         check(code)
