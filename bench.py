@@ -66,8 +66,8 @@ DESIGN_BYTES_FLUID = {"f32": 144, "f16": 80}
 DESIGN_BYTES_FLUID_SC1 = {"f32": 72, "f16": 40}
 DESIGN_BYTES_NODE = 2
 KERNEL_SOURCES = ["lbm_tiling.hpp", "lbm_plan.hpp", "lbm_device.hpp", "lbm_pair.hpp", "lbm_sc1.hpp",
-                  "lbm_common.hpp", "lbm_batch_kernels.hpp", "lbm_single.hip", "lbm_batch.hip", "lbm_batch_f32.hip",
-                  "lbm_batch_f16.hip"]
+                  "lbm_common.hpp", "lbm_step_kernels.hpp", "lbm_batch_kernels.hpp", "lbm_single.hip",
+                  "lbm_step_f32.hip", "lbm_step_f16.hip", "lbm_batch.hip", "lbm_batch_f32.hip", "lbm_batch_f16.hip"]
 RHO_TOL, U_TOL = 1e-5, 1e-6            # FP32 bar against the FP64 oracle
 RHO_TOL_F16, U_TOL_F16 = 5e-3, 1e-3   # FP16 bar (derived from the storage rounding)
 

@@ -7,8 +7,9 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmclbm.so")
-SOURCES = ["lbm_single.hip", "lbm_batch.hip", "lbm_batch_f32.hip", "lbm_batch_f16.hip", "lbm_analysis.hip"]
-HEADERS = ["lbm_tiling.hpp", "lbm_plan.hpp", "lbm_device.hpp", "lbm_pair.hpp", "lbm_sc1.hpp", "lbm_common.hpp", "lbm_batch_kernels.hpp", "lbm_analysis.hpp"]
+SOURCES = ["lbm_single.hip", "lbm_step_f32.hip", "lbm_step_f16.hip", "lbm_batch.hip", "lbm_batch_f32.hip",
+           "lbm_batch_f16.hip", "lbm_analysis.hip"]
+HEADERS = ["lbm_tiling.hpp", "lbm_plan.hpp", "lbm_device.hpp", "lbm_pair.hpp", "lbm_sc1.hpp", "lbm_common.hpp", "lbm_step_kernels.hpp", "lbm_batch_kernels.hpp", "lbm_analysis.hpp"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

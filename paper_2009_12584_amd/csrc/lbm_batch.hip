@@ -152,19 +152,7 @@ int prepare(Prepared &P, const lbm_params &p, int ty, char *base, const uint8_t 
     for (size_t k = 0; k < n; ++k) fl += mask[k] ? 0 : 1;
     P.fluid = fl;
     P.tile_fluid.assign(P.ntiles, 0);
-    for (int t = 0; t < P.ntiles; ++t) {
-        int tx, tyy;
-        tile_coords(t, P.I.tiles_x, P.I.tiles_y, P.I.tg, tx, tyy);
-        const int x0 = tx * TX, y0 = tyy * ty, x1 = std::min(x0 + TX, p.nx), y1 = std::min(y0 + ty, p.ny);
-        bool any = false;
-        for (int y = y0; y < y1 && !any; ++y)
-            for (int x = x0; x < x1; ++x)
-                if (!mask[(size_t)y * p.nx + x]) {
-                    any = true;
-                    break;
-                }
-        P.tile_fluid[t] = any ? 1 : 0;
-    }
+    for (int t : fluid_tiles(mask, p.nx, p.ny, P.I.tiles_x, P.I.tiles_y, P.I.tg, ty)) P.tile_fluid[t] = 1;
     P.I.buf[0] = base + P.m.off_buf0;
     P.I.buf[1] = base + P.m.off_buf1;
     uint16_t *word = (uint16_t *)(base + P.m.off_word);

@@ -1,5 +1,6 @@
 // Step kernels of the batched and served forms: one launch per time step over
-// a flattened list of (instance, tile) pairs of many independent simulations.
+// a flattened list of (instance, tile) pairs of many independent simulations,
+// with streaming population stores (a batch's populations exceed the caches).
 // Each block takes one pair, reads its instance from a table and runs the
 // same tile step as the single-instance kernels (bit-identical results).  On
 // diagnostic launches every block also writes its tile's FP64 partials at its
@@ -49,7 +50,7 @@ __global__ __launch_bounds__(threads_for(TY)) void k_batch_step(const Inst *__re
                                                                 long long L, double *partials) {
     __shared__ Smem<TY> sm;
     MCLBM_BATCH_PROLOGUE
-    process_tile<S, TY, BC, MODE_STEP, DIAG>(I, tx, ty, parity, sm, acc, Fields{});
+    process_tile<S, TY, BC, MODE_STEP, DIAG, true>(I, tx, ty, parity, sm, acc, Fields{});
     if (DIAG) diag_partial<TY>(sm, acc, partials, t);
 }
 
@@ -60,7 +61,7 @@ __global__ __launch_bounds__(ls_threads(TY)) void k_batch_step_ls(const Inst *__
                                                                   long long L, double *partials) {
     __shared__ SmemLS<TY> sm;
     MCLBM_BATCH_PROLOGUE
-    process_tile_ls<S, TY, BC, MODE_STEP, DIAG>(I, tx, ty, parity, sm, acc, Fields{});
+    process_tile_ls<S, TY, BC, MODE_STEP, DIAG, true>(I, tx, ty, parity, sm, acc, Fields{});
     if (DIAG) diag_partial_ls<TY>(sm, acc, partials, t);
 }
 
@@ -74,11 +75,11 @@ __global__ __launch_bounds__(threads_for(TY)) void k_batch_step_all(const Inst *
     __shared__ Smem<TY> sm;
     MCLBM_BATCH_PROLOGUE
     if (I.bc == BC_MC)
-        process_tile<S, TY, BC_MC, MODE_STEP, DIAG>(I, tx, ty, parity, sm, acc, Fields{});
+        process_tile<S, TY, BC_MC, MODE_STEP, DIAG, true>(I, tx, ty, parity, sm, acc, Fields{});
     else if (I.bc == BC_LLKC)
-        process_tile<S, TY, BC_LLKC, MODE_STEP, DIAG>(I, tx, ty, parity, sm, acc, Fields{});
+        process_tile<S, TY, BC_LLKC, MODE_STEP, DIAG, true>(I, tx, ty, parity, sm, acc, Fields{});
     else
-        process_tile<S, TY, BC_IMPROVED, MODE_STEP, DIAG>(I, tx, ty, parity, sm, acc, Fields{});
+        process_tile<S, TY, BC_IMPROVED, MODE_STEP, DIAG, true>(I, tx, ty, parity, sm, acc, Fields{});
     if (DIAG) diag_partial<TY>(sm, acc, partials, t);
 }
 
@@ -90,11 +91,11 @@ __global__ __launch_bounds__(ls_threads(TY)) void k_batch_step_ls_all(const Inst
     __shared__ SmemLS<TY> sm;
     MCLBM_BATCH_PROLOGUE
     if (I.bc == BC_MC)
-        process_tile_ls<S, TY, BC_MC, MODE_STEP, DIAG>(I, tx, ty, parity, sm, acc, Fields{});
+        process_tile_ls<S, TY, BC_MC, MODE_STEP, DIAG, true>(I, tx, ty, parity, sm, acc, Fields{});
     else if (I.bc == BC_LLKC)
-        process_tile_ls<S, TY, BC_LLKC, MODE_STEP, DIAG>(I, tx, ty, parity, sm, acc, Fields{});
+        process_tile_ls<S, TY, BC_LLKC, MODE_STEP, DIAG, true>(I, tx, ty, parity, sm, acc, Fields{});
     else
-        process_tile_ls<S, TY, BC_IMPROVED, MODE_STEP, DIAG>(I, tx, ty, parity, sm, acc, Fields{});
+        process_tile_ls<S, TY, BC_IMPROVED, MODE_STEP, DIAG, true>(I, tx, ty, parity, sm, acc, Fields{});
     if (DIAG) diag_partial_ls<TY>(sm, acc, partials, t);
 }
 

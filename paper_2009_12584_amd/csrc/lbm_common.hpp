@@ -212,10 +212,10 @@ inline void fill_inst(Inst &I, const lbm_params &p, const double rref[2], int ty
     I.rrefA = (float)rref[0];
     I.rrefB = (float)rref[1];
     I.psi0 = (float)p.psi_rho0;
-    // tile walk in groups of 16 tile columns; streaming stores (the next step
-    // reads them from HBM anyway on grids larger than the caches)
+    // tile walk in groups of 16 tile columns
     I.tg = 16;
-    I.nt = 1;
+    I.steps_tiles = nullptr;
+    I.nsteps_tiles = 0;
     I.parity0 = 0;
     I.t_end = INT64_MAX;
 }
@@ -455,37 +455,6 @@ __host__ __device__ __forceinline__ void tile_coords(int t, int tiles_x, int til
     tx = g * tg + (r - ty * gw);
 }
 
-template <typename S, int TY, int BC, int MODE, bool DIAG>
-__global__ __launch_bounds__(threads_for(TY)) void k_step(Inst I, int parity, Fields fo, double *partials) {
-    __shared__ Smem<TY> sm;
-    int tx, ty;
-    tile_coords(xcd_tile(blockIdx.x, gridDim.x), I.tiles_x, I.tiles_y, I.tg, tx, ty);
-    DiagAcc acc;
-    process_tile<S, TY, BC, MODE, DIAG>(I, tx, ty, parity, sm, acc, fo);
-    if (DIAG) diag_partial<TY>(sm, acc, partials, blockIdx.x);
-}
-
-// The same step with two lanes per node (lbm_pair.hpp); bit-identical results.
-template <typename S, int TY, int BC, int MODE, bool DIAG>
-__global__ __launch_bounds__(ls_threads(TY)) void k_step_ls(Inst I, int parity, Fields fo, double *partials) {
-    __shared__ SmemLS<TY> sm;
-    int tx, ty;
-    tile_coords(xcd_tile(blockIdx.x, gridDim.x), I.tiles_x, I.tiles_y, I.tg, tx, ty);
-    DiagAcc acc;
-    process_tile_ls<S, TY, BC, MODE, DIAG>(I, tx, ty, parity, sm, acc, fo);
-    if (DIAG) diag_partial_ls<TY>(sm, acc, partials, blockIdx.x);
-}
-
-template <typename S, int TY, int BC, int MODE, bool DIAG>
-__global__ __launch_bounds__(threads_for(TY)) void k_step_sc1(Inst I, int parity, Fields fo, double *partials) {
-    __shared__ Smem<TY> sm;
-    int tx, ty;
-    tile_coords(xcd_tile(blockIdx.x, gridDim.x), I.tiles_x, I.tiles_y, I.tg, tx, ty);
-    DiagAcc acc;
-    process_tile_sc1<S, TY, BC, MODE, DIAG>(I, tx, ty, parity, sm, acc, fo);
-    if (DIAG) diag_partial<TY>(sm, acc, partials, blockIdx.x);
-}
-
 // Final FP64 reduction of the per-tile partials in a fixed order, the drift
 // check against step 0 and the sticky failure flags, by one block of 256
 // threads; returns the flags in thread 0.
@@ -546,77 +515,44 @@ struct Launch {
     bool diag;
     int model = LBM_MODEL_TWO;
     int lanes = 1;
+    bool nt = true;  // streaming (non-temporal) population stores
 };
 
-template <typename S, int TY, int BC>
-inline void launch3(const Launch &L, dim3 g, hipStream_t s, const Inst &I, int parity, const Fields &fo,
-                    double *partials) {
-    if (L.model == LBM_MODEL_SC1) {
-        if constexpr (BC == BC_MC || BC == BC_LLKC) {
-            if (L.mode == MODE_FIELDS)
-                hipLaunchKernelGGL((k_step_sc1<S, TY, BC, MODE_FIELDS, true>), g, dim3(threads_for(TY)), 0, s, I,
-                                   parity, fo, partials);
-            else if (L.diag)
-                hipLaunchKernelGGL((k_step_sc1<S, TY, BC, MODE_STEP, true>), g, dim3(threads_for(TY)), 0, s, I,
-                                   parity, fo, partials);
-            else
-                hipLaunchKernelGGL((k_step_sc1<S, TY, BC, MODE_STEP, false>), g, dim3(threads_for(TY)), 0, s, I,
-                                   parity, fo, partials);
-        }
-        return;
-    }
-    if (L.lanes == 2) {
-        const dim3 b(ls_threads(TY));
-        if (L.mode == MODE_FIELDS)
-            hipLaunchKernelGGL((k_step_ls<S, TY, BC, MODE_FIELDS, true>), g, b, 0, s, I, parity, fo, partials);
-        else if (L.diag)
-            hipLaunchKernelGGL((k_step_ls<S, TY, BC, MODE_STEP, true>), g, b, 0, s, I, parity, fo, partials);
-        else
-            hipLaunchKernelGGL((k_step_ls<S, TY, BC, MODE_STEP, false>), g, b, 0, s, I, parity, fo, partials);
-        return;
-    }
-    const dim3 b(threads_for(TY));
-    if (L.mode == MODE_FIELDS)
-        hipLaunchKernelGGL((k_step<S, TY, BC, MODE_FIELDS, true>), g, b, 0, s, I, parity, fo, partials);
-    else if (L.diag)
-        hipLaunchKernelGGL((k_step<S, TY, BC, MODE_STEP, true>), g, b, 0, s, I, parity, fo, partials);
-    else
-        hipLaunchKernelGGL((k_step<S, TY, BC, MODE_STEP, false>), g, b, 0, s, I, parity, fo, partials);
-}
-
-template <typename S, int TY>
-inline void launch2(const Launch &L, dim3 g, hipStream_t s, const Inst &I, int parity, const Fields &fo,
-                    double *partials) {
-    switch (L.bc) {
-    case BC_MC: launch3<S, TY, BC_MC>(L, g, s, I, parity, fo, partials); break;
-    case BC_LLKC: launch3<S, TY, BC_LLKC>(L, g, s, I, parity, fo, partials); break;
-    default: launch3<S, TY, BC_IMPROVED>(L, g, s, I, parity, fo, partials); break;
-    }
-}
-
-template <typename S>
-inline void launch1(const Launch &L, dim3 g, hipStream_t s, const Inst &I, int parity, const Fields &fo,
-                    double *partials) {
-    switch (L.ty) {
-    case 4: launch2<S, 4>(L, g, s, I, parity, fo, partials); break;
-    case 16: launch2<S, 16>(L, g, s, I, parity, fo, partials); break;
-    case 32: launch2<S, 32>(L, g, s, I, parity, fo, partials); break;
-    default: launch2<S, 8>(L, g, s, I, parity, fo, partials); break;
-    }
-}
+// Step kernels of one storage type over grid g (lbm_step_f32.hip, lbm_step_f16.hip).
+void launch_step_f32(const Launch &L, dim3 g, hipStream_t s, const Inst &I, int parity, const Fields &fo,
+                     double *partials);
+void launch_step_f16(const Launch &L, dim3 g, hipStream_t s, const Inst &I, int parity, const Fields &fo,
+                     double *partials);
 
 // One step (or fields pass) of one simulation; with diagnostics, followed by
-// the one-block reduction.
-inline void launch_step(const Launch &L, hipStream_t s, const Inst &I, int parity, const Fields &fo,
-                        double *partials, DiagDev *dd) {
-    const int nt = I.tiles_x * I.tiles_y;
-    dim3 g((unsigned)nt);
-    if (L.storage == LBM_STORE_F16)
-        launch1<__half>(L, g, s, I, parity, fo, partials);
-    else
-        launch1<float>(L, g, s, I, parity, fo, partials);
-    if (L.diag || L.mode == MODE_FIELDS)
-        hipLaunchKernelGGL(k_diag_reduce, dim3(1), dim3(256), 0, s, partials, nt, dd);
+// the one-block reduction (lbm_single.hip).
+void launch_step(const Launch &L, hipStream_t s, const Inst &I, int parity, const Fields &fo, double *partials,
+                 DiagDev *dd);
+
+// Population stores of a step stream past the caches (non-temporal) when the
+// two population buffers exceed this many bytes: the next step reads them
+// back from HBM anyway.  Smaller working sets stay in the 256 MB Infinity
+// Cache, where plain stores let the next step hit it.
+constexpr size_t NT_STORE_BYTES = (size_t)192 << 20;
+
+// Logical tiles (in the grouped walk order of tile_coords) that hold at least
+// one fluid node of the host mask.
+inline std::vector<int> fluid_tiles(const uint8_t *mask, int nx, int ny, int tiles_x, int tiles_y, int tg, int ty) {
+    std::vector<int> out;
+    for (int t = 0; t < tiles_x * tiles_y; ++t) {
+        int tx, tyy;
+        tile_coords(t, tiles_x, tiles_y, tg, tx, tyy);
+        const int x0 = tx * TX, y0 = tyy * ty, x1 = std::min(x0 + TX, nx), y1 = std::min(y0 + ty, ny);
+        bool any = false;
+        for (int y = y0; y < y1 && !any; ++y)
+            for (int x = x0; x < x1; ++x)
+                if (!mask[(size_t)y * nx + x]) {
+                    any = true;
+                    break;
+                }
+        if (any) out.push_back(t);
+    }
+    return out;
 }
 
 }  // namespace mclbm

@@ -236,11 +236,12 @@ struct Inst {
     float rrefA, rrefB;       // deviation references
     float psi0;               // single-component model: psi = psi0 (1 - exp(-rho / psi0))
     int tg;                   // tile columns per group of the tile walk
-    int nt;                   // streaming (non-temporal) stores
     int parity0;              // pool: parity of the buffer read at launch counter 0
     int64_t t_end;            // pool: launch counter at which this instance stops
     DiagDev *dd;              // batch and pool: this instance's FP64 reduction targets
     int tile0, ntl;           // batch and pool: its tiles' range in the flattened tile list
+    const int *steps_tiles;   // single simulation: logical tiles a step launches (those
+    int nsteps_tiles;         //   holding a fluid node), or null for every tile
 };
 
 struct Fields {  // fields mode outputs, unpadded nx * ny planes, any may be null
@@ -309,10 +310,18 @@ __device__ __forceinline__ Around around(const Inst &I, int gx, int gy, bool edg
     return a;
 }
 
-// Pull the 9 populations of both components at a fluid node (Eq. 1 streaming,
-// half-way bounce-back where the upstream node x - c_i = x + c_opp(i) is solid,
-// read from the node word).  base is the first plane, pb the plane size in
-// bytes; dA, dB receive storage units.
+// Byte offset, from the first plane, of the population of direction i that
+// a fluid node pulls: from the upstream node x - c_i = x + c_opp(i), or, when
+// that node is solid (bit opp(i) - 1 of the node word w), the half-way
+// bounce-back of the node's own opposite population.
+__device__ __forceinline__ uint32_t pull_off(int i, uint32_t pb, const Around &a, uint32_t own, uint32_t w) {
+    const bool bb = (w >> (OPP[i] - 1)) & 1u;
+    return bb ? (uint32_t)OPP[i] * pb + own : (uint32_t)i * pb + a.row[1 - CY[i]] + a.col[1 - CX[i]];
+}
+
+// Pull the 9 populations of both components at a fluid node (Eq. 1
+// streaming with half-way bounce-back).  base is the first plane, pb the plane
+// size in bytes; dA, dB receive storage units.
 template <typename S>
 __device__ __forceinline__ void pull9(const typename Store<S>::P *__restrict__ base, uint32_t pb, const Around &a,
                                       uint32_t w, float dA[9], float dB[9]) {
@@ -322,10 +331,7 @@ __device__ __forceinline__ void pull9(const typename Store<S>::P *__restrict__ b
     dB[0] = v.y;
 #pragma unroll
     for (int i = 1; i < 9; ++i) {
-        const uint32_t up = a.row[1 - CY[i]] + a.col[1 - CX[i]];
-        const bool bb = (w >> (OPP[i] - 1)) & 1u;
-        const uint32_t off = bb ? (uint32_t)OPP[i] * pb + own : (uint32_t)i * pb + up;
-        v = Store<S>::ld2(at(base, off));
+        v = Store<S>::ld2(at(base, pull_off(i, pb, a, own, w)));
         dA[i] = v.x;
         dB[i] = v.y;
     }
@@ -475,7 +481,7 @@ __device__ __forceinline__ void frame_pass(const Inst &I, Smem<TY> &sm, const ty
 // No multiply-add contraction: the one-lane and two-lane steps evaluate the
 // same expressions in the same order and agree bit for bit, whatever the
 // compiler would fuse in each.
-template <typename S, int TY, int BC, int MODE, bool DIAG>
+template <typename S, int TY, int BC, int MODE, bool DIAG, bool NT>
 __device__ __forceinline__ void process_tile(const Inst &I, int tile_x, int tile_y, int parity, Smem<TY> &sm,
                                              DiagAcc &acc, const Fields &fo) {
 #pragma clang fp contract(off)
@@ -734,7 +740,6 @@ __device__ __forceinline__ void process_tile(const Inst &I, int tile_x, int tile
         const float uFA3 = 3.f * (ux * FAx + uy * FAy), uFB3 = 3.f * (ux * FBx + uy * FBy);
         const float drA = sd[r][0] * (1.f / SC), drB = sd[r][1] * (1.f / SC);
         const CollK ck = coll_consts(I.omega, I.guo, SC);
-        P *o = at(fout, own[r]);
         float eA = 0.f, eB = 0.f;
 #pragma unroll
         for (int i = 1; i < 9; ++i) {
@@ -745,14 +750,17 @@ __device__ __forceinline__ void process_tile(const Inst &I, int tile_x, int tile
             const auto q = Store<S>::enc2(coll_dir(i, d[r][0][i], drA, ra, eq, t, cFA, uFA3, ck),
                                           coll_dir(i, d[r][1][i], drB, rb, eq, t, cFB, uFB3, ck));
             const float2 qd = Store<S>::dec2(q);
-            eA += remainder_term(d[r][0][i], qd.x);
-            eB += remainder_term(d[r][1][i], qd.y);
-            if (I.nt)
-                Store<S>::put2nt(at(o, (uint32_t)i * pb), q);
+            // the sums start from the first term (0 + x would cost an add)
+            eA = i == 1 ? remainder_term(d[r][0][i], qd.x) : eA + remainder_term(d[r][0][i], qd.x);
+            eB = i == 1 ? remainder_term(d[r][1][i], qd.y) : eB + remainder_term(d[r][1][i], qd.y);
+            // a uniform base plus a 32-bit offset; streaming (non-temporal)
+            // stores when the populations do not fit the caches
+            if constexpr (NT)
+                Store<S>::put2nt(at(fout, own[r] + (uint32_t)i * pb), q);
             else
-                Store<S>::put2(at(o, (uint32_t)i * pb), q);
+                Store<S>::put2(at(fout, own[r] + (uint32_t)i * pb), q);
         }
-        put_rest<S>(fout, pb, own[r], d[r][0][0] + eA, d[r][1][0] + eB, I.nt != 0);
+        put_rest<S>(fout, pb, own[r], d[r][0][0] + eA, d[r][1][0] + eB, NT);
     }
 }
 

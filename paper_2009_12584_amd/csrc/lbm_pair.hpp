@@ -39,65 +39,58 @@ template <int TY> struct SmemLS {
     int redi[ls_threads(TY) / 64];
 };
 
-// One component of a pair element: loads and stores at byte offset off of a
-// plane base already advanced to the lane's component.
+// One component of a pair element.  Every address is the buffer's base (the
+// same for all lanes) plus a 32-bit byte offset that includes the lane's
+// component, coff = c * sizeof(S) within a pair element.  put streams past
+// the caches (non-temporal), put_plain does not.
 template <typename S> struct Comp;
-// ld_rest / put_rest address the lane's component c of the node's rest
-// element (FP32 in both storages, see Store): base is already advanced to the
-// component within a pair element of the nine planes.
+// ld_rest / put_rest address component c of the node's rest element, FP32 in
+// both storages (see Store): in plane 0 for FP32 storage, in the float pair
+// plane after the nine FP16 planes for FP16 storage.
 template <> struct Comp<float> {
     static __device__ __forceinline__ float ld(const char *p) { return *(const float *)p; }
     static __device__ __forceinline__ float enc(float v) { return v; }
     static __device__ __forceinline__ float dec(float v) { return v; }
-    static __device__ __forceinline__ void put(char *p, float v, bool nt) {
-        if (nt)
-            __builtin_nontemporal_store(v, (float *)p);
-        else
-            *(float *)p = v;
-    }
-    static __device__ __forceinline__ float ld_rest(const char *base, uint32_t, uint32_t own, int) {
-        return *(const float *)(base + own);
-    }
-    static __device__ __forceinline__ void put_rest(char *base, uint32_t, uint32_t own, int, float v, bool nt) {
-        put(base + own, v, nt);
-    }
+    static __device__ __forceinline__ void put(char *p, float v) { __builtin_nontemporal_store(v, (float *)p); }
+    static __device__ __forceinline__ void put_plain(char *p, float v) { *(float *)p = v; }
+    static __device__ __forceinline__ uint32_t rest_off(uint32_t, uint32_t own, int c) { return own + 4u * (uint32_t)c; }
     using E = float;
 };
 template <> struct Comp<__half> {
     static __device__ __forceinline__ float ld(const char *p) { return __half2float(*(const __half *)p); }
     static __device__ __forceinline__ __half enc(float v) { return __float2half_rn(v); }
     static __device__ __forceinline__ float dec(__half v) { return __half2float(v); }
-    static __device__ __forceinline__ void put(char *p, __half v, bool nt) {
-        if (nt)
-            __builtin_nontemporal_store(__builtin_bit_cast(uint16_t, v), (uint16_t *)p);
-        else
-            *(__half *)p = v;
+    static __device__ __forceinline__ void put(char *p, __half v) {
+        __builtin_nontemporal_store(__builtin_bit_cast(uint16_t, v), (uint16_t *)p);
     }
-    // the float pair at 9 pb + 2 own from the buffer base, component c at
-    // 4 c; base is the buffer base plus 2 c
-    static __device__ __forceinline__ float ld_rest(const char *base, uint32_t pb, uint32_t own, int c) {
-        return *(const float *)(base + 9u * pb + 2u * own + 2u * (uint32_t)c);
-    }
-    static __device__ __forceinline__ void put_rest(char *base, uint32_t pb, uint32_t own, int c, float v, bool nt) {
-        Comp<float>::put(base + 9u * pb + 2u * own + 2u * (uint32_t)c, v, nt);
+    static __device__ __forceinline__ void put_plain(char *p, __half v) { *(__half *)p = v; }
+    static __device__ __forceinline__ uint32_t rest_off(uint32_t pb, uint32_t own, int c) {
+        return 9u * pb + 2u * own + 4u * (uint32_t)c;
     }
     using E = __half;
 };
 
+template <typename S> __device__ __forceinline__ float ld_rest_c(const char *base, uint32_t pb, uint32_t own, int c) {
+    return *(const float *)(base + Comp<S>::rest_off(pb, own, c));
+}
+template <typename S, bool NT>
+__device__ __forceinline__ void put_rest_c(char *base, uint32_t pb, uint32_t own, int c, float v) {
+    float *p = (float *)(base + Comp<S>::rest_off(pb, own, c));
+    if constexpr (NT)
+        __builtin_nontemporal_store(v, p);
+    else
+        *p = v;
+}
+
 // Pull of one component's 9 populations (Eq. 1 streaming, half-way
-// bounce-back from the node word); base points at the lane's component of
-// the first pair plane.
+// bounce-back from the node word); base is the buffer's first plane.
 template <typename S>
 __device__ __forceinline__ void pull9c(const char *base, uint32_t pb, const Around &a, uint32_t w, int c, float d[9]) {
     const uint32_t own = a.row[1] + a.col[1];
-    d[0] = Comp<S>::ld_rest(base, pb, own, c);
+    const uint32_t coff = (uint32_t)c * (uint32_t)sizeof(S);
+    d[0] = ld_rest_c<S>(base, pb, own, c);
 #pragma unroll
-    for (int i = 1; i < 9; ++i) {
-        const uint32_t up = a.row[1 - CY[i]] + a.col[1 - CX[i]];
-        const bool bb = (w >> (OPP[i] - 1)) & 1u;
-        const uint32_t off = bb ? (uint32_t)OPP[i] * pb + own : (uint32_t)i * pb + up;
-        d[i] = Comp<S>::ld(base + off);
-    }
+    for (int i = 1; i < 9; ++i) d[i] = Comp<S>::ld(base + (pull_off(i, pb, a, own, w) + coff));
 }
 
 // Per-tile FP64 partials of the lane-pair layout (mass A, mass B, momentum,
@@ -167,7 +160,7 @@ __device__ __forceinline__ void frame_ls(const Inst &I, SmemLS<TY> &sm, const ch
     }
 }
 
-template <typename S, int TY, int BC, int MODE, bool DIAG>
+template <typename S, int TY, int BC, int MODE, bool DIAG, bool NT>
 __device__ __forceinline__ void process_tile_ls(const Inst &I, int tile_x, int tile_y, int parity, SmemLS<TY> &sm,
                                                 DiagAcc &acc, const Fields &fo) {
 #pragma clang fp contract(off)
@@ -182,8 +175,9 @@ __device__ __forceinline__ void process_tile_ls(const Inst &I, int tile_x, int t
     const int c = tid & 1;             // this lane's component
     const int q = tid >> 1;            // node slot of the lane pair
     const int tx0 = tile_x * TX, ty0 = tile_y * TY;
-    const char *fin = (const char *)I.buf[parity] + c * sizeof(S);
-    char *fout = (char *)I.buf[parity ^ 1] + c * sizeof(S);
+    const char *fin = (const char *)I.buf[parity];
+    char *fout = (char *)I.buf[parity ^ 1];
+    const uint32_t coff = (uint32_t)c * (uint32_t)sizeof(S);  // the lane's component within a pair element
     const uint32_t pb = (uint32_t)(I.plane * (int64_t)sizeof(P));
     const float rref = c == 0 ? I.rrefA : I.rrefB;
     const bool edge = tile_edge(I.small != 0, I.periodic, tx0, ty0, I.nx, I.ny, TY);
@@ -395,7 +389,6 @@ __device__ __forceinline__ void process_tile_ls(const Inst &I, int tile_x, int t
         const float uF3 = 3.f * (ux * Fx + uy * Fy);
         const float dr = sd[r] * (1.f / SC);
         const CollK ck = coll_consts(I.omega, I.guo, SC);
-        char *o = fout + own[r];
         float e = 0.f;
 #pragma unroll
         for (int i = 1; i < 9; ++i) {
@@ -403,10 +396,13 @@ __device__ __forceinline__ void process_tile_ls(const Inst &I, int tile_x, int t
             const float eq = coll_eq(cu, m15uu), t = coll_t(cu);
             const float cF = cdot(i, Fx, Fy);
             const auto v = Comp<S>::enc(coll_dir(i, d[r][i], dr, rm, eq, t, cF, uF3, ck));
-            e += remainder_term(d[r][i], Comp<S>::dec(v));
-            Comp<S>::put(o + (uint32_t)i * pb, v, I.nt != 0);
+            e = i == 1 ? remainder_term(d[r][i], Comp<S>::dec(v)) : e + remainder_term(d[r][i], Comp<S>::dec(v));
+            if constexpr (NT)
+                Comp<S>::put(fout + (own[r] + (uint32_t)i * pb + coff), v);
+            else
+                Comp<S>::put_plain(fout + (own[r] + (uint32_t)i * pb + coff), v);
         }
-        Comp<S>::put_rest(fout, pb, own[r], c, d[r][0] + e, I.nt != 0);
+        put_rest_c<S, NT>(fout, pb, own[r], c, d[r][0] + e);
     }
 }
 

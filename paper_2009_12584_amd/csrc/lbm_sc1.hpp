@@ -67,17 +67,12 @@ __device__ __forceinline__ void pull9_1(const typename Store1<S>::P *__restrict_
     const uint32_t own = a.row[1] + a.col[1];
     d[0] = ld_rest1<S>(base, pb, own);
 #pragma unroll
-    for (int i = 1; i < 9; ++i) {
-        const uint32_t up = a.row[1 - CY[i]] + a.col[1 - CX[i]];
-        const bool bb = (w >> (OPP[i] - 1)) & 1u;
-        const uint32_t off = bb ? (uint32_t)OPP[i] * pb + own : (uint32_t)i * pb + up;
-        d[i] = Store1<S>::ld(at(base, off));
-    }
+    for (int i = 1; i < 9; ++i) d[i] = Store1<S>::ld(at(base, pull_off(i, pb, a, own, w)));
 }
 
 __device__ __forceinline__ float psi_of(float rho, float psi0) { return psi0 * (1.f - expf(-rho / psi0)); }
 
-template <typename S, int TY, int BC, int MODE, bool DIAG>
+template <typename S, int TY, int BC, int MODE, bool DIAG, bool NT>
 __device__ __forceinline__ void process_tile_sc1(const Inst &I, int tile_x, int tile_y, int parity, Smem<TY> &sm,
                                                  DiagAcc &acc, const Fields &fo) {
 #pragma clang fp contract(off)
@@ -221,20 +216,19 @@ __device__ __forceinline__ void process_tile_sc1(const Inst &I, int tile_x, int 
         const float uF3 = 3.f * (ux * Fx + uy * Fy);
         const float dr = sd[r] * (1.f / SC);
         const CollK ck = coll_consts(I.omega, I.guo, SC);
-        P *o = at(fout, own[r]);
         float e = 0.f;
 #pragma unroll
         for (int i = 1; i < 9; ++i) {
             const float cu = cdot(i, ux, uy);
             const float cF = cdot(i, Fx, Fy);
             const P q = Store1<S>::enc(coll_dir(i, d[r][i], dr, ra, coll_eq(cu, m15uu), coll_t(cu), cF, uF3, ck));
-            e += remainder_term(d[r][i], Store1<S>::dec(q));
-            if (I.nt)
-                Store1<S>::putnt(at(o, (uint32_t)i * pb), q);
+            e = i == 1 ? remainder_term(d[r][i], Store1<S>::dec(q)) : e + remainder_term(d[r][i], Store1<S>::dec(q));
+            if constexpr (NT)
+                Store1<S>::putnt(at(fout, own[r] + (uint32_t)i * pb), q);
             else
-                Store1<S>::put(at(o, (uint32_t)i * pb), q);
+                Store1<S>::put(at(fout, own[r] + (uint32_t)i * pb), q);
         }
-        put_rest1<S>(fout, pb, own[r], d[r][0] + e, I.nt != 0);
+        put_rest1<S>(fout, pb, own[r], d[r][0] + e, NT);
     }
 }
 

@@ -4,6 +4,24 @@
 
 using namespace mclbm;
 
+namespace mclbm {
+
+void launch_step(const Launch &L, hipStream_t s, const Inst &I, int parity, const Fields &fo, double *partials,
+                 DiagDev *dd) {
+    const int ntl = (L.mode == MODE_STEP && I.steps_tiles) ? I.nsteps_tiles : I.tiles_x * I.tiles_y;
+    if (ntl > 0) {
+        const dim3 g((unsigned)ntl);
+        if (L.storage == LBM_STORE_F16)
+            launch_step_f16(L, g, s, I, parity, fo, partials);
+        else
+            launch_step_f32(L, g, s, I, parity, fo, partials);
+    }
+    if (L.diag || L.mode == MODE_FIELDS)
+        hipLaunchKernelGGL(k_diag_reduce, dim3(1), dim3(256), 0, s, partials, ntl, dd);
+}
+
+}  // namespace mclbm
+
 struct lbm_handle {
     lbm_params p;
     hipStream_t stream = nullptr;
@@ -12,6 +30,7 @@ struct lbm_handle {
     int ty = 8;
     int ntiles = 0;
     uint8_t *tflag = nullptr, *nbr = nullptr, *cls = nullptr;
+    int *tlist = nullptr;     // logical tiles holding a fluid node: the ones a step launches
     uint16_t *word = nullptr;
     uint32_t *m25 = nullptr;
     double *partials = nullptr;
@@ -44,14 +63,16 @@ void release(lbm_handle *h) {
     }
     for (void *q : {(void *)h->I.buf[0], (void *)h->I.buf[1], (void *)h->word, (void *)h->m25, (void *)h->tflag,
                     (void *)h->nbr, (void *)h->cls, (void *)h->partials, (void *)h->dd, (void *)h->fields,
-                    (void *)h->cwork, (void *)h->rho1})
+                    (void *)h->cwork, (void *)h->rho1, (void *)h->tlist})
         if (q) (void)hipFree(q);
     if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
     delete h;
 }
 
 Launch launch_of(const lbm_handle *h, int mode, bool diag) {
-    return Launch{h->p.storage, h->ty, kernel_bc(h->p), mode, diag, h->p.model, lanes_of(h->p)};
+    // streaming stores only when the two population buffers exceed the caches
+    return Launch{h->p.storage, h->ty, kernel_bc(h->p), mode, diag, h->p.model, lanes_of(h->p),
+                  2 * pop_buffer_bytes(h->p) > NT_STORE_BYTES};
 }
 
 int run_fields(lbm_handle *h, const Fields &fo) {
@@ -154,6 +175,14 @@ int lbm_create(const lbm_params *p, const uint8_t *mask, const double *rhoA0, co
         MCLBM_HIP(hipMalloc(&h->nbr, n));
         MCLBM_HIP(hipMalloc(&h->cls, n));
         MCLBM_HIP(hipMalloc(&h->tflag, h->ntiles));
+        // a step launches only the tiles that hold fluid, so that the blocks
+        // of every XCD's band carry an equal share of the work
+        const std::vector<int> fl = fluid_tiles(mask, p->nx, p->ny, h->I.tiles_x, h->I.tiles_y, h->I.tg, h->ty);
+        MCLBM_HIP(hipMalloc(&h->tlist, sizeof(int) * std::max<size_t>(fl.size(), 1)));
+        if (!fl.empty())
+            MCLBM_HIP(hipMemcpyAsync(h->tlist, fl.data(), sizeof(int) * fl.size(), hipMemcpyHostToDevice, h->stream));
+        h->I.steps_tiles = h->tlist;
+        h->I.nsteps_tiles = (int)fl.size();
         MCLBM_HIP(hipMalloc(&h->partials, sizeof(double) * 6 * (size_t)h->ntiles));
         MCLBM_HIP(hipMalloc(&h->dd, sizeof(DiagDev)));
         MCLBM_HIP(hipMalloc(&dmask, n));
