@@ -309,22 +309,20 @@ __device__ __forceinline__ void process_tile_ls(const Inst &I, int tile_x, int t
         // Eq. 5 over fluid neighbours with the other component's density;
         // Eq. 6 over solid neighbours.  Solid and out-of-domain positions
         // hold density 0 in LDS and fluid positions hold rho~ 0: no branch.
-        float sx = 0.f, sy = 0.f, nxs = 0.f, nys = 0.f, tx = 0.f, ty = 0.f;
+        float vo[9], vn[9], vt[9];  // the other component's psi; phi; its rho~
 #pragma unroll
         for (int i = 1; i < 9; ++i) {
             const int qx = lx + CX[i], qy = ly + CY[i];
-            const float wi = WF[i];
-            const float a = wi * sm.rho[c ^ 1][rho_idx<TY>(qx, qy)];
-            cacc(i, a, sx, sy);
-            if (BC != BC_IMPROVED) {
-                const bool sol = (w[r] >> (i - 1)) & 1u;
-                cacc(i, sol ? wi : 0.f, nxs, nys);
-            } else if (need_rt) {
-                // tiles without interface solids in reach leave rho~ unset
-                const float t = wi * sm.rt[c ^ 1][rt_idx<TY>(qx, qy)];
-                cacc(i, t, tx, ty);
-            }
+            vo[i] = sm.rho[c ^ 1][rho_idx<TY>(qx, qy)];
+            vn[i] = ((w[r] >> (i - 1)) & 1u) ? 1.f : 0.f;
+            if (BC == BC_IMPROVED && need_rt) vt[i] = sm.rt[c ^ 1][rt_idx<TY>(qx, qy)];
         }
+        float sx, sy, nxs = 0.f, nys = 0.f, tx = 0.f, ty = 0.f;
+        grad9(vo, sx, sy);
+        if (BC != BC_IMPROVED)
+            grad9(vn, nxs, nys);
+        else if (need_rt)  // tiles without interface solids in reach leave rho~ unset
+            grad9(vt, tx, ty);
         float Fx = -I.G * rm * sx, Fy = -I.G * rm * sy;
         if (BC == BC_MC) {
             Fx -= Gs * rm * nxs;

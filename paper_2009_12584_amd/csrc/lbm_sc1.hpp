@@ -116,7 +116,7 @@ __device__ __forceinline__ void process_tile_sc1(const Inst &I, int tile_x, int 
         }
     }
 
-    // ---- one-node frame: psi of the neighbours (0 at solids, never read there):
+    // ---- one-node frame: psi of the neighbours (0 at solids):
     // the rows above and below (TX + 2 each), then the columns left and right
 #pragma unroll
     for (int s = 0; s < NFS; ++s) {
@@ -163,18 +163,17 @@ __device__ __forceinline__ void process_tile_sc1(const Inst &I, int tile_x, int 
         }
         const float ra = rho[r];
         const float px = sm.rho[0][rho_idx<TY>(lx, ly)];
-        float sx = 0.f, sy = 0.f;  // sum w psi c over fluid neighbours
-        float nxs = 0.f, nys = 0.f;  // sum w phi c
+        // psi is 0 at solid positions in LDS, so the Shan-Chen sum over fluid
+        // neighbours runs over all 8; the wall normal reads the node word
+        float vp[9], vn[9];
 #pragma unroll
         for (int i = 1; i < 9; ++i) {
-            const float wi = WF[i];
-            if (!((w[r] >> (i - 1)) & 1u)) {
-                const float a = wi * sm.rho[0][rho_idx<TY>(lx + CX[i], ly + CY[i])];
-                cacc(i, a, sx, sy);
-            } else {
-                cacc(i, wi, nxs, nys);
-            }
+            vp[i] = sm.rho[0][rho_idx<TY>(lx + CX[i], ly + CY[i])];
+            vn[i] = ((w[r] >> (i - 1)) & 1u) ? 1.f : 0.f;
         }
+        float sx, sy, nxs, nys;  // sum w psi c over fluid neighbours; sum w phi c
+        grad9(vp, sx, sy);
+        grad9(vn, nxs, nys);
         const float Sw = BC == BC_MC ? 1.f : px;  // the solid's pseudopotential
         const float Fx = -I.G * px * sx - I.GsA * px * Sw * nxs;
         const float Fy = -I.G * px * sy - I.GsA * px * Sw * nys;
