@@ -108,11 +108,24 @@ def roofline(kernel, profile, fluid, nodes, storage, ms_per_launch, sc1=False):
             "design_frac": round(des / (ms_per_launch * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
 
-def kernel_name(storage, ty, lanes, bc, sc1=False):
+# the library's store policy: streaming (non-temporal) population stores only
+# when both population buffers together exceed 192 MiB; smaller grids keep
+# their populations in the 256 MB Infinity Cache between steps
+NT_STORE_BYTES = 192 << 20
+
+
+def streaming_stores(nx, ny, storage, comps=2):
+    pitch = (nx + 63) // 64 * 64
+    per_node = 9 * 4 if storage == "f32" else 9 * 2 + 4
+    return 2 * comps * ny * pitch * per_node > NT_STORE_BYTES
+
+
+def kernel_name(storage, ty, lanes, bc, nx, ny, sc1=False):
     s = "float" if storage == "f32" else "__half"
+    nt = "true" if streaming_stores(nx, ny, storage, 1 if sc1 else 2) else "false"
     if sc1:
-        return "k_step_sc1<%s, %d, %d, 0, false>" % (s, ty, bc)
-    return "%s<%s, %d, %d, 0, false>" % ("k_step_ls" if lanes == 2 else "k_step", s, ty, bc)
+        return "k_step_sc1<%s, %d, %d, 0, false, %s>" % (s, ty, bc, nt)
+    return "%s<%s, %d, %d, 0, false, %s>" % ("k_step_ls" if lanes == 2 else "k_step", s, ty, bc, nt)
 
 
 class Timer:
@@ -191,7 +204,7 @@ def headline(M, torch, W, args, probe):
     mask = M.mask_disk(c.nx, c.ny, g[1], g[2], g[3])
     fluid, nodes = int((mask == 0).sum()), c.nx * c.ny
     if args.fixed_shapes:
-        ty, lanes = 8, 2
+        ty, lanes = 8, 1  # the autotuner's pick on this workload
     else:
         cfg = launch_config_for(mask, c.rhoA0, c.rhoB0, **c.params())
         ty, lanes = cfg["tile_y"], cfg["lanes"]
@@ -211,7 +224,7 @@ def headline(M, torch, W, args, probe):
     ms = t.ms / K
     # the rest of the configuration's run, untimed, and the oracle comparison at its final step
     err = None
-    if sim.t <= c.steps:
+    if sim.t <= c.steps and not args.no_oracle:
         sim.step(c.steps - sim.t)
         gold = np.load(os.path.join(ROOT, "tests", "golden", "longrun_c3.npz"), allow_pickle=False)
         if str(gold["input_sha"]) == W.input_hash(c, mask):
@@ -222,7 +235,7 @@ def headline(M, torch, W, args, probe):
             err = err_entry(er, eu, "f32", at_step=c.steps, nodes="%d sampled fluid nodes" % idx.size)
     d = sim.diag()
     sim.close()
-    kname = kernel_name("f32", ty, lanes, 2)
+    kname = kernel_name("f32", ty, lanes, 2, c.nx, c.ny)
     return {
         "metric": METRIC,
         "value": round(fluid * K / (t.ms * 1e-3) / 1e6, 1),
@@ -302,8 +315,9 @@ def large_row(M, torch, ora, args, c, mask, storage, profile, windows, sc1=False
     sim.close()
     ms = t.ms / steps
     row = {"ms_per_step": round(ms, 4), "fluid_mlups": round(fluid * steps / (t.ms * 1e-3) / 1e6, 1),
-           "fluid_nodes": fluid, "roofline": roofline(kernel_name(storage, 8, 1, c.bc if c.bc < 3 else 0, sc1),
-                                                      profile, fluid, nodes, storage, ms, sc1)}
+           "fluid_nodes": fluid,
+           "roofline": roofline(kernel_name(storage, 8, 1, c.bc if c.bc < 3 else 0, c.nx, c.ny, sc1), profile, fluid,
+                                nodes, storage, ms, sc1)}
     if ora is not None:
         row["error_vs_oracle"] = err_entry(er, eu, storage, at_step=10, nodes="3 windows of 240 x 240")
     return row
@@ -312,12 +326,18 @@ def large_row(M, torch, ora, args, c, mask, storage, profile, windows, sc1=False
 def rows_5600x4000(M, torch, W, args, probe):
     import oracle
 
-    oracle.build()
+    if args.no_oracle:
+        oracle = None
+    else:
+        oracle.build()
+    pick = set(args.large_only.split(",")) if args.large_only else None
     out = {"workload": "5600x4000, the paper's largest grid (Section 4): 3.2 GB of FP32 populations per step, "
                        "out of every cache; 64 x 8 tiles, one lane per node"}
     mix = W.roofline_case()
     seams = [(5600 - 120, 4000 - 120), (2800, 1900), (5500, 700)]
     for storage in ("f32", "f16"):
+        if pick and "mixture_mc_" + storage not in pick:
+            continue
         r = large_row(M, torch, oracle, args, mix, mix.mask_user, storage, "k_step_mc_periodic_5600x4000.md", seams)
         r["roofline"]["frac_of_copy_probe"] = round(r["roofline"]["achieved"] / probe["gbs"], 4)
         out["mixture_mc_" + storage] = r
@@ -327,13 +347,15 @@ def rows_5600x4000(M, torch, W, args, probe):
         c = W.roofline_plane_case(bc)
         m = M.mask_plane(c.nx, c.ny, c.geometry[1], c.geometry[2])
         for storage in (("f32", "f16") if bc == W.IMPROVED else ("f32",)):
+            if pick and "plane30_%s_%s" % (name, storage) not in pick:
+                continue
             r = large_row(M, torch, oracle, args, c, m, storage, "k_step_plane30_5600x4000_%s.md" % name, wins)
             r["roofline"]["frac_of_copy_probe"] = round(r["roofline"]["achieved"] / probe["gbs"], 4)
             out["plane30_%s_%s" % (name, storage)] = r
-    sc = W.sc1_roofline_case()
-    r = large_row(M, torch, oracle, args, sc, sc.mask_user, "f32", "k_step_sc1_periodic_5600x4000.md", seams,
-                  sc1=True)
-    out["single_component_f32"] = r
+    if not pick or "single_component_f32" in pick:
+        sc = W.sc1_roofline_case()
+        out["single_component_f32"] = large_row(M, torch, oracle, args, sc, sc.mask_user, "f32",
+                                                "k_step_sc1_periodic_5600x4000.md", seams, sc1=True)
     out["plane_workload"] = ("drop R=400 at rest on a 30-degree stair plane (Section 3.1 set-up), G=3, rho 1.0/0.055; "
                              "Martys-Chen G_w=-0.2, LLKC G_w=-0.5, improved chi 1.2/0.8")
     out["mixture_workload"] = "fully periodic seeded 50/50 mixture at G=3 (spinodal start), Martys-Chen path"
@@ -356,7 +378,7 @@ def config2_row(M, torch, W, args):
     sim = M.Simulation(mask, c.rhoA0, c.rhoB0, stream=stream, graph_steps=glen, diag_every=glen if glen else 100,
                        tile_y=ty, lanes=lanes, **c.params())
     sim.step(200)
-    K = 20000
+    K = args.config2_steps
     with Timer(torch, stream) as t:
         sim.step(K)
     sim.close()
@@ -365,7 +387,7 @@ def config2_row(M, torch, W, args):
                         "18.9 MB of populations: cache-resident and launch-latency-bound",
             "ms_per_step": round(ms, 5), "fluid_mlups": round(fluid * K / (t.ms * 1e-3) / 1e6, 1), "steps": K,
             "tile_y": ty, "lanes": lanes,
-            "roofline": roofline(kernel_name("f32", ty, lanes, 2), "k_step_improved_plane30_512x256.md", fluid,
+            "roofline": roofline(kernel_name("f32", ty, lanes, 2, c.nx, c.ny), "k_step_improved_plane30_512x256.md", fluid,
                                  nodes, "f32", ms)}
 
 
@@ -376,7 +398,8 @@ def batched_rows(M, torch, W, args):
     import oracle
     from paper_2009_12584_amd.autotune import launch_config_for_batch
 
-    oracle.build()
+    if not args.no_oracle:
+        oracle.build()
     steps = args.batch_steps
     warm = 100
     glen = graph_len(args, 100)
@@ -401,7 +424,7 @@ def batched_rows(M, torch, W, args):
     for s in sims:
         s.close()
     out["plain_loop_fluid_mlups"] = round(fluid * steps / (plain_ms * 1e-3) / 1e6, 1)
-    picks = (0, 3, 5)
+    picks = () if args.no_oracle else (0, 3, 5)
     refs = {}
     for k in picks:
         o = oracle.Oracle(masks[k], cases[k].rhoA0, cases[k].rhoB0, **cases[k].params())
@@ -436,7 +459,7 @@ def batched_rows(M, torch, W, args):
                         "roofline": roofline(kern, "k_batch_step_all_c4_64_instances.md", fluid, 0, storage, ms),
                         "error_vs_oracle": err_entry(*worst, storage, at_step=warm + steps,
                                                      nodes="all fluid nodes of instances 0, 3, 5 (improved, "
-                                                           "Martys-Chen, LLKC)")}
+                                                           "Martys-Chen, LLKC)") if picks else None}
     return out
 
 
@@ -583,6 +606,9 @@ def main():
                          "configuration's 50,000 steps")
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--large-steps", type=int, default=200, help="timed steps of each 5600x4000 row")
+    ap.add_argument("--large-only", default="",
+                    help="comma list of 5600x4000 rows to run (e.g. plane30_mc_f32); default all")
+    ap.add_argument("--config2-steps", type=int, default=20000)
     ap.add_argument("--batch-steps", type=int, default=1000)
     ap.add_argument("--served-requests", type=int, default=400)
     ap.add_argument("--rows", default="headline,large,config2,batched,served,cpu",
@@ -592,6 +618,9 @@ def main():
                          "collection needs); default min(100, steps)")
     ap.add_argument("--fixed-shapes", action="store_true",
                     help="fixed launch shapes instead of the autotuner (counter runs name one kernel)")
+    ap.add_argument("--no-oracle", action="store_true",
+                    help="no oracle comparisons (error_vs_oracle null) and no untimed run to 50,000 steps: for "
+                         "profiler runs, which time kernels only")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
