@@ -157,10 +157,35 @@ def errors(mask, got, ref):
     return er, eu
 
 
-def err_entry(er, eu, storage, **extra):
-    rt, ut = (RHO_TOL, U_TOL) if storage == "f32" else (RHO_TOL_F16, U_TOL_F16)
-    return dict(max_rel_rho=float("%.3e" % er), max_abs_u=float("%.3e" % eu), bar=[rt, ut],
-                within_bar=bool(er <= rt and eu <= ut), **extra)
+def err_entry(er, eu, storage, bar=None, **extra):
+    rt, ut = bar if bar else ((RHO_TOL, U_TOL) if storage == "f32" else (RHO_TOL_F16, U_TOL_F16))
+    return dict(max_rel_rho=float("%.3e" % er), max_abs_u=float("%.3e" % eu), bar=[float("%.3e" % rt),
+                float("%.3e" % ut)], within_bar=bool(er <= rt and eu <= ut), **extra)
+
+
+def f16_model_bars(W, cases, masks, picks, at_step):
+    """Per picked instance, twice the error FP16 storage alone gives at
+    at_step (the FP64 oracle with the storage rounding applied,
+    tests/golden/f16_model_c4.npz, written by the oracle alone); None when
+    the file does not cover the instances or the step."""
+    import numpy as np
+
+    try:
+        gold = np.load(os.path.join(ROOT, "tests", "golden", "f16_model_c4.npz"), allow_pickle=False)
+    except OSError:
+        return None
+    steps = [int(x) for x in gold["steps"]]
+    inst = [int(x) for x in gold["instances"]]
+    if at_step not in steps or any(k not in inst for k in picks):
+        return None
+    col = steps.index(at_step)
+    out = {}
+    for k in picks:
+        if str(gold["input_sha_%d" % k]) != W.input_hash(cases[k], masks[k]):
+            return None
+        a = inst.index(k)
+        out[k] = (2 * float(gold["err_rho"][a, col]), 2 * float(gold["err_u"][a, col]))
+    return out
 
 
 def copy_probe(torch, nbytes=1 << 31, reps=5):
@@ -444,9 +469,15 @@ def batched_rows(M, torch, W, args):
         c1 = b.launch_counts()
         ms = t.ms / steps
         worst = (0.0, 0.0)
+        # the FP16 bar: twice the FP16 storage format's own error on each
+        # instance at this step
+        bars = f16_model_bars(W, cases, masks, picks, warm + steps) if storage == "f16" else None
+        ok = True
         for k in picks:
             er, eu = errors(masks[k], b.fields(k), refs[k])
             worst = (max(worst[0], er), max(worst[1], eu))
+            if bars:
+                ok = ok and er <= bars[k][0] and eu <= bars[k][1]
         flags = sum(1 for k in range(64) if b.diag(k, raise_on_flags=False)["flags"])
         b.close()
         mlups = fluid * steps / (t.ms * 1e-3) / 1e6
@@ -460,6 +491,14 @@ def batched_rows(M, torch, W, args):
                         "error_vs_oracle": err_entry(*worst, storage, at_step=warm + steps,
                                                      nodes="all fluid nodes of instances 0, 3, 5 (improved, "
                                                            "Martys-Chen, LLKC)") if picks else None}
+        if bars and picks:
+            e = out[storage]["error_vs_oracle"]
+            e["within_bar"] = bool(ok)
+            e["bar"] = None
+            e["bar_per_instance"] = {str(k): [float("%.3e" % v) for v in bars[k]] for k in picks}
+            e["bar_rule"] = ("twice the error FP16 storage alone gives on the instance at this step: the FP64 "
+                             "oracle with the same storage rounding after every step "
+                             "(tests/golden/f16_model_c4.npz)")
     return out
 
 
