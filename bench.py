@@ -409,14 +409,28 @@ def config2_row(M, torch, W, args):
     K = args.config2_steps
     with Timer(torch, stream) as t:
         sim.step(K)
-    sim.close()
     ms = t.ms / K
+    # the oracle's fields at the configuration's final step (written by the
+    # oracle alone), when the run ends there
+    err = None
+    if sim.t == c.steps and not args.no_oracle:
+        import numpy as np
+
+        gold = np.load(os.path.join(ROOT, "tests", "golden", "longrun_c2.npz"), allow_pickle=False)
+        if str(gold["input_sha"]) == W.input_hash(c, mask):
+            idx = gold["idx"]
+            got = [f.ravel()[idx] for f in sim.fields()]
+            ref = [gold["%s_%d" % (k, c.steps)].astype(np.float64) for k in ("rhoA", "rhoB", "ux", "uy")]
+            er, eu = errors(np.zeros(idx.size, np.uint8), got, ref)
+            err = err_entry(er, eu, "f32", at_step=c.steps, nodes="%d sampled fluid nodes" % idx.size)
+    sim.close()
     return {"workload": "512x256, 30-degree stair plane, drop R=40, improved scheme, FP32 (configuration 2); "
                         "18.9 MB of populations: cache-resident and launch-latency-bound",
             "ms_per_step": round(ms, 5), "fluid_mlups": round(fluid * K / (t.ms * 1e-3) / 1e6, 1), "steps": K,
             "tile_y": ty, "lanes": lanes,
             "roofline": roofline(kernel_name("f32", ty, lanes, 2, c.nx, c.ny), "k_step_improved_plane30_512x256.md", fluid,
-                                 nodes, "f32", ms)}
+                                 nodes, "f32", ms),
+            "error_vs_oracle": err}
 
 
 # ----------------------------------------------------------------- batched
@@ -652,7 +666,8 @@ def main():
     ap.add_argument("--large-steps", type=int, default=200, help="timed steps of each 5600x4000 row")
     ap.add_argument("--large-only", default="",
                     help="comma list of 5600x4000 rows to run (e.g. plane30_mc_f32); default all")
-    ap.add_argument("--config2-steps", type=int, default=20000)
+    ap.add_argument("--config2-steps", type=int, default=19800,
+                    help="timed steps of configuration 2 (after 200 untimed: the run ends at its 20,000 steps)")
     ap.add_argument("--batch-steps", type=int, default=1000)
     ap.add_argument("--served-requests", type=int, default=400)
     ap.add_argument("--rows", default="headline,large,config2,batched,served,cpu",

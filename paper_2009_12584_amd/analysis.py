@@ -331,10 +331,74 @@ def main_coalescence(argv):
     return 0
 
 
+def adhesion_angles(rules, betas, *, n=400, R0=18.0, tau=1.0, G=3.0, rho_out=0.055, marks=(5000, 10000, 20000, 40000),
+                    skip=3, log=None):
+    """Contact angles of drops under the adhesion-force rules (Martys-Chen,
+    LLKC) at the set-up of Section 3.1: box n x n, drop of radius R0 tangent to
+    a plane of inclination beta, densities 1.0 / rho_out, G_AB = G,
+    G_As = -G_Bs = G_w.  rules: iterable of (bc, G_w).  Returns one dict per
+    (bc, G_w, beta) with the angle (half-way wall line) and the circle radius
+    at each mark.  Drops at rest need beta = 0 or 45 degrees (Section 3.1)."""
+    import workloads as W
+
+    keys, cases, walls = [], [], []
+    for bc, gw in rules:
+        for beta in betas:
+            c = W.plane_drop(n, n, beta, R0, bc, G=G, tau=tau, rho_out=rho_out, Gw=gw)
+            mask = mask_plane(n, n, c.geometry[1], c.geometry[2])
+            keys.append((int(bc), float(gw), float(beta)))
+            cases.append((mask, c.rhoA0, c.rhoB0, c.params()))
+            walls.append(wall_line(mask, range(max(1, n // 2 - int(3.5 * R0)), min(n - 1, n // 2 + int(3.5 * R0)))))
+    roi = drop_roi(n, n, R0, half=4.0)
+    b = Batch(cases)
+    rows = [dict(bc=k[0], Gw=k[1], beta=k[2], theta=[], R=[], steps=[]) for k in keys]
+    done = 0
+    try:
+        for m in sorted(marks):
+            b.step(m - done)
+            done = m
+            for i, r in enumerate(rows):
+                c = b.contour_fit(i, 0.5, skip, roi)
+                r["theta"].append(contact_angle(c, walls[i]))
+                r["R"].append(c["R"])
+                r["steps"].append(m)
+            if log:
+                log("adhesion angles: step %d" % m)
+    finally:
+        b.close()
+    return rows
+
+
+def main_adhesion(argv):
+    import workloads as W
+
+    ap = argparse.ArgumentParser(description="Contact angles under the Martys-Chen and LLKC rules (Section 3.1).")
+    ap.add_argument("--mc", default="-0.1,-0.2,-0.3,-0.4", help="G_w values of the Martys-Chen rule")
+    ap.add_argument("--llkc", default="-0.3,-0.5,-0.7,-1.0", help="G_w values of the LLKC rule")
+    ap.add_argument("--beta", default="0,45")
+    ap.add_argument("--n", type=int, default=400)
+    ap.add_argument("--R0", type=float, default=18.0)
+    ap.add_argument("--steps", default="5000,10000,20000,40000")
+    a = ap.parse_args(argv)
+    rules = [(W.MC, float(g)) for g in a.mc.split(",") if g.strip()]
+    rules += [(W.LLKC, float(g)) for g in a.llkc.split(",") if g.strip()]
+    betas = [float(v) for v in a.beta.split(",")]
+    rows = adhesion_angles(rules, betas, n=a.n, R0=a.R0, marks=[int(v) for v in a.steps.split(",")],
+                           log=lambda m: print(m, flush=True))
+    print("| rule | G_w | beta | " + " | ".join("t=%d" % t for t in rows[0]["steps"]) + " |")
+    print("|---|---|---|" + "---|" * len(rows[0]["steps"]))
+    for r in rows:
+        print("| %s | %g | %g | " % (W.BC_NAMES[r["bc"]], r["Gw"], r["beta"]) +
+              " | ".join("%.1f" % t for t in r["theta"]) + " |")
+    return 0
+
+
 def main(argv=None):
     argv = sys.argv[1:] if argv is None else list(argv)
     if argv and argv[0] == "coalescence":
         return main_coalescence(argv[1:])
+    if argv and argv[0] == "adhesion":
+        return main_adhesion(argv[1:])
     if argv and argv[0] == "sliding":
         return main_sliding(argv[1:])
     if argv and argv[0] == "angles":
