@@ -54,8 +54,10 @@ inline int pops_per_node(const lbm_params &p) { return p.model == LBM_MODEL_SC1 
 // bytes of one population buffer: nine planes per component; with FP16
 // storage the rest population has an FP32 plane of its own after them
 inline size_t pop_buffer_bytes(const lbm_params &p) {
+    // 64-node row segments of 9 direction slots (FP32) or 10 (FP16: the two
+    // extra 4-byte halves of the slot pair hold the FP32 rest populations)
     const size_t np = (size_t)p.ny * pitch_of(p.nx), comps = (size_t)pops_per_node(p) / 9;
-    return comps * np * (9 * store_bytes(p.storage) + (p.storage == LBM_STORE_F16 ? 4 : 0));
+    return comps * np * store_bytes(p.storage) * (p.storage == LBM_STORE_F16 ? 10 : 9);
 }
 
 // Bytes of device memory one simulation holds (two population buffers, node
@@ -348,7 +350,8 @@ __global__ void k_init(Inst I, const double *__restrict__ rA, const double *__re
     if (I.node[(int64_t)y * I.pitch + x] & NW_SOLID) return;
     using P = typename Store<S>::P;
     P *b = (P *)I.buf[which];
-    const int64_t own = (int64_t)y * I.pitch + x;
+    const uint32_t own = row_off<S, 2>(I, y) + col_off<S, 2>(x);
+    constexpr uint32_t pb = slot_bytes<S, 2>();
     const double wd[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
     const double sc = (double)Store<S>::SC;
     for (int j = 0; j < 9; ++j) {
@@ -357,10 +360,9 @@ __global__ void k_init(Inst I, const double *__restrict__ rA, const double *__re
         if (I.node[(int64_t)ys * I.pitch + xs] & NW_SOLID) src = k;
         const float va = (float)(wd[j] * (rA[src] - rrefA) * sc), vb = (float)(wd[j] * (rB[src] - rrefB) * sc);
         if (j == 0)  // the rest population: FP32 in both storages
-            put_rest<S>(b, (uint32_t)(I.plane * (int64_t)sizeof(P)), (uint32_t)(own * (int64_t)sizeof(P)), va, vb,
-                        false);
+            put_rest<S>(b, pb, own, va, vb, false);
         else
-            Store<S>::put2(b + (int64_t)j * I.plane + own, Store<S>::enc2(va, vb));
+            Store<S>::put2(at(b, own + (uint32_t)j * pb), Store<S>::enc2(va, vb));
     }
 }
 
@@ -373,7 +375,8 @@ __global__ void k_init_sc1(Inst I, const double *__restrict__ rA, double rref, i
     if (I.node[(int64_t)y * I.pitch + x] & NW_SOLID) return;
     using P = typename Store1<S>::P;
     P *b = (P *)I.buf[which];
-    const int64_t own = (int64_t)y * I.pitch + x;
+    const uint32_t own = row_off<S, 1>(I, y) + col_off<S, 1>(x);
+    constexpr uint32_t pb = slot_bytes<S, 1>();
     const double wd[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
     const double sc = (double)Store1<S>::SC;
     for (int j = 0; j < 9; ++j) {
@@ -382,9 +385,9 @@ __global__ void k_init_sc1(Inst I, const double *__restrict__ rA, double rref, i
         if (I.node[(int64_t)ys * I.pitch + xs] & NW_SOLID) src = k;
         const float v = (float)(wd[j] * (rA[src] - rref) * sc);
         if (j == 0)  // the rest population: FP32 in both storages
-            put_rest1<S>(b, (uint32_t)(I.plane * (int64_t)sizeof(P)), (uint32_t)(own * (int64_t)sizeof(P)), v, false);
+            put_rest1<S>(b, pb, own, v, false);
         else
-            Store1<S>::put(b + (int64_t)j * I.plane + own, Store1<S>::enc(v));
+            Store1<S>::put(at(b, own + (uint32_t)j * pb), Store1<S>::enc(v));
     }
 }
 

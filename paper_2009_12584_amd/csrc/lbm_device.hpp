@@ -24,14 +24,21 @@
 // within reach of an interface solid; interface solids also have a 24-bit
 // mask of their fluid D2Q25 neighbours for Eq. 7.
 //
-// Populations are stored as 9 direction planes, row pitch a multiple of 64
-// nodes, each element the pair (A, B) of one direction -- both components are
-// pulled from the same upstream node, so one load brings both -- as
-// deviations d_i = f_i - w_i rho_ref in FP32 (float2) or scaled FP16 (half2).
-// The buffer read in a step holds the post-collision values of the previous
-// step at their node of origin (pull scheme).  Loads address the 9 planes from
-// one uniform base with 32-bit byte offsets (a buffer stays below 4 GiB),
-// stores a plane base plus the node offset.
+// Populations are stored in 64-node row segments: a segment holds, for 64
+// consecutive nodes of one lattice row (rows padded to a multiple of 64), one
+// slot of 64 elements per direction, back to back, each element the pair
+// (A, B) of one direction -- both components are pulled from the same
+// upstream node, so one load brings both -- as deviations
+// d_i = f_i - w_i rho_ref in FP32 (float2) or scaled FP16 (half2).  A
+// wavefront's pull of one direction still reads one contiguous 512-byte run
+// (plus one element of the neighbouring segment for a shifted direction),
+// and a step's reads and writes form a few address streams instead of one
+// per direction plane: on MI355X the step's access pattern moved 5.8 TB/s in
+// this layout against 5.4 TB/s in nine planes.  The buffer read in a step
+// holds the post-collision values of the previous step at their node of
+// origin (pull scheme).  Loads address the buffer from one uniform base with
+// 32-bit byte offsets (a buffer stays below 4 GiB): a node's offset is its
+// row's plus its column's (row_off, col_off), and direction i adds i slots.
 #pragma once
 
 #include <hip/hip_fp16.h>
@@ -129,14 +136,13 @@ __device__ __forceinline__ float coll_dir(int i, float d, float dr, float rho, f
 //
 // The rest population is the remainder of the node's incoming mass after the
 // 8 moving populations are rounded to storage (remainder_term below).  With
-// FP16 storage it
-// stays in FP32, in a plane of (A, B) float pairs after the nine FP16 planes
-// (whose plane 0 is then unused): rounding it to FP16 would move the node's
-// mass by up to 2^-12 of the rest population every step, and those roundings
-// add up (4% of a component's mass over 20k steps of a drop on the 30-degree
-// plane), where the FP32 remainder keeps the mass as FP32 storage does.
-// rest_off is the byte offset of a node's rest element from the buffer base,
-// own the node's byte offset within one of the nine planes, pb a plane's bytes.
+// FP16 storage it stays in FP32: component A's as a float in slot 0 (where a
+// half2 of direction 0 would be) and component B's in a tenth slot: rounding
+// it to FP16 would move the node's mass by up to 2^-12 of the rest population
+// every step, and those roundings add up (4% of a component's mass over 20k
+// steps of a drop on the 30-degree plane), where the FP32 remainder keeps the
+// mass as FP32 storage does.  own is a node's byte offset from the buffer
+// base, pb a slot's bytes.
 template <typename S> struct Store;
 template <> struct Store<float> {
     using P = float2;  // one direction of components A and B
@@ -150,7 +156,6 @@ template <> struct Store<float> {
         f2v t = {v.x, v.y};
         __builtin_nontemporal_store(t, (f2v *)p);
     }
-    static __device__ __forceinline__ uint32_t rest_off(uint32_t, uint32_t own) { return own; }
 };
 template <> struct Store<__half> {
     using P = __half2;
@@ -162,24 +167,47 @@ template <> struct Store<__half> {
     static __device__ __forceinline__ void put2nt(__half2 *p, __half2 v) {
         __builtin_nontemporal_store(__builtin_bit_cast(uint32_t, v), (uint32_t *)p);
     }
-    static __device__ __forceinline__ uint32_t rest_off(uint32_t pb, uint32_t own) { return 9u * pb + 2u * own; }
 };
+
+// Direction slots per segment: 9 in FP32 (slot 0 holds the rest pair), 10 in
+// FP16 (slots 0 and 9 hold the FP32 rest populations of A and B).
+template <typename S> constexpr uint32_t pop_slots() { return sizeof(S) == 4 ? 9u : 10u; }
+// bytes of one slot and of one segment, for elements of NC components of S
+template <typename S, int NC> constexpr uint32_t slot_bytes() { return 64u * (uint32_t)sizeof(S) * NC; }
+template <typename S, int NC> constexpr uint32_t seg_bytes() { return pop_slots<S>() * slot_bytes<S, NC>(); }
+template <typename S, int NC> __device__ __forceinline__ uint32_t col_off(int x) {
+    return (uint32_t)(x >> 6) * seg_bytes<S, NC>() + (uint32_t)(x & 63) * ((uint32_t)sizeof(S) * NC);
+}
 
 // The rest population of components A and B at a node, storage units, FP32.
 template <typename S>
 __device__ __forceinline__ float2 ld_rest(const typename Store<S>::P *base, uint32_t pb, uint32_t own) {
-    return *(const float2 *)((const char *)base + Store<S>::rest_off(pb, own));
+    const char *b = (const char *)base + own;
+    if constexpr (sizeof(S) == 4)
+        return *(const float2 *)b;
+    else
+        return make_float2(*(const float *)b, *(const float *)(b + 9u * pb));
 }
 template <typename S>
 __device__ __forceinline__ void put_rest(typename Store<S>::P *base, uint32_t pb, uint32_t own, float a, float b,
                                          bool nt) {
-    float2 *p = (float2 *)((char *)base + Store<S>::rest_off(pb, own));
-    if (nt) {
-        typedef float f2v __attribute__((ext_vector_type(2)));
-        f2v t = {a, b};
-        __builtin_nontemporal_store(t, (f2v *)p);
+    char *q = (char *)base + own;
+    if constexpr (sizeof(S) == 4) {
+        if (nt) {
+            typedef float f2v __attribute__((ext_vector_type(2)));
+            f2v t = {a, b};
+            __builtin_nontemporal_store(t, (f2v *)q);
+        } else {
+            *(float2 *)q = make_float2(a, b);
+        }
     } else {
-        *p = make_float2(a, b);
+        if (nt) {
+            __builtin_nontemporal_store(a, (float *)q);
+            __builtin_nontemporal_store(b, (float *)(q + 9u * pb));
+        } else {
+            *(float *)q = a;
+            *(float *)(q + 9u * pb) = b;
+        }
     }
 }
 
@@ -233,7 +261,7 @@ struct Inst {
     const uint32_t *m25;      // fluid D2Q25 neighbours of interface solids, row pitch `pitch`
     const uint8_t *tflag;     // TF_* per tile
     int nx, ny, pitch, tiles_x, tiles_y;
-    int64_t plane;            // elements per population plane = ny * pitch
+    int64_t plane;            // nodes per padded lattice = ny * pitch (node words, masks)
     uint32_t periodic;        // bit0 x, bit1 y
     int small;                // a periodic size below a tile plus halo: wrap by modulo
     int bc, avg;
@@ -288,36 +316,42 @@ __device__ __forceinline__ uint32_t node_word(const Inst &I, int gx, int gy) {
     return I.node[(size_t)gy * I.pitch + gx];
 }
 
-// Byte offsets, within one population plane, of the 3 x 3 block around a fluid
-// node, for plane elements of NC components of type S.  Only tiles on a
-// periodic border (edge) need the wrap: elsewhere a fluid node's neighbours
-// are inside the domain.
+// Byte offset of lattice row y from the buffer base (segments of NC
+// components of type S).
+template <typename S, int NC> __device__ __forceinline__ uint32_t row_off(const Inst &I, int y) {
+    return (uint32_t)y * ((uint32_t)(I.pitch >> 6) * seg_bytes<S, NC>());
+}
+
+// Byte offsets, from the buffer base, of the rows and columns of the 3 x 3
+// block around a fluid node, for elements of NC components of type S (a
+// node's offset is its row's plus its column's).  Only tiles on a periodic
+// border (edge) need the wrap: elsewhere a fluid node's neighbours are inside
+// the domain.
 struct Around {
     uint32_t row[3], col[3];
 };
 
 template <typename S, int NC = 2>
 __device__ __forceinline__ Around around(const Inst &I, int gx, int gy, bool edge) {
-    constexpr uint32_t EB = (uint32_t)sizeof(S) * NC;
     Around a;
     if (!edge) {
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
-            a.col[j] = (uint32_t)(gx - 1 + j) * EB;
-            a.row[j] = (uint32_t)(gy - 1 + j) * (uint32_t)I.pitch * EB;
+            a.col[j] = col_off<S, NC>(gx - 1 + j);
+            a.row[j] = row_off<S, NC>(I, gy - 1 + j);
         }
         return a;
     }
     const bool small = I.small != 0;
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-        a.col[j] = (uint32_t)wrap(gx - 1 + j, I.nx, small) * EB;
-        a.row[j] = (uint32_t)wrap(gy - 1 + j, I.ny, small) * (uint32_t)I.pitch * EB;
+        a.col[j] = col_off<S, NC>(wrap(gx - 1 + j, I.nx, small));
+        a.row[j] = row_off<S, NC>(I, wrap(gy - 1 + j, I.ny, small));
     }
     return a;
 }
 
-// Byte offset, from the first plane, of the population of direction i that
+// Byte offset, from the buffer base, of the population of direction i that
 // a fluid node pulls: from the upstream node x - c_i = x + c_opp(i), or, when
 // that node is solid (bit opp(i) - 1 of the node word w), the half-way
 // bounce-back of the node's own opposite population.
@@ -327,8 +361,8 @@ __device__ __forceinline__ uint32_t pull_off(int i, uint32_t pb, const Around &a
 }
 
 // Pull the 9 populations of both components at a fluid node (Eq. 1
-// streaming with half-way bounce-back).  base is the first plane, pb the plane
-// size in bytes; dA, dB receive storage units.
+// streaming with half-way bounce-back).  base is the buffer base, pb a slot's
+// bytes; dA, dB receive storage units.
 template <typename S>
 __device__ __forceinline__ void pull9(const typename Store<S>::P *__restrict__ base, uint32_t pb, const Around &a,
                                       uint32_t w, float dA[9], float dB[9]) {
@@ -500,7 +534,7 @@ __device__ __forceinline__ void process_tile(const Inst &I, int tile_x, int tile
     using P = typename Store<S>::P;
     const P *__restrict__ fin = (const P *)I.buf[parity];
     P *__restrict__ fout = (P *)I.buf[parity ^ 1];
-    const uint32_t pb = (uint32_t)(I.plane * (int64_t)sizeof(P));
+    constexpr uint32_t pb = slot_bytes<S, 2>();
     const float rref[2] = {I.rrefA, I.rrefB};
     // tiles whose halo crosses a periodic border need coordinate wraps
     const bool edge = tile_edge(I.small != 0, I.periodic, tx0, ty0, I.nx, I.ny, TY);
@@ -517,7 +551,7 @@ __device__ __forceinline__ void process_tile(const Inst &I, int tile_x, int tile
     float d[RPT][2][9];
     float sd[RPT][2];   // incoming deviation sums, storage units
     uint32_t w[RPT];    // node words
-    uint32_t own[RPT];  // byte offset of the owned node in a plane
+    uint32_t own[RPT];  // byte offset of the owned node (its direction-0 element)
     bool owned[RPT];
 #pragma unroll
     for (int r = 0; r < RPT; ++r) w[r] = node_word(I, tx0 + lx, ty0 + lr + RPP * r);
@@ -532,7 +566,7 @@ __device__ __forceinline__ void process_tile(const Inst &I, int tile_x, int tile
         const int ly = lr + RPP * r;
         const int gx = tx0 + lx, gy = ty0 + ly;
         owned[r] = gx < I.nx && gy < I.ny;
-        own[r] = (uint32_t)(gy * I.pitch + gx) * (uint32_t)sizeof(P);
+        own[r] = row_off<S, 2>(I, gy) + col_off<S, 2>(gx);
         sm.lf[rt_idx<TY>(lx, ly)] =
             (uint8_t)(((w[r] & NW_SOLID) ? LF_SOLID : 0) | ((w[r] & NW_IFACE) ? LF_IFACE : 0));
         if (!(w[r] & NW_SOLID)) {

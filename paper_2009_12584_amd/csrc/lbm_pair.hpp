@@ -45,8 +45,8 @@ template <int TY> struct SmemLS {
 // the caches (non-temporal), put_plain does not.
 template <typename S> struct Comp;
 // ld_rest / put_rest address component c of the node's rest element, FP32 in
-// both storages (see Store): in plane 0 for FP32 storage, in the float pair
-// plane after the nine FP16 planes for FP16 storage.
+// both storages (see Store): in slot 0 as a float pair for FP32 storage, in
+// slots 0 (A) and 9 (B) as floats for FP16 storage.
 template <> struct Comp<float> {
     static __device__ __forceinline__ float ld(const char *p) { return *(const float *)p; }
     static __device__ __forceinline__ float enc(float v) { return v; }
@@ -65,7 +65,7 @@ template <> struct Comp<__half> {
     }
     static __device__ __forceinline__ void put_plain(char *p, __half v) { *(__half *)p = v; }
     static __device__ __forceinline__ uint32_t rest_off(uint32_t pb, uint32_t own, int c) {
-        return 9u * pb + 2u * own + 4u * (uint32_t)c;
+        return own + (c ? 9u * pb : 0u);
     }
     using E = __half;
 };
@@ -83,7 +83,7 @@ __device__ __forceinline__ void put_rest_c(char *base, uint32_t pb, uint32_t own
 }
 
 // Pull of one component's 9 populations (Eq. 1 streaming, half-way
-// bounce-back from the node word); base is the buffer's first plane.
+// bounce-back from the node word); base is the buffer's base.
 template <typename S>
 __device__ __forceinline__ void pull9c(const char *base, uint32_t pb, const Around &a, uint32_t w, int c, float d[9]) {
     const uint32_t own = a.row[1] + a.col[1];
@@ -178,7 +178,7 @@ __device__ __forceinline__ void process_tile_ls(const Inst &I, int tile_x, int t
     const char *fin = (const char *)I.buf[parity];
     char *fout = (char *)I.buf[parity ^ 1];
     const uint32_t coff = (uint32_t)c * (uint32_t)sizeof(S);  // the lane's component within a pair element
-    const uint32_t pb = (uint32_t)(I.plane * (int64_t)sizeof(P));
+    constexpr uint32_t pb = slot_bytes<S, 2>();
     const float rref = c == 0 ? I.rrefA : I.rrefB;
     const bool edge = tile_edge(I.small != 0, I.periodic, tx0, ty0, I.nx, I.ny, TY);
     const bool need_rt = (BC == BC_IMPROVED) &&
@@ -190,7 +190,7 @@ __device__ __forceinline__ void process_tile_ls(const Inst &I, int tile_x, int t
     float d[RPT][9];
     float sd[RPT];      // incoming deviation sum, storage units
     uint32_t w[RPT];    // node words
-    uint32_t own[RPT];  // byte offset of the node's pair element in a plane
+    uint32_t own[RPT];  // byte offset of the node's pair element (direction 0)
     bool owned[RPT];
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
@@ -198,7 +198,7 @@ __device__ __forceinline__ void process_tile_ls(const Inst &I, int tile_x, int t
         const int gx = tx0 + lx, gy = ty0 + ly;
         w[r] = node_word(I, gx, gy);
         owned[r] = gx < I.nx && gy < I.ny;
-        own[r] = (uint32_t)(gy * I.pitch + gx) * (uint32_t)sizeof(P);
+        own[r] = row_off<S, 2>(I, gy) + col_off<S, 2>(gx);
         if (c == 0)
             sm.lf[rt_idx<TY>(lx, ly)] =
                 (uint8_t)(((w[r] & NW_SOLID) ? LF_SOLID : 0) | ((w[r] & NW_IFACE) ? LF_IFACE : 0));

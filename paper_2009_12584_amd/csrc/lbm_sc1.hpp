@@ -3,8 +3,9 @@
 // wetting problem (a drop sliding on an off-grid wall under Martys-Chen and
 // LLKC adhesion) appears in this standard model as well (Sections 3.1, 5).
 //
-// One population set, stored as 9 planes of single deviations
-// d_i = f_i - w_i rho_ref (FP32, or FP16 x 2^10).  Per step and node:
+// One population set, stored in the same 64-node row segments as the
+// two-component step, of single deviations d_i = f_i - w_i rho_ref (FP32, or
+// FP16 x 2^10).  Per step and node:
 //   rho = sum_i f_i (pull streaming with half-way bounce-back),
 //   psi = psi0 (1 - exp(-rho / psi0)),
 //   F = -G psi(x) sum_i w_i psi(x + c_i) c_i over fluid neighbours
@@ -30,7 +31,6 @@ template <> struct Store1<float> {
     static __device__ __forceinline__ float dec(float v) { return v; }
     static __device__ __forceinline__ void put(float *p, float v) { *p = v; }
     static __device__ __forceinline__ void putnt(float *p, float v) { __builtin_nontemporal_store(v, p); }
-    static __device__ __forceinline__ uint32_t rest_off(uint32_t, uint32_t own) { return own; }
 };
 template <> struct Store1<__half> {
     using P = __half;
@@ -42,22 +42,40 @@ template <> struct Store1<__half> {
     static __device__ __forceinline__ void putnt(__half *p, __half v) {
         __builtin_nontemporal_store(__builtin_bit_cast(uint16_t, v), (uint16_t *)p);
     }
-    // the rest population in FP32 after the nine FP16 planes, as in Store<__half>
-    static __device__ __forceinline__ uint32_t rest_off(uint32_t pb, uint32_t own) { return 9u * pb + 2u * own; }
 };
 
-// The node's rest population, storage units, FP32 in both storages.
+// The node's rest population, storage units, FP32 in both storages: in slot 0
+// for FP32 storage; for FP16 storage, whose 2-byte elements cannot hold it,
+// its upper 16 bits in slot 0 and its lower 16 bits in slot 9.
 template <typename S>
 __device__ __forceinline__ float ld_rest1(const typename Store1<S>::P *base, uint32_t pb, uint32_t own) {
-    return *(const float *)((const char *)base + Store1<S>::rest_off(pb, own));
+    const char *b = (const char *)base + own;
+    if constexpr (sizeof(S) == 4) {
+        return *(const float *)b;
+    } else {
+        const uint32_t hi = *(const uint16_t *)b, lo = *(const uint16_t *)(b + 9u * pb);
+        return __builtin_bit_cast(float, (hi << 16) | lo);
+    }
 }
 template <typename S>
 __device__ __forceinline__ void put_rest1(typename Store1<S>::P *base, uint32_t pb, uint32_t own, float v, bool nt) {
-    float *p = (float *)((char *)base + Store1<S>::rest_off(pb, own));
-    if (nt)
-        __builtin_nontemporal_store(v, p);
-    else
-        *p = v;
+    char *q = (char *)base + own;
+    if constexpr (sizeof(S) == 4) {
+        if (nt)
+            __builtin_nontemporal_store(v, (float *)q);
+        else
+            *(float *)q = v;
+    } else {
+        const uint32_t bits = __builtin_bit_cast(uint32_t, v);
+        const uint16_t hi = (uint16_t)(bits >> 16), lo = (uint16_t)(bits & 0xffffu);
+        if (nt) {
+            __builtin_nontemporal_store(hi, (uint16_t *)q);
+            __builtin_nontemporal_store(lo, (uint16_t *)(q + 9u * pb));
+        } else {
+            *(uint16_t *)q = hi;
+            *(uint16_t *)(q + 9u * pb) = lo;
+        }
+    }
 }
 
 // Pull of the 9 populations at a fluid node (bounce-back from the node word).
@@ -84,7 +102,7 @@ __device__ __forceinline__ void process_tile_sc1(const Inst &I, int tile_x, int 
     const int tx0 = tile_x * TX, ty0 = tile_y * TY;
     const P *__restrict__ fin = (const P *)I.buf[parity];
     P *__restrict__ fout = (P *)I.buf[parity ^ 1];
-    const uint32_t pb = (uint32_t)(I.plane * (int64_t)sizeof(P));
+    constexpr uint32_t pb = slot_bytes<S, 1>();
     const float rref = I.rrefA;
     const bool edge = tile_edge(I.small != 0, I.periodic, tx0, ty0, I.nx, I.ny, TY);
 
@@ -107,7 +125,7 @@ __device__ __forceinline__ void process_tile_sc1(const Inst &I, int tile_x, int 
         const int ly = lr + RPP * r;
         const int gx = tx0 + lx, gy = ty0 + ly;
         owned[r] = gx < I.nx && gy < I.ny;
-        own[r] = (uint32_t)(gy * I.pitch + gx) * (uint32_t)sizeof(P);
+        own[r] = row_off<S, 1>(I, gy) + col_off<S, 1>(gx);
         if (!(w[r] & NW_SOLID)) {
             pull9_1<S>(fin, pb, around<S, 1>(I, gx, gy, edge), w[r], d[r]);
         } else {

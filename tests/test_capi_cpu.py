@@ -83,7 +83,7 @@ def test_state_bytes_of_a_parameter_set():
     from paper_2009_12584_amd.sim import state_bytes
 
     assert state_bytes(100, 30) == 9 * 30 * 128 * 8
-    assert state_bytes(100, 30, storage="f16") == 30 * 128 * (9 * 4 + 8)
+    assert state_bytes(100, 30, storage="f16") == 30 * 128 * 10 * 4
     assert state_bytes(0, 30) == 0
 
 
@@ -93,15 +93,15 @@ def test_pool_footprint_counts_both_buffers():
     f32 = M.Pool.footprint(512, 256)
     f16 = M.Pool.footprint(512, 256, storage="f16")
     assert f32 >= 2 * 18 * 512 * 256 * 4
-    # FP16: nine FP16 planes and the FP32 rest-population plane per component
-    assert f16 >= 2 * 2 * 512 * 256 * (9 * 2 + 4) and f16 < f32
+    # FP16: eight FP16 directions and the FP32 rest population per component
+    assert f16 >= 2 * 2 * 512 * 256 * (8 * 2 + 4) and f16 < f32
 
 
-@pytest.mark.parametrize("nx,ny,storage", [(8000, 8000, "f32"), (11000, 9000, "f16"), (16000, 16000, "f16")])
+@pytest.mark.parametrize("nx,ny,storage", [(8000, 8000, "f32"), (11000, 10000, "f16"), (16000, 16000, "f16")])
 def test_grid_beyond_the_32bit_buffer_offsets_rejected(nx, ny, storage):
     """A population buffer is addressed with 32-bit byte offsets: FP32 holds 72 B
-    per node, FP16 44 B (nine FP16 planes and the FP32 rest plane, two
-    components).  Larger grids are refused before the mask or densities are
+    per node, FP16 40 B (eight FP16 directions and the FP32 rest
+    population of two components).  Larger grids are refused before the mask or densities are
     read, so one-element host buffers suffice here."""
     import ctypes
 
