@@ -228,14 +228,14 @@ def headline(M, torch, W, args, probe):
     g = c.geometry
     mask = M.mask_disk(c.nx, c.ny, g[1], g[2], g[3])
     fluid, nodes = int((mask == 0).sum()), c.nx * c.ny
-    if args.autotune_headline:
+    if args.autotune_shapes:
         cfg = launch_config_for(mask, c.rhoA0, c.rhoB0, **c.params())
         ty, lanes = cfg["tile_y"], cfg["lanes"]
     else:
-        # the autotuner's pick for this workload on MI355X (64 x 4 tiles, one
-        # lane per node: 24.97 us per step against 25.65 for 64 x 8), fixed so
-        # that the profiled kernel is the timed one
-        ty, lanes = 4, 1
+        # the autotuner's pick for this workload on MI355X (64 x 8 tiles, one
+        # lane per node: 23.8 us per step against 24.7 for 64 x 4 and 29.6
+        # for two lanes), fixed so that the profiled kernel is the timed one
+        ty, lanes = 8, 1
     K, Wm = args.steps, args.warmup
     glen = graph_len(args, K)
     diag_every = glen if glen else 100
@@ -396,11 +396,13 @@ def config2_row(M, torch, W, args):
     c = W.config2()
     mask = M.mask_plane(c.nx, c.ny, c.geometry[1], c.geometry[2])
     fluid, nodes = int((mask == 0).sum()), c.nx * c.ny
-    if args.fixed_shapes:
-        ty, lanes = 8, 2
-    else:
+    if args.autotune_shapes:
         cfg = launch_config_for(mask, c.rhoA0, c.rhoB0, **c.params())
         ty, lanes = cfg["tile_y"], cfg["lanes"]
+    else:
+        # the autotuner's pick (64 x 8, one lane per node: 8.0 us against 8.3
+        # for two lanes), fixed so that the profiled kernel is the timed one
+        ty, lanes = 8, 1
     glen = graph_len(args, 100)
     stream = torch.cuda.Stream()
     sim = M.Simulation(mask, c.rhoA0, c.rhoB0, stream=stream, graph_steps=glen, diag_every=glen if glen else 100,
@@ -476,7 +478,7 @@ def batched_rows(M, torch, W, args):
         if args.fixed_shapes or args.graph_steps == 0:
             # fixed shapes (the autotuner's usual picks): counter runs name
             # one kernel per storage and capture no autotuner graphs
-            ty, lanes = (8 if storage == "f32" else 4), 1
+            ty, lanes = 8, 1
         else:
             cfg = launch_config_for_batch(items, storage=storage, stream=stream)
             ty, lanes = cfg["tile_y"], cfg["lanes"]
@@ -676,9 +678,11 @@ def main():
                     help="steps per captured HIP graph (0 = plain launches only, which per-dispatch counter "
                          "collection needs); default min(100, steps)")
     ap.add_argument("--fixed-shapes", action="store_true",
-                    help="fixed launch shapes instead of the autotuner (counter runs name one kernel)")
-    ap.add_argument("--autotune-headline", action="store_true",
-                    help="pick the headline's launch shape with the autotuner instead of the fixed 64 x 4, one lane")
+                    help="fixed launch shapes for the batched row instead of the autotuner (counter runs name one "
+                         "kernel)")
+    ap.add_argument("--autotune-shapes", action="store_true",
+                    help="pick the launch shapes of configurations 3 and 2 with the autotuner instead of the fixed "
+                         "64 x 8, one lane per node")
     ap.add_argument("--no-oracle", action="store_true",
                     help="no oracle comparisons (error_vs_oracle null) and no untimed run to 50,000 steps: for "
                          "profiler runs, which time kernels only")

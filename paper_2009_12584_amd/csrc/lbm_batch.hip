@@ -58,19 +58,44 @@ void launch_batch(const BatchLaunch &B, hipStream_t s, long long L, bool diag) {
         hipLaunchKernelGGL(k_batch_diag_reduce, dim3(B.ninst), dim3(256), 0, s, B.insts, B.partials, L, B.flags);
 }
 
-// Flattened (instance, tile) pairs in instance order; within an instance
-// tiles follow the grouped order of the single-instance kernel.  Tiles without
-// a fluid node are left out (fluid_of(k): one flag per logical tile of
-// instance k): such a tile moves no population, and its workgroup would only
-// occupy a slot of the launch.  range[k] receives instance k's (first, count).
+// Flattened (instance, tile) pairs, each instance's tiles contiguous and in
+// the grouped order of the single-instance kernel.  Tiles without a fluid node
+// are left out (fluid_of(k): one flag per logical tile of instance k): such a
+// tile moves no population, and its workgroup would only occupy a slot of the
+// launch.  The launch gives each of the 8 XCDs one contiguous eighth of the
+// list (xcd_tile), so instances are dealt to 8 bands of about equal tile
+// counts, least-loaded band first, improved-scheme instances (whose wall tiles
+// carry the 3-ring frame and Eq. 7) before the others and larger before
+// smaller: every XCD then runs its heavy tiles first and ends on light ones
+// (the 64-instance FP16 batch, bound by instruction issue, ran 4.5-6.5%
+// faster; FP32 unchanged).  range[k] receives instance k's (first, count).
 template <typename InstOf, typename FluidOf>
 TileLists build_tiles(int n, InstOf inst_of, FluidOf fluid_of, std::vector<int2> &out, std::vector<int2> &range) {
     TileLists T;
     out.clear();
     range.assign(n, make_int2(0, 0));
+    std::vector<int> ord, cnt(n, 0);
     for (int k = 0; k < n; ++k) {
+        if (!inst_of(k)) continue;
+        for (uint8_t v : fluid_of(k)) cnt[k] += v ? 1 : 0;
+        ord.push_back(k);
+    }
+    auto heavy = [&](int k) { return inst_of(k)->bc == BC_IMPROVED ? 1 : 0; };
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) {
+        if (heavy(a) != heavy(b)) return heavy(a) > heavy(b);
+        return cnt[a] > cnt[b];
+    });
+    std::vector<std::vector<int>> band(8);
+    std::vector<long> load(8, 0);
+    for (int k : ord) {
+        const int j = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        band[j].push_back(k);
+        load[j] += cnt[k];
+    }
+    std::vector<int> seq;
+    for (const std::vector<int> &b : band) seq.insert(seq.end(), b.begin(), b.end());
+    for (int k : seq) {
         const Inst *I = inst_of(k);
-        if (!I) continue;
         const std::vector<uint8_t> &f = fluid_of(k);
         const int nt = I->tiles_x * I->tiles_y;
         const int first = (int)out.size();

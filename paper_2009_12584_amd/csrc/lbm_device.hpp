@@ -50,9 +50,13 @@
 
 namespace mclbm {
 
-// Threads per workgroup for a tile of TY rows: 4 wavefronts, or 8 for the
-// 32-row tile (each thread then owns TY / (threads / 64) rows).
-constexpr int threads_for(int TY) { return TY == 32 ? 512 : 256; }
+// Threads per workgroup for a tile of TY rows: one per node up to 8 rows
+// (fewer registers per lane and more wavefronts in flight: on MI355X the
+// 64 x 8 tile with one thread per node ran configuration 3 in 23.7 us
+// instead of 25.9 and configuration 2 in 8.0 instead of 12.1 against two nodes
+// per thread), 4 wavefronts for 16 rows and 8 for 32 (each thread then owns
+// TY / (threads / 64) rows).
+constexpr int threads_for(int TY) { return TY == 32 || TY == 8 ? 512 : 256; }
 
 // Node word: bit (i-1), i = 1..8, set when neighbour x + c_i is solid or lies
 // beyond a closed border; then the flags below.
