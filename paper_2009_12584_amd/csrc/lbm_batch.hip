@@ -58,8 +58,8 @@ void launch_batch(const BatchLaunch &B, hipStream_t s, long long L, bool diag) {
         hipLaunchKernelGGL(k_batch_diag_reduce, dim3(B.ninst), dim3(256), 0, s, B.insts, B.partials, L, B.flags);
 }
 
-// Flattened (instance, tile) pairs, each instance's tiles contiguous and in
-// the grouped order of the single-instance kernel.  Tiles without a fluid node
+// Flattened (instance, packed tile coordinates) pairs, each instance's tiles
+// contiguous and in the grouped order of the single-instance kernel.  Tiles without a fluid node
 // are left out (fluid_of(k): one flag per logical tile of instance k): such a
 // tile moves no population, and its workgroup would only occupy a slot of the
 // launch.  The launch gives each of the 8 XCDs one contiguous eighth of the
@@ -99,8 +99,12 @@ TileLists build_tiles(int n, InstOf inst_of, FluidOf fluid_of, std::vector<int2>
         const std::vector<uint8_t> &f = fluid_of(k);
         const int nt = I->tiles_x * I->tiles_y;
         const int first = (int)out.size();
-        for (int t = 0; t < nt; ++t)
-            if (f[t]) out.push_back(make_int2(k, t));
+        for (int t = 0; t < nt; ++t) {
+            if (!f[t]) continue;
+            int tx, ty;
+            tile_coords(t, I->tiles_x, I->tiles_y, I->tg, tx, ty);
+            out.push_back(make_int2(k, pack_tile(tx, ty)));
+        }
         const int kept = (int)out.size() - first;
         range[k] = make_int2(first, kept);
         T.cnt[I->bc] += kept;

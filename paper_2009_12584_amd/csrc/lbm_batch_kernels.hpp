@@ -26,7 +26,7 @@ struct BatchLaunch {
     TileLists T;
     const Inst *insts = nullptr;  // device table of ninst instances
     int ninst = 0;
-    const int2 *tiles = nullptr;  // device list of (instance, logical tile), instance order
+    const int2 *tiles = nullptr;  // device list of (instance, packed tile coordinates)
     double *partials = nullptr;   // device, 6 doubles per listed tile (diagnostic launches)
     int *flags = nullptr;         // device, per instance: sticky flags after a reduction (or null)
 };
@@ -41,7 +41,7 @@ struct BatchLaunch {
     if (L >= I.t_end) return;                                                 \
     const int parity = (I.parity0 ^ launch_parity) & 1;                       \
     int tx, ty;                                                               \
-    tile_coords(e.y, I.tiles_x, I.tiles_y, I.tg, tx, ty);                     \
+    unpack_tile(e.y, tx, ty);                                                 \
     DiagAcc acc;
 
 template <typename S, int TY, int BC, bool DIAG>

@@ -94,9 +94,15 @@ inline int validate(const lbm_params *p, const uint8_t *mask, const double *rA, 
         set_err("grid %d x %d: both sizes must be >= 1", p->nx, p->ny);
         return LBM_EINVAL;
     }
-    // the 9 population planes are addressed with 32-bit byte offsets
+    // a population buffer is addressed with 32-bit byte offsets
     if ((double)pop_buffer_bytes(*p) >= 4294967296.0) {
         set_err("grid %d x %d: a population buffer would exceed 4 GiB", p->nx, p->ny);
+        return LBM_EINVAL;
+    }
+    // row offsets are 24-bit products: the bytes of one row of segments (at
+    // most 72 per node) stay below 2^24 (the row index does by the 4 GiB bound)
+    if ((double)pitch_of(p->nx) * 72.0 >= 16777216.0) {
+        set_err("grid %d x %d: rows wider than 233,000 nodes are not supported", p->nx, p->ny);
         return LBM_EINVAL;
     }
     if (!(p->tau > 0.5) || !std::isfinite(p->tau)) {

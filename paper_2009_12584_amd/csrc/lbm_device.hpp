@@ -279,8 +279,8 @@ struct Inst {
     int64_t t_end;            // pool: launch counter at which this instance stops
     DiagDev *dd;              // batch and pool: this instance's FP64 reduction targets
     int tile0, ntl;           // batch and pool: its tiles' range in the flattened tile list
-    const int *steps_tiles;   // single simulation: logical tiles a step launches (those
-    int nsteps_tiles;         //   holding a fluid node), or null for every tile
+    const int *steps_tiles;   // single simulation: tiles a step launches (those holding a
+    int nsteps_tiles;         //   fluid node, packed coordinates), or null for every tile
 };
 
 struct Fields {  // fields mode outputs, unpadded nx * ny planes, any may be null
@@ -306,6 +306,13 @@ template <int TY> __device__ __forceinline__ int rt_idx(int lx, int ly) {
     return (ly + 1) * Smem<TY>::VW + (lx + 1);
 }
 
+// Index of a coordinate near a tile, kept inside the lattice: wrapped in a
+// periodic direction, clamped in a closed one (positions beyond a closed
+// border are never used for their value there).
+__device__ __forceinline__ int keep_in(int g, int n, bool periodic, bool small) {
+    return periodic ? wrap(g, n, small) : min(max(g, 0), n - 1);
+}
+
 // Node word at global (gx, gy) near a tile: wrapped in periodic directions,
 // solid beyond a closed border.
 __device__ __forceinline__ uint32_t node_word(const Inst &I, int gx, int gy) {
@@ -317,13 +324,18 @@ __device__ __forceinline__ uint32_t node_word(const Inst &I, int gx, int gy) {
         if (!(I.periodic & 2u)) return NW_SOLID;
         gy = wrap(gy, I.ny, I.small != 0);
     }
-    return I.node[(size_t)gy * I.pitch + gx];
+    return I.node[__umul24((uint32_t)gy, (uint32_t)I.pitch) + (uint32_t)gx];
 }
 
-// Byte offset of lattice row y from the buffer base (segments of NC
-// components of type S).
+// Bytes of one lattice row of segments, and the byte offset of row y from the
+// buffer base (segments of NC components of type S).  Row indices and row
+// bytes stay below 2^24 (the host refuses wider grids), so the products are
+// full-rate 24-bit multiplies instead of quarter-rate 32-bit ones.
+template <typename S, int NC> __device__ __forceinline__ uint32_t row_bytes(const Inst &I) {
+    return (uint32_t)(I.pitch >> 6) * seg_bytes<S, NC>();
+}
 template <typename S, int NC> __device__ __forceinline__ uint32_t row_off(const Inst &I, int y) {
-    return (uint32_t)y * ((uint32_t)(I.pitch >> 6) * seg_bytes<S, NC>());
+    return __umul24((uint32_t)y, row_bytes<S, NC>(I));
 }
 
 // Byte offsets, from the buffer base, of the rows and columns of the 3 x 3
@@ -339,11 +351,12 @@ template <typename S, int NC = 2>
 __device__ __forceinline__ Around around(const Inst &I, int gx, int gy, bool edge) {
     Around a;
     if (!edge) {
+        const uint32_t rb = row_bytes<S, NC>(I);
+        a.row[1] = __umul24((uint32_t)gy, rb);
+        a.row[0] = a.row[1] - rb;
+        a.row[2] = a.row[1] + rb;
 #pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            a.col[j] = col_off<S, NC>(gx - 1 + j);
-            a.row[j] = row_off<S, NC>(I, gy - 1 + j);
-        }
+        for (int j = 0; j < 3; ++j) a.col[j] = col_off<S, NC>(gx - 1 + j);
         return a;
     }
     const bool small = I.small != 0;
@@ -592,8 +605,10 @@ __device__ __forceinline__ void process_tile(const Inst &I, int tile_x, int tile
         for (int s = 0; s < NV; ++s) {
             const int k = tid + s * threads_for(TY);
             const int vx = k % Smem<TY>::VW - 1, vy = k / Smem<TY>::VW - 1;
-            const int gx = wrap(tx0 + vx, I.nx, true), gy = wrap(ty0 + vy, I.ny, true);
-            m25v[s] = k < Smem<TY>::VW * Smem<TY>::VH ? I.m25[(size_t)gy * I.pitch + gx] : 0u;
+            const int gx = keep_in(tx0 + vx, I.nx, I.periodic & 1u, I.small != 0);
+            const int gy = keep_in(ty0 + vy, I.ny, I.periodic & 2u, I.small != 0);
+            m25v[s] = k < Smem<TY>::VW * Smem<TY>::VH ? I.m25[__umul24((uint32_t)gy, (uint32_t)I.pitch) + (uint32_t)gx]
+                                                      : 0u;
         }
     }
 

@@ -220,8 +220,9 @@ __device__ __forceinline__ void process_tile_ls(const Inst &I, int tile_x, int t
         for (int s = 0; s < NV; ++s) {
             const int k = q + s * NPP;
             const int vx = k % L::VW - 1, vy = k / L::VW - 1;
-            const int gx = wrap(tx0 + vx, I.nx, true), gy = wrap(ty0 + vy, I.ny, true);
-            m25v[s] = k < NVP ? I.m25[(size_t)gy * I.pitch + gx] : 0u;
+            const int gx = keep_in(tx0 + vx, I.nx, I.periodic & 1u, I.small != 0);
+            const int gy = keep_in(ty0 + vy, I.ny, I.periodic & 2u, I.small != 0);
+            m25v[s] = k < NVP ? I.m25[__umul24((uint32_t)gy, (uint32_t)I.pitch) + (uint32_t)gx] : 0u;
         }
     }
 

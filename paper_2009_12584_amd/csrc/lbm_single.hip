@@ -177,7 +177,12 @@ int lbm_create(const lbm_params *p, const uint8_t *mask, const double *rhoA0, co
         MCLBM_HIP(hipMalloc(&h->tflag, h->ntiles));
         // a step launches only the tiles that hold fluid, so that the blocks
         // of every XCD's band carry an equal share of the work
-        const std::vector<int> fl = fluid_tiles(mask, p->nx, p->ny, h->I.tiles_x, h->I.tiles_y, h->I.tg, h->ty);
+        std::vector<int> fl = fluid_tiles(mask, p->nx, p->ny, h->I.tiles_x, h->I.tiles_y, h->I.tg, h->ty);
+        for (int &t : fl) {  // the list holds packed tile coordinates
+            int tx, ty;
+            tile_coords(t, h->I.tiles_x, h->I.tiles_y, h->I.tg, tx, ty);
+            t = pack_tile(tx, ty);
+        }
         MCLBM_HIP(hipMalloc(&h->tlist, sizeof(int) * std::max<size_t>(fl.size(), 1)));
         if (!fl.empty())
             MCLBM_HIP(hipMemcpyAsync(h->tlist, fl.data(), sizeof(int) * fl.size(), hipMemcpyHostToDevice, h->stream));

@@ -7,19 +7,23 @@
 
 namespace mclbm {
 
-// Logical tile of block b: a step launch covers the listed tiles (those that
-// hold a fluid node, so that every XCD's band of blocks gets an equal share of
-// the work); a fields pass covers every tile.
-template <int MODE> __device__ __forceinline__ int block_tile(const Inst &I) {
+// Tile of block b: a step launch covers the listed tiles (those that hold a
+// fluid node, so that every XCD's band of blocks gets an equal share of the
+// work), whose coordinates the list holds packed; a fields pass covers every
+// logical tile.
+template <int MODE> __device__ __forceinline__ void block_tile(const Inst &I, int &tx, int &ty) {
     const int b = xcd_tile(blockIdx.x, gridDim.x);
-    return (MODE == MODE_STEP && I.steps_tiles) ? I.steps_tiles[b] : b;
+    if (MODE == MODE_STEP && I.steps_tiles)
+        unpack_tile(I.steps_tiles[b], tx, ty);
+    else
+        tile_coords(b, I.tiles_x, I.tiles_y, I.tg, tx, ty);
 }
 
 template <typename S, int TY, int BC, int MODE, bool DIAG, bool NT>
 __global__ __launch_bounds__(threads_for(TY)) void k_step(Inst I, int parity, Fields fo, double *partials) {
     __shared__ Smem<TY> sm;
     int tx, ty;
-    tile_coords(block_tile<MODE>(I), I.tiles_x, I.tiles_y, I.tg, tx, ty);
+    block_tile<MODE>(I, tx, ty);
     DiagAcc acc;
     process_tile<S, TY, BC, MODE, DIAG, NT>(I, tx, ty, parity, sm, acc, fo);
     if (DIAG) diag_partial<TY>(sm, acc, partials, blockIdx.x);
@@ -30,7 +34,7 @@ template <typename S, int TY, int BC, int MODE, bool DIAG, bool NT>
 __global__ __launch_bounds__(ls_threads(TY)) void k_step_ls(Inst I, int parity, Fields fo, double *partials) {
     __shared__ SmemLS<TY> sm;
     int tx, ty;
-    tile_coords(block_tile<MODE>(I), I.tiles_x, I.tiles_y, I.tg, tx, ty);
+    block_tile<MODE>(I, tx, ty);
     DiagAcc acc;
     process_tile_ls<S, TY, BC, MODE, DIAG, NT>(I, tx, ty, parity, sm, acc, fo);
     if (DIAG) diag_partial_ls<TY>(sm, acc, partials, blockIdx.x);
@@ -40,7 +44,7 @@ template <typename S, int TY, int BC, int MODE, bool DIAG, bool NT>
 __global__ __launch_bounds__(threads_for(TY)) void k_step_sc1(Inst I, int parity, Fields fo, double *partials) {
     __shared__ Smem<TY> sm;
     int tx, ty;
-    tile_coords(block_tile<MODE>(I), I.tiles_x, I.tiles_y, I.tg, tx, ty);
+    block_tile<MODE>(I, tx, ty);
     DiagAcc acc;
     process_tile_sc1<S, TY, BC, MODE, DIAG, NT>(I, tx, ty, parity, sm, acc, fo);
     if (DIAG) diag_partial<TY>(sm, acc, partials, blockIdx.x);

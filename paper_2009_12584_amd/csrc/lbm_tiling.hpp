@@ -15,6 +15,17 @@ constexpr int TX = 64;        // tile width: one wavefront per tile row
 constexpr int HMAX = 3;       // widest density halo (improved scheme, D2Q25 average)
 constexpr int FH = HMAX + 1;  // flag halo: a halo node's pull needs its neighbours' phi
 
+// A tile's coordinates packed into one word for the launch lists: the tile
+// column in the low 12 bits (grids are at most 233,000 nodes wide, 3,641
+// tile columns) and the tile row above them, so a block reads its tile with
+// two bit operations instead of dividing a logical index.
+constexpr int TILE_X_BITS = 12;
+MCLBM_HD int pack_tile(int tx, int ty) { return (ty << TILE_X_BITS) | tx; }
+MCLBM_HD void unpack_tile(int p, int &tx, int &ty) {
+    tx = p & ((1 << TILE_X_BITS) - 1);
+    ty = (int)((unsigned)p >> TILE_X_BITS);
+}
+
 // Periodic wrap of a coordinate into [0, n).  The compare-and-add form maps
 // [-n, 2n) into [0, n); `small` selects the modulo for any g.
 MCLBM_HD int wrap(int g, int n, bool small) {

@@ -48,6 +48,20 @@ int main() {
             ++cases;
         }
     }
+    // packed tile coordinates of the launch lists: every tile column of a
+    // 233,000-node-wide grid and every tile row of the tallest grid a 4 GiB
+    // buffer holds (64-node rows of 20 B per node, 4-row tiles) round-trip
+    const int max_tx = (233000 + TX - 1) / TX, max_ty = (int)(4294967296.0 / (64.0 * 20.0) / 4.0) + 1;
+    for (int tx : {0, 1, 63, 64, 4095, max_tx - 1})
+        for (int ty : {0, 1, 4095, 65535, 65536, max_ty - 1}) {
+            int a = -1, b = -1;
+            unpack_tile(pack_tile(tx, ty), a, b);
+            if (a != tx || b != ty || max_tx > (1 << TILE_X_BITS)) {
+                std::printf("tile (%d, %d) packs to (%d, %d)\n", tx, ty, a, b);
+                return 1;
+            }
+            ++cases;
+        }
     // the case of a 32-row tile over a 33-row periodic lattice reaches row 67
     if (!needs_modulo(33, 32)) {
         std::printf("33 rows in 32-row tiles must wrap by modulo\n");

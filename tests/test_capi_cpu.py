@@ -117,3 +117,23 @@ def test_grid_beyond_the_32bit_buffer_offsets_rejected(nx, ny, storage):
     assert code == capi.LBM_EINVAL
     assert "4 GiB" in capi.lib().lbm_last_error(None).decode()
     assert not h.value
+
+
+@pytest.mark.parametrize("nx,ny", [(240000, 10), (233100, 3)])
+def test_grid_beyond_the_24bit_row_offsets_rejected(nx, ny):
+    """Row offsets are 24-bit products (the bytes of a row of segments, at most
+    72 per node, below 2^24): wider grids are refused on the host."""
+    import ctypes
+
+    from paper_2009_12584_amd import capi
+
+    p = capi.make_params(nx, ny, storage="f16")
+    mask = np.ones(1, np.uint8)
+    rho = np.zeros(1)
+    h = ctypes.c_void_p()
+    code = capi.lib().lbm_create(ctypes.byref(p), mask.ctypes.data_as(ctypes.c_void_p),
+                                 rho.ctypes.data_as(ctypes.c_void_p), rho.ctypes.data_as(ctypes.c_void_p), None,
+                                 ctypes.byref(h))
+    assert code == capi.LBM_EINVAL
+    assert "233,000" in capi.lib().lbm_last_error(None).decode()
+    assert not h.value
