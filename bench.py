@@ -476,8 +476,8 @@ def batched_rows(M, torch, W, args):
         refs[k] = o.fields()
     for storage in ("f32", "f16"):
         if args.fixed_shapes or args.graph_steps == 0:
-            # fixed shapes (the autotuner's usual picks): counter runs name
-            # one kernel per storage and capture no autotuner graphs
+            # the autotuner's default shape: counter runs name one kernel per
+            # storage and capture no autotuner graphs
             ty, lanes = 8, 1
         else:
             cfg = launch_config_for_batch(items, storage=storage, stream=stream)
