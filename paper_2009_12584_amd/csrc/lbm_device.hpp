@@ -246,6 +246,18 @@ __device__ __forceinline__ double dsum9(const float d[9]) {
 // is its rounding.  Summed in FP32 in direction order by every step kernel.
 __device__ __forceinline__ float remainder_term(float d, float q) { return d - q; }
 
+// The same two terms for an FP16-stored pair (A in the low half, B in the
+// high half of the 32-bit word): d - q with q read as FP16 straight from its
+// half by one mixed-precision multiply-add, q (-1) + d, exact product and one
+// rounding, so the result is bit for bit that of converting q and
+// subtracting, without the two conversions.  Register arithmetic only.
+__device__ __forceinline__ float2 remainder_terms_f16(float dA, float dB, uint32_t q) {
+    float a, b;
+    asm("v_fma_mix_f32 %0, %1, -1.0, %2 op_sel_hi:[1,0,0]" : "=v"(a) : "v"(q), "v"(dA));
+    asm("v_fma_mix_f32 %0, %1, -1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "=v"(b) : "v"(q), "v"(dB));
+    return make_float2(a, b);
+}
+
 // FP64 reduction targets of one simulation.
 struct DiagDev {
     double mass[2];
@@ -811,10 +823,16 @@ __device__ __forceinline__ void process_tile(const Inst &I, int tile_x, int tile
             const float cFB = cdot(i, FBx, FBy);
             const auto q = Store<S>::enc2(coll_dir(i, d[r][0][i], drA, ra, eq, t, cFA, uFA3, ck),
                                           coll_dir(i, d[r][1][i], drB, rb, eq, t, cFB, uFB3, ck));
-            const float2 qd = Store<S>::dec2(q);
+            float2 rt;
+            if constexpr (sizeof(S) == 2) {
+                rt = remainder_terms_f16(d[r][0][i], d[r][1][i], __builtin_bit_cast(uint32_t, q));
+            } else {
+                const float2 qd = Store<S>::dec2(q);
+                rt = make_float2(remainder_term(d[r][0][i], qd.x), remainder_term(d[r][1][i], qd.y));
+            }
             // the sums start from the first term (0 + x would cost an add)
-            eA = i == 1 ? remainder_term(d[r][0][i], qd.x) : eA + remainder_term(d[r][0][i], qd.x);
-            eB = i == 1 ? remainder_term(d[r][1][i], qd.y) : eB + remainder_term(d[r][1][i], qd.y);
+            eA = i == 1 ? rt.x : eA + rt.x;
+            eB = i == 1 ? rt.y : eB + rt.y;
             // a uniform base plus a 32-bit offset; streaming (non-temporal)
             // stores when the populations do not fit the caches
             if constexpr (NT)
