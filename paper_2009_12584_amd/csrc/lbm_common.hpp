@@ -564,4 +564,44 @@ inline std::vector<int> fluid_tiles(const uint8_t *mask, int nx, int ny, int til
     return out;
 }
 
+// Launches of a few rounds of resident blocks end on a partial round; there
+// the tiles next to a wall (whose density frame, and with the improved
+// scheme Eq. 7, make them the slowest) go first in each XCD's band of the
+// list (xcd_tile), so that the last round holds bulk tiles only.
+// Configuration 3 (1,581 tiles of 64 x 8, 1.5 rounds): 23.8 -> 22.4 us per
+// step.  Longer lists keep the grouped walk, whose L2 locality matters more
+// there than the tail.
+constexpr size_t WALL_FIRST_MAX_TILES = 8192;
+inline void wall_tiles_first(std::vector<int> &tiles, const uint8_t *mask, int nx, int ny, int tiles_x, int tiles_y,
+                             int tg, int ty) {
+    const int n = (int)tiles.size();
+    if (n == 0 || (size_t)n > WALL_FIRST_MAX_TILES) return;
+    std::vector<char> wall(n, 0);
+    for (int j = 0; j < n; ++j) {
+        int tx, tyy;
+        tile_coords(tiles[j], tiles_x, tiles_y, tg, tx, tyy);
+        const int x0 = std::max(tx * TX - 1, 0), x1 = std::min(tx * TX + TX + 1, nx);
+        const int y0 = std::max(tyy * ty - 1, 0), y1 = std::min(tyy * ty + ty + 1, ny);
+        for (int y = y0; y < y1 && !wall[j]; ++y)
+            for (int x = x0; x < x1; ++x)
+                if (mask[(size_t)y * nx + x]) {
+                    wall[j] = 1;
+                    break;
+                }
+    }
+    // the bands of xcd_tile: the first n % 8 hold n / 8 + 1 tiles, the others n / 8
+    const int q = n >> 3, r = n & 7;
+    std::vector<int> out;
+    out.reserve(n);
+    for (int x = 0, start = 0; x < 8; ++x) {
+        const int len = q + (x < r ? 1 : 0);
+        for (int j = start; j < start + len; ++j)
+            if (wall[j]) out.push_back(tiles[j]);
+        for (int j = start; j < start + len; ++j)
+            if (!wall[j]) out.push_back(tiles[j]);
+        start += len;
+    }
+    tiles.swap(out);
+}
+
 }  // namespace mclbm

@@ -178,6 +178,7 @@ int lbm_create(const lbm_params *p, const uint8_t *mask, const double *rhoA0, co
         // a step launches only the tiles that hold fluid, so that the blocks
         // of every XCD's band carry an equal share of the work
         std::vector<int> fl = fluid_tiles(mask, p->nx, p->ny, h->I.tiles_x, h->I.tiles_y, h->I.tg, h->ty);
+        wall_tiles_first(fl, mask, p->nx, p->ny, h->I.tiles_x, h->I.tiles_y, h->I.tg, h->ty);
         for (int &t : fl) {  // the list holds packed tile coordinates
             int tx, ty;
             tile_coords(t, h->I.tiles_x, h->I.tiles_y, h->I.tg, tx, ty);
