@@ -133,7 +133,9 @@ void lbm_params_default(lbm_params *p);
  * Section 2).  rhoA0, rhoB0: nx*ny initial densities (read on fluid nodes;
  * each >= 0 and finite, their sum > 0).  The initial populations are the rest
  * equilibrium w_i rho_0.  stream: a hipStream_t or NULL.  On success *out
- * owns device memory until lbm_destroy.  Errors: LBM_EINVAL (sizes, tau,
+ * owns device memory until lbm_destroy.  Errors: LBM_EINVAL (sizes -- a
+ * population buffer must stay below 4 GiB, 72 B per node in FP32 and 40 B in
+ * FP16 for two components, and rows at most about 233,000 nodes wide -- tau,
  * enum values, fluid on a non-periodic border, bad densities, graph_steps and
  * diag_every that do not divide one another), LBM_ENOMEM, LBM_EDEVICE.
  * Synchronises the stream before returning. */
