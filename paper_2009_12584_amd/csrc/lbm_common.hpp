@@ -51,11 +51,9 @@ inline int lanes_of(const lbm_params &p) { return p.lanes == 2 && p.model == LBM
 inline size_t store_bytes(int storage) { return storage == LBM_STORE_F16 ? 2 : 4; }
 // populations stored per node: 9 directions of both components, or of one
 inline int pops_per_node(const lbm_params &p) { return p.model == LBM_MODEL_SC1 ? 9 : 18; }
-// bytes of one population buffer: nine planes per component; with FP16
-// storage the rest population has an FP32 plane of its own after them
+// bytes of one population buffer: 64-node row segments of 9 direction slots
+// (FP32) or 10 (FP16: slots 0 and 9 hold the FP32 rest populations)
 inline size_t pop_buffer_bytes(const lbm_params &p) {
-    // 64-node row segments of 9 direction slots (FP32) or 10 (FP16: the two
-    // extra 4-byte halves of the slot pair hold the FP32 rest populations)
     const size_t np = (size_t)p.ny * pitch_of(p.nx), comps = (size_t)pops_per_node(p) / 9;
     return comps * np * store_bytes(p.storage) * (p.storage == LBM_STORE_F16 ? 10 : 9);
 }
@@ -240,7 +238,7 @@ inline int make_graph_plan(int graph_steps, int diag_every, GraphPlan &g) {
 
 // Stair classification (Fig. 1A caption; Sections 3.1, 3.2) and the node
 // words: neighbour solid bits, solid, interface solid.  nbr and cls are the
-// ABI outputs (nx * ny); word0 has the row pitch of the population planes.
+// ABI outputs (nx * ny); word0 has the padded row pitch (a multiple of 64).
 static __global__ void k_classify(const uint8_t *__restrict__ mask, int nx, int ny, uint32_t periodic, int pitch,
                                   uint8_t *__restrict__ nbr, uint8_t *__restrict__ cls, uint16_t *__restrict__ word0) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -372,7 +370,7 @@ __global__ void k_init(Inst I, const double *__restrict__ rA, const double *__re
     }
 }
 
-// The same initial buffer for the single-component model (one plane set).
+// The same initial buffer for the single-component model (one population set).
 template <typename S>
 __global__ void k_init_sc1(Inst I, const double *__restrict__ rA, double rref, int which) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

@@ -1,8 +1,8 @@
 // Device side of the two-component pseudopotential LBM with wetting walls
 // (arXiv:2009.12584, Section 2) for gfx950.
 //
-// One workgroup of 256 threads (4 wavefronts) owns a tile of 64 x TY lattice
-// nodes and performs one whole time step for it:
+// One workgroup (one thread per node for tiles of up to 8 rows) owns a tile
+// of 64 x TY lattice nodes and performs one whole time step for it:
 //   phase 1  pull streaming with half-way bounce-back for the owned nodes
 //            (populations kept in registers) and for a ring of halo nodes
 //            (densities only); densities rho^A, rho^B into LDS  (Eqs. 1, 3)
