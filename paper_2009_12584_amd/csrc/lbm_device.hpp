@@ -125,11 +125,16 @@ __device__ __forceinline__ CollK coll_consts(float omega, float guo, float sc) {
 __device__ __forceinline__ float coll_eq(float cu, float m15uu) { return fmaf(cu, fmaf(4.5f, cu, 3.f), m15uu); }
 __device__ __forceinline__ float coll_t(float cu) { return fmaf(9.f, cu, 3.f); }
 // One component: d its incoming deviation, cF = c_i.F, uF3 = 3 u.F.
-__device__ __forceinline__ float coll_dir(int i, float d, float dr, float rho, float eq, float t, float cF, float uF3,
+// coll_dir is (1 - omega) d + coll_rhs, the last multiply-add fused.
+__device__ __forceinline__ float coll_rhs(int i, float dr, float rho, float eq, float t, float cF, float uF3,
                                           const CollK &k) {
     const int a = i < 5 ? 0 : 1;
     const float src = k.wg[a] * fmaf(cF, t, -uF3);
-    return fmaf(k.omc, d, fmaf(k.wo[a], fmaf(rho, eq, dr), src));
+    return fmaf(k.wo[a], fmaf(rho, eq, dr), src);
+}
+__device__ __forceinline__ float coll_dir(int i, float d, float dr, float rho, float eq, float t, float cF, float uF3,
+                                          const CollK &k) {
+    return fmaf(k.omc, d, coll_rhs(i, dr, rho, eq, t, cF, uF3, k));
 }
 
 // FP16 deviations are stored multiplied by 2^10, which keeps the smallest
@@ -246,16 +251,36 @@ __device__ __forceinline__ double dsum9(const float d[9]) {
 // is its rounding.  Summed in FP32 in direction order by every step kernel.
 __device__ __forceinline__ float remainder_term(float d, float q) { return d - q; }
 
-// The same two terms for an FP16-stored pair (A in the low half, B in the
-// high half of the 32-bit word): d - q with q read as FP16 straight from its
-// half by one mixed-precision multiply-add, q (-1) + d, exact product and one
-// rounding, so the result is bit for bit that of converting q and
-// subtracting, without the two conversions.  Register arithmetic only.
-__device__ __forceinline__ float2 remainder_terms_f16(float dA, float dB, uint32_t q) {
-    float a, b;
-    asm("v_fma_mix_f32 %0, %1, -1.0, %2 op_sel_hi:[1,0,0]" : "=v"(a) : "v"(q), "v"(dA));
-    asm("v_fma_mix_f32 %0, %1, -1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "=v"(b) : "v"(q), "v"(dB));
-    return make_float2(a, b);
+// Mixed-precision forms of an add, a subtract and a multiply-add whose FP16
+// operands are read straight from the low (HI = false) or high half of a
+// 32-bit register holding a pair (component A low, B high): one
+// v_fma_mix_f32, exact product and one FP32 rounding, so each is bit for bit
+// the FP32 operation on the converted values, without the conversions.
+// Register arithmetic only.
+template <bool HI> __device__ __forceinline__ float mix_add(uint32_t h, float s) {  // h + s
+    float r;
+    if constexpr (HI)
+        asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "=v"(r) : "v"(h), "v"(s));
+    else
+        asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel_hi:[1,0,0]" : "=v"(r) : "v"(h), "v"(s));
+    return r;
+}
+template <bool HI> __device__ __forceinline__ float mix_sub(uint32_t a, uint32_t b) {  // a - b
+    float r;
+    if constexpr (HI)
+        asm("v_fma_mix_f32 %0, %1, -1.0, %2 op_sel:[1,0,1] op_sel_hi:[1,0,1]" : "=v"(r) : "v"(b), "v"(a));
+    else
+        asm("v_fma_mix_f32 %0, %1, -1.0, %2 op_sel_hi:[1,0,1]" : "=v"(r) : "v"(b), "v"(a));
+    return r;
+}
+// The pair (k h_A + x_A, k h_B + x_B), each multiply-add rounded to FP32
+// and then to FP16 (round to nearest even), as one word: the FP16 results of
+// mixed-precision multiply-adds written to the low and the high half.
+__device__ __forceinline__ uint32_t mix_fma_pair_f16(float k, uint32_t h, float xa, float xb) {
+    uint32_t q;
+    asm("v_fma_mixlo_f16 %0, %1, %2, %3 op_sel_hi:[0,1,0]" : "=v"(q) : "v"(k), "v"(h), "v"(xa));
+    asm("v_fma_mixhi_f16 %0, %1, %2, %3 op_sel:[0,1,0] op_sel_hi:[0,1,0]" : "+v"(q) : "v"(k), "v"(h), "v"(xb));
+    return q;
 }
 
 // FP64 reduction targets of one simulation.
@@ -407,6 +432,107 @@ __device__ __forceinline__ void pull9(const typename Store<S>::P *__restrict__ b
     }
 }
 
+// Deviation sums of both components at a fluid node, storage units: fsum9 of
+// what pull9 gives, in the same order.  With FP16 storage each moving
+// population is added straight from its half of the loaded word, so a node
+// whose populations are needed only for its density skips the 16
+// conversions.
+template <typename S>
+__device__ __forceinline__ void pull_sums(const typename Store<S>::P *__restrict__ base, uint32_t pb, const Around &a,
+                                          uint32_t w, float &sA, float &sB) {
+    if constexpr (sizeof(S) == 4) {
+        float dA[9], dB[9];
+        pull9<S>(base, pb, a, w, dA, dB);
+        sA = fsum9(dA);
+        sB = fsum9(dB);
+    } else {
+        const uint32_t own = a.row[1] + a.col[1];
+        const float2 r = ld_rest<S>(base, pb, own);
+        uint32_t h[9];
+#pragma unroll
+        for (int i = 1; i < 9; ++i) h[i] = __builtin_bit_cast(uint32_t, *at(base, pull_off(i, pb, a, own, w)));
+        float s = 0.f, t = 0.f;
+        s += r.x;
+        t += r.y;
+#pragma unroll
+        for (int i = 1; i < 9; ++i) {
+            s = mix_add<false>(h[i], s);
+            t = mix_add<true>(h[i], t);
+        }
+        sA = s;
+        sB = t;
+    }
+}
+
+// Operations of the step on a fluid node's incoming populations of both
+// components, as pulled, storage units, held in float d[2][9].  FP32
+// storage keeps the values: d[c][i] is direction i of component c.  FP16
+// storage keeps the FP32 rest populations in d[c][0] and, in d[0][i] for
+// i = 1..8, the loaded word of direction i itself (A in its low half, B in
+// its high half; d[1][i] is unused): every sum, difference and multiply-add
+// reads the halves directly (mix_add, mix_sub, mix_fma_pair_f16), bit for
+// bit the FP32 arithmetic on the converted values, without converting.
+template <typename S> struct Incoming;
+template <> struct Incoming<float> {
+    using D = float[2][9];
+    static __device__ __forceinline__ void pull(const float2 *__restrict__ base, uint32_t pb, const Around &a,
+                                                uint32_t w, D &d) {
+        pull9<float>(base, pb, a, w, d[0], d[1]);
+    }
+    static __device__ __forceinline__ float sum(const D &d, int c) { return fsum9(d[c]); }
+    static __device__ __forceinline__ double dsum(const D &d, int c) { return dsum9(d[c]); }
+    // d_i - d_j
+    static __device__ __forceinline__ float diff(const D &d, int c, int i, int j) { return d[c][i] - d[c][j]; }
+    // the stored pair (k d_i + x_A, k d_i + x_B) of direction i
+    static __device__ __forceinline__ float2 collide(const D &d, int i, float k, float xa, float xb) {
+        return Store<float>::enc2(fmaf(k, d[0][i], xa), fmaf(k, d[1][i], xb));
+    }
+    // the remainder terms d_i - q_i of both components (remainder_term)
+    static __device__ __forceinline__ float2 remainder(const D &d, int i, float2 q) {
+        return make_float2(remainder_term(d[0][i], q.x), remainder_term(d[1][i], q.y));
+    }
+};
+template <> struct Incoming<__half> {
+    using D = float[2][9];
+    static __device__ __forceinline__ uint32_t word(const D &d, int i) { return __builtin_bit_cast(uint32_t, d[0][i]); }
+    static __device__ __forceinline__ void pull(const __half2 *__restrict__ base, uint32_t pb, const Around &a,
+                                                uint32_t w, D &d) {
+        const uint32_t own = a.row[1] + a.col[1];
+        const float2 v = ld_rest<__half>(base, pb, own);
+        d[0][0] = v.x;
+        d[1][0] = v.y;
+#pragma unroll
+        for (int i = 1; i < 9; ++i) d[0][i] = __builtin_bit_cast(float, *at(base, pull_off(i, pb, a, own, w)));
+    }
+    static __device__ __forceinline__ float sum(const D &d, int c) {
+        float s = 0.f;
+        s += d[c][0];
+#pragma unroll
+        for (int i = 1; i < 9; ++i) s = c ? mix_add<true>(word(d, i), s) : mix_add<false>(word(d, i), s);
+        return s;
+    }
+    static __device__ __forceinline__ double dsum(const D &d, int c) {
+        double s = 0.0;
+        s += (double)d[c][0];
+#pragma unroll
+        for (int i = 1; i < 9; ++i) {
+            const float2 v = __half22float2(__builtin_bit_cast(__half2, word(d, i)));
+            s += (double)(c ? v.y : v.x);
+        }
+        return s;
+    }
+    static __device__ __forceinline__ float diff(const D &d, int c, int i, int j) {
+        return c ? mix_sub<true>(word(d, i), word(d, j)) : mix_sub<false>(word(d, i), word(d, j));
+    }
+    static __device__ __forceinline__ __half2 collide(const D &d, int i, float k, float xa, float xb) {
+        return __builtin_bit_cast(__half2, mix_fma_pair_f16(k, word(d, i), xa, xb));
+    }
+    static __device__ __forceinline__ float2 remainder(const D &d, int i, __half2 q) {
+        const uint32_t qw = __builtin_bit_cast(uint32_t, q);
+        return make_float2(mix_sub<false>(word(d, i), qw), mix_sub<true>(word(d, i), qw));
+    }
+};
+
 struct DiagAcc {
     double mA = 0, mB = 0, px = 0, py = 0;
     float u2max = 0.f;
@@ -536,10 +662,10 @@ __device__ __forceinline__ void frame_pass(const Inst &I, Smem<TY> &sm, const ty
         const bool want = !(w & NW_SOLID) && (HF == 1 || ring <= 1 || (w & NW_NEAR));
         if (want) {
             const Around a = around<S>(I, gx, gy, edge);
-            float dA[9], dB[9];
-            pull9<S>(fin, pb, a, w, dA, dB);
-            ra = rref[0] + fsum9(dA) * (1.f / Store<S>::SC);
-            rb = rref[1] + fsum9(dB) * (1.f / Store<S>::SC);
+            float sA, sB;
+            pull_sums<S>(fin, pb, a, w, sA, sB);
+            ra = rref[0] + sA * (1.f / Store<S>::SC);
+            rb = rref[1] + sB * (1.f / Store<S>::SC);
         }
         sm.rho[0][rho_idx<TY>(hx, hy)] = ra;
         sm.rho[1][rho_idx<TY>(hx, hy)] = rb;
@@ -577,8 +703,8 @@ __device__ __forceinline__ void process_tile(const Inst &I, int tile_x, int tile
     // issued its own, so the loads form two dependent latencies, not four.
     const int lx = tid & (TX - 1);
     const int lr = tid >> 6;
-    float d[RPT][2][9];
-    float sd[RPT][2];   // incoming deviation sums, storage units
+    float d[RPT][2][9];  // incoming populations (Incoming<S>)
+    float sd[RPT][2];    // incoming deviation sums, storage units
     uint32_t w[RPT];    // node words
     uint32_t own[RPT];  // byte offset of the owned node (its direction-0 element)
     bool owned[RPT];
@@ -600,7 +726,7 @@ __device__ __forceinline__ void process_tile(const Inst &I, int tile_x, int tile
             (uint8_t)(((w[r] & NW_SOLID) ? LF_SOLID : 0) | ((w[r] & NW_IFACE) ? LF_IFACE : 0));
         if (!(w[r] & NW_SOLID)) {
             const Around a = around<S>(I, gx, gy, edge);
-            pull9<S>(fin, pb, a, w[r], d[r][0], d[r][1]);
+            Incoming<S>::pull(fin, pb, a, w[r], d[r]);
         } else {
 #pragma unroll
             for (int i = 0; i < 9; ++i) d[r][0][i] = d[r][1][i] = 0.f;
@@ -634,8 +760,8 @@ __device__ __forceinline__ void process_tile(const Inst &I, int tile_x, int tile
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
         const int ly = lr + RPP * r;
-        sd[r][0] = fsum9(d[r][0]);
-        sd[r][1] = fsum9(d[r][1]);
+        sd[r][0] = Incoming<S>::sum(d[r], 0);
+        sd[r][1] = Incoming<S>::sum(d[r], 1);
         const bool fl = !(w[r] & NW_SOLID);
         sm.rho[0][rho_idx<TY>(lx, ly)] = fl ? rref[0] + sd[r][0] * (1.f / SC) : 0.f;
         sm.rho[1][rho_idx<TY>(lx, ly)] = fl ? rref[1] + sd[r][1] * (1.f / SC) : 0.f;
@@ -769,8 +895,9 @@ __device__ __forceinline__ void process_tile(const Inst &I, int tile_x, int tile
         float jx = 0.f, jy = 0.f;
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
-            jx += (d[r][c][1] - d[r][c][3]) + (d[r][c][5] - d[r][c][6]) + (d[r][c][8] - d[r][c][7]);
-            jy += (d[r][c][2] - d[r][c][4]) + (d[r][c][5] - d[r][c][8]) + (d[r][c][6] - d[r][c][7]);
+            using In = Incoming<S>;
+            jx += (In::diff(d[r], c, 1, 3) + In::diff(d[r], c, 5, 6)) + In::diff(d[r], c, 8, 7);
+            jy += (In::diff(d[r], c, 2, 4) + In::diff(d[r], c, 5, 8)) + In::diff(d[r], c, 6, 7);
         }
         jx *= 1.f / SC;
         jy *= 1.f / SC;
@@ -781,8 +908,8 @@ __device__ __forceinline__ void process_tile(const Inst &I, int tile_x, int tile
 
         if (DIAG) {
             // total-mass reduction in FP64: reference plus the exact deviation sum
-            acc.mA += (double)rref[0] + dsum9(d[r][0]) * (double)(1.f / SC);
-            acc.mB += (double)rref[1] + dsum9(d[r][1]) * (double)(1.f / SC);
+            acc.mA += (double)rref[0] + Incoming<S>::dsum(d[r], 0) * (double)(1.f / SC);
+            acc.mB += (double)rref[1] + Incoming<S>::dsum(d[r], 1) * (double)(1.f / SC);
             acc.px += (double)rt * (double)ux;
             acc.py += (double)rt * (double)uy;
             acc.u2max = fmaxf(acc.u2max, ux * ux + uy * uy);
@@ -821,15 +948,10 @@ __device__ __forceinline__ void process_tile(const Inst &I, int tile_x, int tile
             const float eq = coll_eq(cu, m15uu), t = coll_t(cu);
             const float cFA = cdot(i, FAx, FAy);
             const float cFB = cdot(i, FBx, FBy);
-            const auto q = Store<S>::enc2(coll_dir(i, d[r][0][i], drA, ra, eq, t, cFA, uFA3, ck),
-                                          coll_dir(i, d[r][1][i], drB, rb, eq, t, cFB, uFB3, ck));
-            float2 rt;
-            if constexpr (sizeof(S) == 2) {
-                rt = remainder_terms_f16(d[r][0][i], d[r][1][i], __builtin_bit_cast(uint32_t, q));
-            } else {
-                const float2 qd = Store<S>::dec2(q);
-                rt = make_float2(remainder_term(d[r][0][i], qd.x), remainder_term(d[r][1][i], qd.y));
-            }
+            // coll_dir of both components, rounded to storage
+            const auto q = Incoming<S>::collide(d[r], i, ck.omc, coll_rhs(i, drA, ra, eq, t, cFA, uFA3, ck),
+                                                coll_rhs(i, drB, rb, eq, t, cFB, uFB3, ck));
+            const float2 rt = Incoming<S>::remainder(d[r], i, q);
             // the sums start from the first term (0 + x would cost an add)
             eA = i == 1 ? rt.x : eA + rt.x;
             eB = i == 1 ? rt.y : eB + rt.y;

@@ -243,6 +243,27 @@ def test_tile_shapes_and_lanes_bit_identical_and_runs_repeat(gpu, ora, bc):
             assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("bc", [W.MC, W.LLKC, W.IMPROVED])
+def test_fp16_tile_shapes_and_lanes_bit_identical(gpu, ora, bc):
+    """FP16 storage, every tile height, one or two lanes per node: the same
+    bits.  The one-lane step reads the stored FP16 halves straight into
+    mixed-precision adds, subtracts and multiply-adds; the two-lane step
+    converts them to FP32 first.  Equal bits pin the mixed forms to the plain
+    FP32 arithmetic."""
+    c = W.plane_drop(300, 150, 33.0, 20.0, bc, G=3.0, chi=(1.1, 0.9))
+    mask = gpu_mask(gpu, c)
+    res = []
+    for ty, lanes in ((8, 1), (4, 1), (16, 1), (32, 1), (8, 2), (4, 2), (32, 2)):
+        say("case: FP16, tile rows %d lanes %d" % (ty, lanes))
+        sim = gpu.Simulation(mask, c.rhoA0, c.rhoB0, storage="f16", tile_y=ty, lanes=lanes, **c.params())
+        sim.step(150)
+        res.append(tuple(sim.fields()) + (sim.get_state()[0],))
+        sim.close()
+    for r in res[1:]:
+        for a, b in zip(res[0], r):
+            assert np.array_equal(a, b)
+
+
 def test_graph_replay_matches_plain_launches(gpu, ora):
     c = W.plane_drop(256, 128, 30.0, 20.0, W.IMPROVED, G=3.0)
     mask = gpu_mask(gpu, c)
