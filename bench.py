@@ -329,11 +329,16 @@ def window_errors(ora, c, mask, fields, windows, size=240, k=10):
 
 
 def large_row(M, torch, ora, args, c, mask, storage, profile, windows, sc1=False):
+    from paper_2009_12584_amd.autotune import default_shape
+
     fluid, nodes = int((mask == 0).sum()), c.nx * c.ny
     steps = args.large_steps
     glen = graph_len(args, 20)
     stream = torch.cuda.Stream()
-    sim = M.Simulation(mask, c.rhoA0, c.rhoB0 if not sc1 else None, stream=stream, storage=storage, tile_y=8,
+    # the library's default tile for the storage: 64 x 8, or 64 x 16 for the
+    # two-component step with FP16 storage
+    ty = default_shape(storage, 1 if sc1 else 0)[0]
+    sim = M.Simulation(mask, c.rhoA0, c.rhoB0 if not sc1 else None, stream=stream, storage=storage, tile_y=ty,
                        lanes=1, graph_steps=glen, diag_every=glen if glen else 20, **c.params())
     sim.step(10)
     er, eu = window_errors(ora, c, mask, sim.fields(), windows) if ora is not None else (float("nan"),) * 2
@@ -344,7 +349,8 @@ def large_row(M, torch, ora, args, c, mask, storage, profile, windows, sc1=False
     ms = t.ms / steps
     row = {"ms_per_step": round(ms, 4), "fluid_mlups": round(fluid * steps / (t.ms * 1e-3) / 1e6, 1),
            "fluid_nodes": fluid,
-           "roofline": roofline(kernel_name(storage, 8, 1, c.bc if c.bc < 3 else 0, c.nx, c.ny, sc1), profile, fluid,
+           "tile_y": ty,
+           "roofline": roofline(kernel_name(storage, ty, 1, c.bc if c.bc < 3 else 0, c.nx, c.ny, sc1), profile, fluid,
                                 nodes, storage, ms, sc1)}
     if ora is not None:
         row["error_vs_oracle"] = err_entry(er, eu, storage, at_step=10, nodes="3 windows of 240 x 240")
@@ -360,7 +366,7 @@ def rows_5600x4000(M, torch, W, args, probe):
         oracle.build()
     pick = set(args.large_only.split(",")) if args.large_only else None
     out = {"workload": "5600x4000, the paper's largest grid (Section 4): 3.2 GB of FP32 populations per step, "
-                       "out of every cache; 64 x 8 tiles, one lane per node"}
+                       "out of every cache; 64 x 8 tiles (64 x 16 with FP16 storage), one lane per node"}
     mix = W.roofline_case()
     seams = [(5600 - 120, 4000 - 120), (2800, 1900), (5500, 700)]
     for storage in ("f32", "f16"):
@@ -440,7 +446,7 @@ def config2_row(M, torch, W, args):
 def batched_rows(M, torch, W, args):
     import numpy as np
     import oracle
-    from paper_2009_12584_amd.autotune import launch_config_for_batch
+    from paper_2009_12584_amd.autotune import default_shape, launch_config_for_batch
 
     if not args.no_oracle:
         oracle.build()
@@ -478,7 +484,7 @@ def batched_rows(M, torch, W, args):
         if args.fixed_shapes or args.graph_steps == 0:
             # the autotuner's default shape: counter runs name one kernel per
             # storage and capture no autotuner graphs
-            ty, lanes = 8, 1
+            ty, lanes = default_shape(storage)
         else:
             cfg = launch_config_for_batch(items, storage=storage, stream=stream)
             ty, lanes = cfg["tile_y"], cfg["lanes"]

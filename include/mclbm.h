@@ -104,7 +104,8 @@ typedef struct {
                             multiple of G and at least G steps remain, plain launches
                             otherwise; G and diag_every must divide one another;
                             0 = plain launches only */
-    int32_t tile_y;      /* rows per tile: 0 = default (8), else 4, 8, 16 or 32 (512-thread workgroups) */
+    int32_t tile_y;      /* rows per 64-wide tile: 4, 8, 16 or 32; 0 = the default, 16 for the
+                            two-component model with FP16 storage, else 8 */
     int32_t model;       /* lbm_model */
     double psi_rho0;     /* single-component model: the density scale of psi */
     int32_t lanes;       /* two-component step: 0 or 1 = one lane per node, 2 = one lane per
@@ -310,7 +311,9 @@ int lbm_pool_create(size_t hbm_budget, int32_t max_slots, int32_t storage, int32
 /* Bytes of device memory one solve of these parameters occupies. */
 size_t lbm_pool_footprint(const lbm_params *p);
 /* Admits one solve of nsteps steps.  Returns LBM_EAGAIN when neither a slot
- * nor enough budget is free; *slot receives the slot id otherwise. */
+ * nor enough budget is free; *slot receives the slot id otherwise.  The pool
+ * tiles every slot with the default tile rows of its storage: p->tile_y must
+ * be 0 or those rows (LBM_EINVAL otherwise). */
 int lbm_pool_admit(lbm_pool *pool, const lbm_params *p, const uint8_t *mask, const double *rhoA0,
                    const double *rhoB0, int64_t nsteps, int32_t *slot);
 /* lbm_pool_admit for callers that cannot allocate device memory (code under

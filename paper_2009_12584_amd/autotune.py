@@ -3,10 +3,14 @@
 A tile is 64 nodes wide (one wavefront row) and TY rows tall, TY in
 {4, 8, 16, 32}; the two-component step runs with one lane per node or one
 lane per node and component (bit-identical results).  The 64 x 8 tile with
-one lane per node (one thread per node) is the default: on MI355X it is the
-fastest or within 2% of the fastest on every workload measured, from the
-latency-bound 512 x 256 plane to the 5600 x 4000 grid; smaller tiles and two
-lanes win only where few tiles cover the 256 compute units.  The tuner times
+one lane per node (one thread per node) is the default with FP32 storage: on
+MI355X it is the fastest or within 2% of the fastest on every FP32 workload
+measured, from the latency-bound 512 x 256 plane to the 5600 x 4000 grid;
+smaller tiles and two lanes win only where few tiles cover the 256 compute
+units.  With FP16 storage the 64 x 16 tile (four nodes per thread) is the
+default: a node moves half the bytes, and four per thread keep enough of them
+in flight (2.6% to 7% faster than 64 x 8 on the 5600 x 4000 grids and the
+64-instance batch).  The library applies the same defaults.  The tuner times
 a few steps of the caller's own problem for each candidate on the device and
 keeps the default unless another shape is at least 2% faster (shapes within
 timing noise of each other would otherwise flip from run to run), cached per
@@ -22,10 +26,15 @@ import time
 
 from .sim import Batch, Simulation
 
-# (tile rows, lanes per node); the first is the default
+# (tile rows, lanes per node)
 CANDIDATES = ((8, 1), (4, 1), (16, 1), (32, 1), (4, 2), (8, 2), (16, 2))
 MARGIN = 0.02  # another shape must be this much faster than the default
-_CACHE_PATH = os.path.join(os.path.expanduser("~"), ".cache", "mclbm", "autotune-v4.json")
+
+
+def default_shape(storage="f32", model=0):
+    """The library's own choice when tile_y and lanes are left at 0."""
+    return (16, 1) if storage == "f16" and model == 0 else (8, 1)
+_CACHE_PATH = os.path.join(os.path.expanduser("~"), ".cache", "mclbm", "autotune-v5.json")
 _cache = None
 
 
@@ -72,10 +81,10 @@ def _time(step, sync, steps, reps=3):
     return best
 
 
-def pick(times):
-    """The default shape unless another is at least MARGIN faster; then the
-    fastest."""
-    default = CANDIDATES[0]
+def pick(times, storage="f32", model=0):
+    """The default shape of the storage and model unless another is at least
+    MARGIN faster; then the fastest."""
+    default = default_shape(storage, model)
     fastest = min(times, key=times.get)
     if default in times and times[fastest] > (1.0 - MARGIN) * times[default]:
         return default
@@ -103,7 +112,7 @@ def launch_config_for(mask, rhoA0, rhoB0, *, storage="f32", steps=None, stream=N
                          graph_steps=graph, **params)
         times[(ty, lanes)] = _time(sim.step, torch.cuda.synchronize, steps)
         sim.close()
-    best = pick(times)
+    best = pick(times, storage, params.get("model", 0))
     cache[key] = dict(tile_y=best[0], lanes=best[1])
     _save()
     return dict(cache[key])
@@ -125,5 +134,5 @@ def launch_config_for_batch(items, *, storage="f32", steps=50, stream=None):
         b = Batch(items, storage=storage, tile_y=ty, lanes=lanes, stream=stream, graph_steps=steps)
         times[(ty, lanes)] = _time(b.step, torch.cuda.synchronize, steps)
         b.close()
-    best = pick(times)
+    best = pick(times, storage, items[0][3].get("model", 0) if items else 0)
     return dict(tile_y=best[0], lanes=best[1])

@@ -785,6 +785,7 @@ int lbm_pool_create(size_t hbm_budget, int32_t max_slots, int32_t storage, int32
     *out = nullptr;
     lbm_pool *P = new lbm_pool();
     P->storage = storage;
+    P->ty = default_rows(storage, LBM_MODEL_TWO);
     P->max_slots = max_slots;
     P->diag_every = diag_every;
     P->slots.resize(max_slots);

@@ -45,7 +45,13 @@ inline void set_err(const char *fmt, ...) {
 }
 
 inline int pitch_of(int nx) { return (nx + 63) / 64 * 64; }
-inline int default_ty(const lbm_params &p) { return p.tile_y > 0 ? p.tile_y : 8; }
+// Tile rows when the caller leaves them to the library: 8, and 16 for the
+// two-component step with FP16 storage, whose nodes carry half the bytes: four
+// nodes per thread keep as many bytes in flight as one FP32 node's thread.
+inline int default_rows(int storage, int model) {
+    return storage == LBM_STORE_F16 && model == LBM_MODEL_TWO ? 16 : 8;
+}
+inline int default_ty(const lbm_params &p) { return p.tile_y > 0 ? p.tile_y : default_rows(p.storage, p.model); }
 // lanes per node of the two-component step: 1 (default) or 2 (lbm_pair.hpp)
 inline int lanes_of(const lbm_params &p) { return p.lanes == 2 && p.model == LBM_MODEL_TWO ? 2 : 1; }
 inline size_t store_bytes(int storage) { return storage == LBM_STORE_F16 ? 2 : 4; }
