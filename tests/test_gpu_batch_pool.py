@@ -154,6 +154,22 @@ def test_fp16_batch_and_pool_match_single_fp16(M):
     b.close()
 
 
+def test_fp16_pool_tiles_its_slots_at_the_fp16_default(M):
+    """An FP16 pool tiles every slot with 16 rows, the library's default for
+    the two-component step with FP16 storage: a request asking for 8 rows is
+    refused on the host before anything is allocated, one asking for 16 or
+    leaving the rows to the library is admitted."""
+    c = small_cases(1, seed=3)[0]
+    m = masks_of(M, [c])[0]
+    pool = M.Pool(2 * M.Pool.footprint(c.nx, c.ny, storage="f16") + 4096, 2, storage="f16")
+    with pytest.raises(M.LbmError) as e:
+        pool.admit(m, c.rhoA0, c.rhoB0, 10, tile_y=8, **c.params())
+    assert "16 rows" in str(e.value)
+    assert pool.admit(m, c.rhoA0, c.rhoB0, 10, tile_y=16, **c.params()) is not None
+    assert pool.admit(m, c.rhoA0, c.rhoB0, 10, **c.params()) is not None
+    pool.close()
+
+
 def test_pool_results_same_alone_and_in_the_mix(M, ora):
     """Continuous batching: requests join while others run, each stops at its own
     step count, and each result equals the same solve run alone (bit for bit)
