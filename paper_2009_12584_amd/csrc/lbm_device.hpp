@@ -141,7 +141,7 @@ __device__ __forceinline__ float coll_dir(int i, float d, float dr, float rho, f
 // populations of a 0.03 minority phase clear of the subnormal range.  The
 // kernels work in storage units (deviation x SC): the power-of-two scale is
 // folded into the equilibrium and source weights and into the density and
-// momentum sums, so loads and stores are bare conversions.
+// momentum sums, so loads and stores need no scaling.
 //
 // The rest population is the remainder of the node's incoming mass after the
 // 8 moving populations are rounded to storage (remainder_term below).  With
@@ -432,38 +432,6 @@ __device__ __forceinline__ void pull9(const typename Store<S>::P *__restrict__ b
     }
 }
 
-// Deviation sums of both components at a fluid node, storage units: fsum9 of
-// what pull9 gives, in the same order.  With FP16 storage each moving
-// population is added straight from its half of the loaded word, so a node
-// whose populations are needed only for its density skips the 16
-// conversions.
-template <typename S>
-__device__ __forceinline__ void pull_sums(const typename Store<S>::P *__restrict__ base, uint32_t pb, const Around &a,
-                                          uint32_t w, float &sA, float &sB) {
-    if constexpr (sizeof(S) == 4) {
-        float dA[9], dB[9];
-        pull9<S>(base, pb, a, w, dA, dB);
-        sA = fsum9(dA);
-        sB = fsum9(dB);
-    } else {
-        const uint32_t own = a.row[1] + a.col[1];
-        const float2 r = ld_rest<S>(base, pb, own);
-        uint32_t h[9];
-#pragma unroll
-        for (int i = 1; i < 9; ++i) h[i] = __builtin_bit_cast(uint32_t, *at(base, pull_off(i, pb, a, own, w)));
-        float s = 0.f, t = 0.f;
-        s += r.x;
-        t += r.y;
-#pragma unroll
-        for (int i = 1; i < 9; ++i) {
-            s = mix_add<false>(h[i], s);
-            t = mix_add<true>(h[i], t);
-        }
-        sA = s;
-        sB = t;
-    }
-}
-
 // Operations of the step on a fluid node's incoming populations of both
 // components, as pulled, storage units, held in float d[2][9].  FP32
 // storage keeps the values: d[c][i] is direction i of component c.  FP16
@@ -662,10 +630,10 @@ __device__ __forceinline__ void frame_pass(const Inst &I, Smem<TY> &sm, const ty
         const bool want = !(w & NW_SOLID) && (HF == 1 || ring <= 1 || (w & NW_NEAR));
         if (want) {
             const Around a = around<S>(I, gx, gy, edge);
-            float sA, sB;
-            pull_sums<S>(fin, pb, a, w, sA, sB);
-            ra = rref[0] + sA * (1.f / Store<S>::SC);
-            rb = rref[1] + sB * (1.f / Store<S>::SC);
+            float d[2][9];
+            Incoming<S>::pull(fin, pb, a, w, d);
+            ra = rref[0] + Incoming<S>::sum(d, 0) * (1.f / Store<S>::SC);
+            rb = rref[1] + Incoming<S>::sum(d, 1) * (1.f / Store<S>::SC);
         }
         sm.rho[0][rho_idx<TY>(hx, hy)] = ra;
         sm.rho[1][rho_idx<TY>(hx, hy)] = rb;
