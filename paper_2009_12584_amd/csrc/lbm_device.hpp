@@ -124,17 +124,15 @@ __device__ __forceinline__ CollK coll_consts(float omega, float guo, float sc) {
 // Per direction, shared by both components: eq_i and 3 + 9 c_i.u.
 __device__ __forceinline__ float coll_eq(float cu, float m15uu) { return fmaf(cu, fmaf(4.5f, cu, 3.f), m15uu); }
 __device__ __forceinline__ float coll_t(float cu) { return fmaf(9.f, cu, 3.f); }
-// One component: d its incoming deviation, cF = c_i.F, uF3 = 3 u.F.
-// coll_dir is (1 - omega) d + coll_rhs, the last multiply-add fused.
+// One component and direction: the post-collision deviation is
+// (1 - omega) d + coll_rhs, d the incoming deviation, the last multiply-add
+// fused (Incoming<S>::collide, Comp<S>::collide, Store1<S>::collide);
+// dr = the density's deviation, cF = c_i.F, uF3 = 3 u.F.
 __device__ __forceinline__ float coll_rhs(int i, float dr, float rho, float eq, float t, float cF, float uF3,
                                           const CollK &k) {
     const int a = i < 5 ? 0 : 1;
     const float src = k.wg[a] * fmaf(cF, t, -uF3);
     return fmaf(k.wo[a], fmaf(rho, eq, dr), src);
-}
-__device__ __forceinline__ float coll_dir(int i, float d, float dr, float rho, float eq, float t, float cF, float uF3,
-                                          const CollK &k) {
-    return fmaf(k.omc, d, coll_rhs(i, dr, rho, eq, t, cF, uF3, k));
 }
 
 // FP16 deviations are stored multiplied by 2^10, which keeps the smallest
@@ -251,11 +249,11 @@ __device__ __forceinline__ double dsum9(const float d[9]) {
 // is its rounding.  Summed in FP32 in direction order by every step kernel.
 __device__ __forceinline__ float remainder_term(float d, float q) { return d - q; }
 
-// Mixed-precision forms of an add, a subtract and a multiply-add whose FP16
-// operands are read straight from the low (HI = false) or high half of a
-// 32-bit register holding a pair (component A low, B high): one
-// v_fma_mix_f32, exact product and one FP32 rounding, so each is bit for bit
-// the FP32 operation on the converted values, without the conversions.
+// Mixed-precision forms of an add and a subtract whose FP16 operands are
+// read straight from the low (HI = false) or high half of a 32-bit register
+// holding a pair (component A low, B high): one v_fma_mix_f32, exact product
+// and one FP32 rounding, so each is bit for bit the FP32 operation on the
+// converted values, without the conversions (FP16 subnormals included).
 // Register arithmetic only.
 template <bool HI> __device__ __forceinline__ float mix_add(uint32_t h, float s) {  // h + s
     float r;
@@ -273,9 +271,23 @@ template <bool HI> __device__ __forceinline__ float mix_sub(uint32_t a, uint32_t
         asm("v_fma_mix_f32 %0, %1, -1.0, %2 op_sel_hi:[1,0,1]" : "=v"(r) : "v"(b), "v"(a));
     return r;
 }
-// The pair (k h_A + x_A, k h_B + x_B), each multiply-add rounded to FP32
-// and then to FP16 (round to nearest even), as one word: the FP16 results of
-// mixed-precision multiply-adds written to the low and the high half.
+// k d + x with FP32 operands, rounded once, from its exact value, to the
+// nearest FP16 (ties to even): the single-rounding conversion of
+// mix_fma_pair_f16 for a value already in FP32.  The FP16 steps round every
+// stored population this way, explicitly, so that they agree bit for bit
+// whatever the compiler would fuse.  Register arithmetic only.
+__device__ __forceinline__ __half fma_to_f16(float k, float d, float x) {
+    uint32_t q;
+    asm("v_fma_mixlo_f16 %0, %1, %2, %3" : "=v"(q) : "v"(k), "v"(d), "v"(x));
+    return __builtin_bit_cast(__half, (uint16_t)q);
+}
+// The pair (k h_A + x_A, k h_B + x_B) as one FP16 word: mixed-precision
+// multiply-adds written to the low and the high half, each rounded once, from
+// its exact value, to the nearest FP16 (ties to even).  This is the form the
+// compiler itself selects for fmaf followed by a conversion to FP16.  It
+// differs from rounding to FP32 first only where that FP32 rounding lands on
+// an FP16 midpoint (about one value in 10^4 of random operands), and there
+// it gives the nearer FP16 value.
 __device__ __forceinline__ uint32_t mix_fma_pair_f16(float k, uint32_t h, float xa, float xb) {
     uint32_t q;
     asm("v_fma_mixlo_f16 %0, %1, %2, %3 op_sel_hi:[0,1,0]" : "=v"(q) : "v"(k), "v"(h), "v"(xa));
@@ -437,9 +449,10 @@ __device__ __forceinline__ void pull9(const typename Store<S>::P *__restrict__ b
 // storage keeps the values: d[c][i] is direction i of component c.  FP16
 // storage keeps the FP32 rest populations in d[c][0] and, in d[0][i] for
 // i = 1..8, the loaded word of direction i itself (A in its low half, B in
-// its high half; d[1][i] is unused): every sum, difference and multiply-add
-// reads the halves directly (mix_add, mix_sub, mix_fma_pair_f16), bit for
-// bit the FP32 arithmetic on the converted values, without converting.
+// its high half; d[1][i] is unused): every sum and difference reads the
+// halves directly (mix_add, mix_sub), bit for bit the FP32 arithmetic on the
+// converted values, and the collision's last multiply-add reads them in
+// mix_fma_pair_f16, which rounds straight to the stored FP16 value.
 template <typename S> struct Incoming;
 template <> struct Incoming<float> {
     using D = float[2][9];
@@ -643,8 +656,9 @@ __device__ __forceinline__ void frame_pass(const Inst &I, Smem<TY> &sm, const ty
 // One time step (MODE_STEP) or the fields at the current time (MODE_FIELDS)
 // for the tile (tile_x, tile_y) of instance I.  parity selects the buffer read.
 // No multiply-add contraction: the one-lane and two-lane steps evaluate the
-// same expressions in the same order and agree bit for bit, whatever the
-// compiler would fuse in each.
+// same expressions in the same order, and round FP16 stores by the same
+// explicit instruction, so they agree bit for bit whatever the compiler would
+// fuse in each.
 template <typename S, int TY, int BC, int MODE, bool DIAG, bool NT>
 __device__ __forceinline__ void process_tile(const Inst &I, int tile_x, int tile_y, int parity, Smem<TY> &sm,
                                              DiagAcc &acc, const Fields &fo) {
@@ -916,7 +930,7 @@ __device__ __forceinline__ void process_tile(const Inst &I, int tile_x, int tile
             const float eq = coll_eq(cu, m15uu), t = coll_t(cu);
             const float cFA = cdot(i, FAx, FAy);
             const float cFB = cdot(i, FBx, FBy);
-            // coll_dir of both components, rounded to storage
+            // the post-collision deviations of both components, rounded to storage
             const auto q = Incoming<S>::collide(d[r], i, ck.omc, coll_rhs(i, drA, ra, eq, t, cFA, uFA3, ck),
                                                 coll_rhs(i, drB, rb, eq, t, cFB, uFB3, ck));
             const float2 rt = Incoming<S>::remainder(d[r], i, q);

@@ -49,7 +49,8 @@ template <typename S> struct Comp;
 // slots 0 (A) and 9 (B) as floats for FP16 storage.
 template <> struct Comp<float> {
     static __device__ __forceinline__ float ld(const char *p) { return *(const float *)p; }
-    static __device__ __forceinline__ float enc(float v) { return v; }
+    // the stored population k d + x (k = 1 - omega, x = coll_rhs)
+    static __device__ __forceinline__ float collide(float k, float d, float x) { return fmaf(k, d, x); }
     static __device__ __forceinline__ float dec(float v) { return v; }
     static __device__ __forceinline__ void put(char *p, float v) { __builtin_nontemporal_store(v, (float *)p); }
     static __device__ __forceinline__ void put_plain(char *p, float v) { *(float *)p = v; }
@@ -58,7 +59,8 @@ template <> struct Comp<float> {
 };
 template <> struct Comp<__half> {
     static __device__ __forceinline__ float ld(const char *p) { return __half2float(*(const __half *)p); }
-    static __device__ __forceinline__ __half enc(float v) { return __float2half_rn(v); }
+    // rounded once to FP16, as the one-lane step rounds (fma_to_f16)
+    static __device__ __forceinline__ __half collide(float k, float d, float x) { return fma_to_f16(k, d, x); }
     static __device__ __forceinline__ float dec(__half v) { return __half2float(v); }
     static __device__ __forceinline__ void put(char *p, __half v) {
         __builtin_nontemporal_store(__builtin_bit_cast(uint16_t, v), (uint16_t *)p);
@@ -394,7 +396,7 @@ __device__ __forceinline__ void process_tile_ls(const Inst &I, int tile_x, int t
             const float cu = cdot(i, ux, uy);
             const float eq = coll_eq(cu, m15uu), t = coll_t(cu);
             const float cF = cdot(i, Fx, Fy);
-            const auto v = Comp<S>::enc(coll_dir(i, d[r][i], dr, rm, eq, t, cF, uF3, ck));
+            const auto v = Comp<S>::collide(ck.omc, d[r][i], coll_rhs(i, dr, rm, eq, t, cF, uF3, ck));
             e = i == 1 ? remainder_term(d[r][i], Comp<S>::dec(v)) : e + remainder_term(d[r][i], Comp<S>::dec(v));
             if constexpr (NT)
                 Comp<S>::put(fout + (own[r] + (uint32_t)i * pb + coff), v);

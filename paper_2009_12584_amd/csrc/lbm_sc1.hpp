@@ -28,6 +28,8 @@ template <> struct Store1<float> {
     static constexpr float SC = 1.f;
     static __device__ __forceinline__ float ld(const float *p) { return *p; }
     static __device__ __forceinline__ float enc(float a) { return a; }
+    // the stored population k d + x (k = 1 - omega, x = coll_rhs)
+    static __device__ __forceinline__ float collide(float k, float d, float x) { return fmaf(k, d, x); }
     static __device__ __forceinline__ float dec(float v) { return v; }
     static __device__ __forceinline__ void put(float *p, float v) { *p = v; }
     static __device__ __forceinline__ void putnt(float *p, float v) { __builtin_nontemporal_store(v, p); }
@@ -37,6 +39,8 @@ template <> struct Store1<__half> {
     static constexpr float SC = 1024.f;
     static __device__ __forceinline__ float ld(const __half *p) { return __half2float(*p); }
     static __device__ __forceinline__ __half enc(float a) { return __float2half_rn(a); }
+    // rounded once to FP16, as the two-component steps round (fma_to_f16)
+    static __device__ __forceinline__ __half collide(float k, float d, float x) { return fma_to_f16(k, d, x); }
     static __device__ __forceinline__ float dec(__half v) { return __half2float(v); }
     static __device__ __forceinline__ void put(__half *p, __half v) { *p = v; }
     static __device__ __forceinline__ void putnt(__half *p, __half v) {
@@ -238,7 +242,7 @@ __device__ __forceinline__ void process_tile_sc1(const Inst &I, int tile_x, int 
         for (int i = 1; i < 9; ++i) {
             const float cu = cdot(i, ux, uy);
             const float cF = cdot(i, Fx, Fy);
-            const P q = Store1<S>::enc(coll_dir(i, d[r][i], dr, ra, coll_eq(cu, m15uu), coll_t(cu), cF, uF3, ck));
+            const P q = Store1<S>::collide(ck.omc, d[r][i], coll_rhs(i, dr, ra, coll_eq(cu, m15uu), coll_t(cu), cF, uF3, ck));
             e = i == 1 ? remainder_term(d[r][i], Store1<S>::dec(q)) : e + remainder_term(d[r][i], Store1<S>::dec(q));
             if constexpr (NT)
                 Store1<S>::putnt(at(fout, own[r] + (uint32_t)i * pb), q);

@@ -248,8 +248,9 @@ def test_fp16_tile_shapes_and_lanes_bit_identical(gpu, ora, bc):
     """FP16 storage, every tile height, one or two lanes per node: the same
     bits.  The one-lane step reads the stored FP16 halves straight into
     mixed-precision adds, subtracts and multiply-adds; the two-lane step
-    converts them to FP32 first.  Equal bits pin the mixed forms to the plain
-    FP32 arithmetic."""
+    converts them to FP32 first.  Equal bits pin the mixed sums and
+    differences to the plain FP32 arithmetic, and both round the stored
+    populations once to FP16."""
     c = W.plane_drop(300, 150, 33.0, 20.0, bc, G=3.0, chi=(1.1, 0.9))
     mask = gpu_mask(gpu, c)
     res = []
