@@ -137,3 +137,21 @@ def test_grid_beyond_the_24bit_row_offsets_rejected(nx, ny):
     assert code == capi.LBM_EINVAL
     assert "233,000" in capi.lib().lbm_last_error(None).decode()
     assert not h.value
+
+
+@pytest.mark.parametrize("storage,model,rows", [("f32", 0, 8), ("f16", 0, 16), ("f16", 1, 8), ("f32", 1, 8)])
+def test_default_tile_rows_follow_storage_and_model(storage, model, rows):
+    """tile_y = 0 takes 16 rows for the two-component model with FP16 storage
+    and 8 otherwise.  The pool footprint counts per-tile flags and partials,
+    so it equals that of the explicit default height and differs from the
+    other one."""
+    import ctypes
+
+    from paper_2009_12584_amd import capi
+
+    def footprint(ty):
+        p = capi.make_params(512, 256, storage=storage, model=model, tile_y=ty)
+        return int(capi.lib().lbm_pool_footprint(ctypes.byref(p)))
+
+    other = 8 if rows == 16 else 16
+    assert footprint(0) == footprint(rows) != footprint(other)
