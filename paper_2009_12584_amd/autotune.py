@@ -7,8 +7,8 @@ one lane per node (one thread per node) is the default with FP32 storage: on
 MI355X it is the fastest or within 2% of the fastest on every FP32 workload
 measured, from the latency-bound 512 x 256 plane to the 5600 x 4000 grid;
 smaller tiles and two lanes win only where few tiles cover the 256 compute
-units.  With FP16 storage the 64 x 16 tile (four nodes per thread) is the
-default: a node moves half the bytes, and four per thread keep enough of them
+units.  With FP16 storage the two-component step defaults to the 64 x 16
+tile (four nodes per thread): a node moves half the bytes, and four per thread keep enough of them
 in flight (2.6% to 7% faster than 64 x 8 on the 5600 x 4000 grids and the
 64-instance batch).  The library applies the same defaults.  The tuner times
 a few steps of the caller's own problem for each candidate on the device and
@@ -34,6 +34,8 @@ MARGIN = 0.02  # another shape must be this much faster than the default
 def default_shape(storage="f32", model=0):
     """The library's own choice when tile_y and lanes are left at 0."""
     return (16, 1) if storage == "f16" and model == 0 else (8, 1)
+
+
 _CACHE_PATH = os.path.join(os.path.expanduser("~"), ".cache", "mclbm", "autotune-v5.json")
 _cache = None
 
