@@ -13,9 +13,11 @@
 
 namespace mclbm {
 
-// Tiles per rule in a flattened list (the rule decides which kernel runs).
+// Tiles per rule in a flattened list (the rule decides which kernel runs) and
+// the list's per-XCD bands.
 struct TileLists {
     int cnt[3] = {0, 0, 0};
+    Bands bands{};
     int total() const { return cnt[0] + cnt[1] + cnt[2]; }
     int rules() const { return (cnt[0] > 0) + (cnt[1] > 0) + (cnt[2] > 0); }
 };
@@ -31,11 +33,13 @@ struct BatchLaunch {
     int *flags = nullptr;         // device, per instance: sticky flags after a reduction (or null)
 };
 
-// Block b of a launch over the list: its position, its instance, and whether
-// the instance still runs at launch counter L (a finished slot's blocks leave
-// at once, together).
+// Block b of a launch over the list: its position (blocks past the end of
+// their XCD's band leave at once), its instance, and whether the instance
+// still runs at launch counter L (a finished slot's blocks leave at once,
+// together).
 #define MCLBM_BATCH_PROLOGUE                                                  \
-    const int t = xcd_tile(blockIdx.x, gridDim.x);                            \
+    const int t = band_tile(blockIdx.x, bands);                               \
+    if (t < 0) return;                                                        \
     const int2 e = tiles[t];                                                  \
     const Inst &I = insts[e.x]; /* uniform, read-only: scalar loads */        \
     if (L >= I.t_end) return;                                                 \
@@ -46,7 +50,7 @@ struct BatchLaunch {
 
 template <typename S, int TY, int BC, bool DIAG>
 __global__ __launch_bounds__(threads_for(TY)) void k_batch_step(const Inst *__restrict__ insts,
-                                                                const int2 *__restrict__ tiles, int launch_parity,
+                                                                const int2 *__restrict__ tiles, Bands bands, int launch_parity,
                                                                 long long L, double *partials) {
     __shared__ Smem<TY> sm;
     MCLBM_BATCH_PROLOGUE
@@ -57,7 +61,7 @@ __global__ __launch_bounds__(threads_for(TY)) void k_batch_step(const Inst *__re
 // The same with two lanes per node (bit-identical results).
 template <typename S, int TY, int BC, bool DIAG>
 __global__ __launch_bounds__(ls_threads(TY)) void k_batch_step_ls(const Inst *__restrict__ insts,
-                                                                  const int2 *__restrict__ tiles, int launch_parity,
+                                                                  const int2 *__restrict__ tiles, Bands bands, int launch_parity,
                                                                   long long L, double *partials) {
     __shared__ SmemLS<TY> sm;
     MCLBM_BATCH_PROLOGUE
@@ -70,7 +74,7 @@ __global__ __launch_bounds__(ls_threads(TY)) void k_batch_step_ls(const Inst *__
 // largest), and a step pays one launch tail instead of three.
 template <typename S, int TY, bool DIAG>
 __global__ __launch_bounds__(threads_for(TY)) void k_batch_step_all(const Inst *__restrict__ insts,
-                                                                    const int2 *__restrict__ tiles, int launch_parity,
+                                                                    const int2 *__restrict__ tiles, Bands bands, int launch_parity,
                                                                     long long L, double *partials) {
     __shared__ Smem<TY> sm;
     MCLBM_BATCH_PROLOGUE
@@ -85,7 +89,7 @@ __global__ __launch_bounds__(threads_for(TY)) void k_batch_step_all(const Inst *
 
 template <typename S, int TY, bool DIAG>
 __global__ __launch_bounds__(ls_threads(TY)) void k_batch_step_ls_all(const Inst *__restrict__ insts,
-                                                                      const int2 *__restrict__ tiles,
+                                                                      const int2 *__restrict__ tiles, Bands bands,
                                                                       int launch_parity, long long L,
                                                                       double *partials) {
     __shared__ SmemLS<TY> sm;
@@ -101,14 +105,16 @@ __global__ __launch_bounds__(ls_threads(TY)) void k_batch_step_ls_all(const Inst
 
 #undef MCLBM_BATCH_PROLOGUE
 
+// A launch covers every band: 8 x (longest band) blocks.
 template <typename S, int TY, int BC, bool DIAG>
-void launch_batch_bc(const BatchLaunch &B, hipStream_t s, int n, int lp, long long L) {
+void launch_batch_bc(const BatchLaunch &B, hipStream_t s, int lp, long long L) {
+    const int n = band_blocks(B.T.bands);
     if (B.lanes == 2)
         hipLaunchKernelGGL((k_batch_step_ls<S, TY, BC, DIAG>), dim3(n), dim3(ls_threads(TY)), 0, s, B.insts, B.tiles,
-                           lp, L, B.partials);
+                           B.T.bands, lp, L, B.partials);
     else
         hipLaunchKernelGGL((k_batch_step<S, TY, BC, DIAG>), dim3(n), dim3(threads_for(TY)), 0, s, B.insts, B.tiles,
-                           lp, L, B.partials);
+                           B.T.bands, lp, L, B.partials);
 }
 
 // With one rule in the list the launch runs the kernel specialised (and
@@ -117,17 +123,18 @@ template <typename S, int TY, bool DIAG>
 void launch_batch_ty(const BatchLaunch &B, hipStream_t s, int lp, long long L) {
     const TileLists &T = B.T;
     if (T.rules() > 1) {
+        const int n = band_blocks(T.bands);
         if (B.lanes == 2)
-            hipLaunchKernelGGL((k_batch_step_ls_all<S, TY, DIAG>), dim3(T.total()), dim3(ls_threads(TY)), 0, s,
-                               B.insts, B.tiles, lp, L, B.partials);
+            hipLaunchKernelGGL((k_batch_step_ls_all<S, TY, DIAG>), dim3(n), dim3(ls_threads(TY)), 0, s, B.insts,
+                               B.tiles, T.bands, lp, L, B.partials);
         else
-            hipLaunchKernelGGL((k_batch_step_all<S, TY, DIAG>), dim3(T.total()), dim3(threads_for(TY)), 0, s, B.insts,
-                               B.tiles, lp, L, B.partials);
+            hipLaunchKernelGGL((k_batch_step_all<S, TY, DIAG>), dim3(n), dim3(threads_for(TY)), 0, s, B.insts,
+                               B.tiles, T.bands, lp, L, B.partials);
         return;
     }
-    if (T.cnt[0]) launch_batch_bc<S, TY, BC_MC, DIAG>(B, s, T.cnt[0], lp, L);
-    if (T.cnt[1]) launch_batch_bc<S, TY, BC_LLKC, DIAG>(B, s, T.cnt[1], lp, L);
-    if (T.cnt[2]) launch_batch_bc<S, TY, BC_IMPROVED, DIAG>(B, s, T.cnt[2], lp, L);
+    if (T.cnt[0]) launch_batch_bc<S, TY, BC_MC, DIAG>(B, s, lp, L);
+    if (T.cnt[1]) launch_batch_bc<S, TY, BC_LLKC, DIAG>(B, s, lp, L);
+    if (T.cnt[2]) launch_batch_bc<S, TY, BC_IMPROVED, DIAG>(B, s, lp, L);
 }
 
 template <typename S>

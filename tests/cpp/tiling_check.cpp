@@ -2,9 +2,11 @@
 // periodic size, tile height and tile, every coordinate the tile touches
 // (its nodes, the density frame and the pull of a frame node) must either lie
 // inside [0, n) on a tile that is not marked as an edge, or wrap to its true
-// residue modulo n.  Prints the first failure and exits non-zero.
+// residue modulo n.  Also the per-XCD bands of batched launches.  Prints the
+// first failure and exits non-zero.
 #include <cstdio>
 #include <initializer_list>
+#include <vector>
 
 #include "../../paper_2009_12584_amd/csrc/lbm_tiling.hpp"
 
@@ -62,6 +64,94 @@ int main() {
             }
             ++cases;
         }
+    // per-XCD bands of batched launches: the listed instances appear once
+    // each, the bands partition the list, every position is taken by exactly
+    // one block of the launch, and the bands' costs differ by at most the
+    // costliest instance (the least-cost-band rule)
+    unsigned seed = 12345u;
+    auto rnd = [&]() { seed = seed * 1664525u + 1013904223u; return seed >> 8; };
+    for (int trial = 0; trial < 400; ++trial) {
+        const bool equal = trial % 2 == 1;
+        const int n = 1 + (int)(rnd() % 80);
+        std::vector<int> cnt(n);
+        std::vector<char> heavy(n);
+        int total = 0;
+        double cmax = 0.0, ctot = 0.0;
+        for (int k = 0; k < n; ++k) {
+            cnt[k] = rnd() % 5 == 0 ? 0 : 1 + (int)(rnd() % (trial < 100 ? 40 : 900));
+            heavy[k] = rnd() % 3 == 0;
+            total += cnt[k];
+            const double c = cnt[k] * (heavy[k] ? IMPROVED_TILE_COST : 1.0);
+            cmax = c > cmax ? c : cmax;
+            ctot += c;
+        }
+        Bands B;
+        const std::vector<int> seq = deal_bands(cnt, heavy, IMPROVED_TILE_COST, equal, B);
+        std::vector<int> seen(n, 0);
+        int listed = 0;
+        for (int k : seq) ++seen[k];
+        for (int k = 0; k < n; ++k) {
+            listed += cnt[k] > 0;
+            if (seen[k] != (cnt[k] > 0 ? 1 : 0)) {
+                std::printf("bands: instance %d listed %d times\n", k, seen[k]);
+                return 1;
+            }
+        }
+        if ((int)seq.size() != listed || B.start[0] != 0 || B.start[8] != total) {
+            std::printf("bands: %d of %d instances, list [%d, %d) of %d\n", (int)seq.size(), listed, B.start[0],
+                        B.start[8], total);
+            return 1;
+        }
+        std::vector<int> hit(total, 0);
+        const int nb = band_blocks(B);
+        for (int b = 0; b < nb; ++b) {
+            const int t = band_tile(b, B);
+            if (t >= total) {
+                std::printf("bands: block %d takes position %d of %d\n", b, t, total);
+                return 1;
+            }
+            if (t >= 0) ++hit[t];
+        }
+        for (int t = 0; t < total; ++t)
+            if (hit[t] != 1) {
+                std::printf("bands: position %d taken %d times\n", t, hit[t]);
+                return 1;
+            }
+        if (equal) {
+            for (int x = 0; x < 8; ++x) {
+                const int len = B.start[x + 1] - B.start[x];
+                if (len != total / 8 + (x < total % 8 ? 1 : 0)) {
+                    std::printf("bands: equal band %d holds %d of %d\n", x, len, total);
+                    return 1;
+                }
+            }
+            ++cases;
+            continue;
+        }
+        // band costs along the list
+        double lo = 1e300, hi = 0.0;
+        size_t i = 0;
+        for (int x = 0; x < 8; ++x) {
+            if (B.start[x + 1] < B.start[x]) {
+                std::printf("bands: band %d ends before it starts\n", x);
+                return 1;
+            }
+            double c = 0.0;
+            int got = 0;
+            while (i < seq.size() && got < B.start[x + 1] - B.start[x]) {
+                got += cnt[seq[i]];
+                c += cnt[seq[i]] * (heavy[seq[i]] ? IMPROVED_TILE_COST : 1.0);
+                ++i;
+            }
+            lo = c < lo ? c : lo;
+            hi = c > hi ? c : hi;
+        }
+        if (hi - lo > cmax + 1e-9 || (ctot > 0 && hi < ctot / 8 - 1e-9)) {
+            std::printf("bands: costs %g .. %g with the costliest instance %g\n", lo, hi, cmax);
+            return 1;
+        }
+        ++cases;
+    }
     // the case of a 32-row tile over a 33-row periodic lattice reaches row 67
     if (!needs_modulo(33, 32)) {
         std::printf("33 rows in 32-row tiles must wrap by modulo\n");
