@@ -83,10 +83,9 @@ TileLists build_tiles(int n, int storage, InstOf inst_of, FluidOf fluid_of, std:
         heavy[k] = I->bc == BC_IMPROVED;
     }
     // FP32: bands of equal cost, improved-scheme tiles weighted by their
-    // measured cost (the 64-instance FP32 batch 132.4 -> 130.5 us).  FP16:
-    // instances dealt by tile count and the list cut in equal eighths, which
-    // measured faster there (85.1 us against 85.7-86.4 with bands of equal
-    // cost at weights 1 to 1.2).
+    // measured cost.  FP16: instances dealt by tile count and the list cut in
+    // equal eighths, which measured faster there (85.1 us against 85.7-86.4
+    // for the 64-instance batch with bands of equal cost at weights 1 to 1.2).
     const bool f16 = storage == LBM_STORE_F16;
     for (int k : deal_bands(cnt, heavy, f16 ? 1.0 : IMPROVED_TILE_COST, f16, T.bands)) {
         const Inst *I = inst_of(k);

@@ -80,15 +80,21 @@ inline int band_blocks(const Bands &B) {
 // Eq. 7).
 constexpr double IMPROVED_TILE_COST = 1.2;
 
-// Deals instances to the 8 bands so that each carries about the same cost:
-// improved-scheme instances first, then larger before smaller, each to the
-// band with the least cost so far.  Every XCD then runs its heavy tiles first
-// and ends on light ones, and the XCDs finish together.  cnt[k] is instance
-// k's listed tiles (0: not listed), heavy[k] whether it runs the improved
-// scheme, w the cost of its tiles relative to the others'.  Returns the
-// listed instances in list order (band 0's, then band 1's, ...) and sets the
-// band starts in tiles: where the instances were dealt or, with equal, eight
-// equal eighths of the list (the first list length % 8 one tile longer).
+// Orders the instances of a batched list and cuts it into the 8 bands.  The
+// instances are dealt to 8 groups of about equal cost, improved-scheme
+// instances first, then larger before smaller, each to the group with the
+// least cost so far, and the groups are listed one after the other.  When the
+// groups' costs agree within DEALT_BAND_SPREAD of their mean, each group is a
+// band: every XCD runs whole instances (their halos stay in its L2), its heavy
+// tiles first, and the XCDs finish together.  Otherwise (a few large
+// instances) the cuts give every band the same cost to within one tile, the
+// tiles of one instance falling in several bands, so that all 8 XCDs work.
+// cnt[k] is instance k's listed tiles (0: not listed), heavy[k] whether it
+// runs the improved scheme, w the cost of its tiles relative to the others'.
+// With equal, the cuts give eight equal eighths of the list instead (the
+// first list length % 8 one tile longer).  Returns the listed instances in
+// list order and sets the band starts in tiles.
+constexpr double DEALT_BAND_SPREAD = 0.05;
 inline std::vector<int> deal_bands(const std::vector<int> &cnt, const std::vector<char> &heavy, double w, bool equal,
                                    Bands &B) {
     const int n = (int)cnt.size();
@@ -117,15 +123,38 @@ inline std::vector<int> deal_bands(const std::vector<int> &cnt, const std::vecto
         tiles[j] += cnt[k];
     }
     std::vector<int> seq;
-    B.start[0] = 0;
+    int total = 0;
+    double all = 0.0;
     for (int x = 0; x < 8; ++x) {
         seq.insert(seq.end(), band[x].begin(), band[x].end());
-        B.start[x + 1] = B.start[x] + tiles[x];
+        total += tiles[x];
+        all += load[x];
+    }
+    B.start[0] = 0;
+    B.start[8] = total;
+    double lo = load[0], hi = load[0];
+    for (int x = 1; x < 8; ++x) {
+        lo = load[x] < lo ? load[x] : lo;
+        hi = load[x] > hi ? load[x] : hi;
+    }
+    if (!equal && all > 0.0 && hi - lo <= DEALT_BAND_SPREAD * all / 8.0) {
+        for (int x = 1; x < 8; ++x) B.start[x] = B.start[x - 1] + tiles[x - 1];
+        return seq;
     }
     if (equal) {
-        const int total = B.start[8], q = total / 8, r = total % 8;
-        for (int x = 0; x <= 8; ++x) B.start[x] = x * q + (x < r ? x : r);
+        const int q = total / 8, r = total % 8;
+        for (int x = 1; x < 8; ++x) B.start[x] = x * q + (x < r ? x : r);
+        return seq;
     }
+    // band x starts at the first tile whose preceding tiles cost x/8 of the whole
+    int x = 1, pos = 0;
+    double acc = 0.0;
+    for (int k : seq) {
+        const double c = heavy[k] ? w : 1.0;
+        for (int i = 0; i < cnt[k]; ++i, ++pos, acc += c)
+            while (x < 8 && acc >= all * x / 8.0) B.start[x++] = pos;
+    }
+    while (x < 8) B.start[x++] = total;
     return seq;
 }
 
