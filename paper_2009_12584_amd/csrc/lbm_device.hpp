@@ -346,6 +346,12 @@ template <int TY> struct Smem {
     uint8_t lf[VH * VW];
     double red[threads_for(TY) / 64][5];
     int redi[threads_for(TY) / 64];
+    // the interface solids of tile + 1 as a dense list for Eq. 7: position,
+    // fluid D2Q25 mask, and per (slot, wavefront) how many each lists
+    static constexpr int NVS = (VW * VH + threads_for(TY) - 1) / threads_for(TY);
+    uint16_t ik[VH * VW];
+    uint32_t im[VH * VW];
+    int icnt[NVS * (threads_for(TY) / 64)];
 };
 
 template <int TY> __device__ __forceinline__ int rho_idx(int lx, int ly) {
@@ -750,55 +756,83 @@ __device__ __forceinline__ void process_tile(const Inst &I, int tile_x, int tile
     }
     __syncthreads();
 
-    // ---- phase 2: virtual solid density of Eq. 7 on interface solids in tile + 1
+    // ---- phase 2: virtual solid density of Eq. 7 on interface solids in tile + 1.
+    // The interface solids lie along the wall line, a few in most wavefronts'
+    // slots, so they are first gathered into a dense list (wavefront ballots,
+    // then each one's place from the counts before it) and then shared out
+    // over the workgroup: a few full wavefronts run the 48-read average
+    // instead of every wavefront running it for a few lanes.  Each position is
+    // computed by the same expressions, whichever thread takes it.
     if (BC == BC_IMPROVED && need_rt) {
-        const float chi[2] = {I.chiA, I.chiB};
+        constexpr int T = threads_for(TY), NW = T / 64, NVP = Smem<TY>::VW * Smem<TY>::VH;
+        static_assert(Smem<TY>::NVS == NV, "slots per thread");
+        const int lane = tid & 63, wv = tid >> 6;
+        unsigned long long bal[NV];
 #pragma unroll
         for (int s = 0; s < NV; ++s) {
-            const int k = tid + s * threads_for(TY);
-            if (k >= Smem<TY>::VW * Smem<TY>::VH) continue;
-            const int vx = k % Smem<TY>::VW - 1, vy = k / Smem<TY>::VW - 1;
-            float ta = 0.f, tb = 0.f;
-            if (sm.lf[k] & LF_IFACE) {
-                // interface solids lie inside the domain or across a periodic border
-                const uint32_t m = m25v[s];
-                // every position of the 5 x 5 block is in LDS, solids and
-                // out-of-domain positions as 0, so the numerator needs no mask:
-                // all 48 reads issue back to back; the mask enters only the
-                // denominator
-                // the components one after the other: 24 LDS values in
-                // flight at a time instead of 48 keeps the phase within the
-                // registers of the rest of the step
-                float na = 0.f, nb = 0.f, den = 0.f;
-                int j = 0;
-#pragma unroll
-                for (int ey = -2; ey <= 2; ++ey)
-#pragma unroll
-                    for (int ex = -2; ex <= 2; ++ex) {
-                        if (ex == 0 && ey == 0) continue;
-                        const int r2 = ex * ex + ey * ey;
-                        // D2Q25 weights, or the D2Q9 ones on the first belt
-                        const float wt = I.avg == 0 ? W25_BY_R2[r2] : (r2 == 1 ? 1.f / 9.f : (r2 == 2 ? 1.f / 36.f : 0.f));
-                        na += wt * sm.rho[0][rho_idx<TY>(vx + ex, vy + ey)];
-                        den += ((m >> j) & 1u) ? wt : 0.f;
-                        ++j;
-                    }
-                __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-                for (int ey = -2; ey <= 2; ++ey)
-#pragma unroll
-                    for (int ex = -2; ex <= 2; ++ex) {
-                        if (ex == 0 && ey == 0) continue;
-                        const int r2 = ex * ex + ey * ey;
-                        const float wt = I.avg == 0 ? W25_BY_R2[r2] : (r2 == 1 ? 1.f / 9.f : (r2 == 2 ? 1.f / 36.f : 0.f));
-                        nb += wt * sm.rho[1][rho_idx<TY>(vx + ex, vy + ey)];
-                    }
-                // den > 0: an interface solid has a fluid first-belt neighbour
-                ta = chi[0] * na / den;
-                tb = chi[1] * nb / den;
+            const int k = tid + s * T;
+            const bool on = k < NVP && (sm.lf[k] & LF_IFACE);
+            if (k < NVP) {
+                sm.rt[0][k] = 0.f;
+                sm.rt[1][k] = 0.f;
             }
-            sm.rt[0][k] = ta;
-            sm.rt[1][k] = tb;
+            bal[s] = __ballot(on);
+            if (lane == 0) sm.icnt[s * NW + wv] = __popcll(bal[s]);
+        }
+        __syncthreads();
+        int total = 0;
+#pragma unroll
+        for (int q = 0; q < NV * NW; ++q) total += sm.icnt[q];
+#pragma unroll
+        for (int s = 0; s < NV; ++s) {
+            if ((bal[s] >> lane) & 1ull) {
+                int pos = __popcll(bal[s] & ((1ull << lane) - 1ull));
+                for (int q = 0; q < s * NW + wv; ++q) pos += sm.icnt[q];
+                sm.ik[pos] = (uint16_t)(tid + s * T);
+                sm.im[pos] = m25v[s];
+            }
+        }
+        __syncthreads();
+        const float chi[2] = {I.chiA, I.chiB};
+        for (int jj = tid; jj < total; jj += T) {
+            const int k = sm.ik[jj];
+            const int vx = k % Smem<TY>::VW - 1, vy = k / Smem<TY>::VW - 1;
+            // interface solids lie inside the domain or across a periodic border
+            const uint32_t m = sm.im[jj];
+            // every position of the 5 x 5 block is in LDS, solids and
+            // out-of-domain positions as 0, so the numerator needs no mask:
+            // all 48 reads issue back to back; the mask enters only the
+            // denominator
+            // the components one after the other: 24 LDS values in
+            // flight at a time instead of 48 keeps the phase within the
+            // registers of the rest of the step
+            float na = 0.f, nb = 0.f, den = 0.f;
+            int j = 0;
+#pragma unroll
+            for (int ey = -2; ey <= 2; ++ey)
+#pragma unroll
+                for (int ex = -2; ex <= 2; ++ex) {
+                    if (ex == 0 && ey == 0) continue;
+                    const int r2 = ex * ex + ey * ey;
+                    // D2Q25 weights, or the D2Q9 ones on the first belt
+                    const float wt = I.avg == 0 ? W25_BY_R2[r2] : (r2 == 1 ? 1.f / 9.f : (r2 == 2 ? 1.f / 36.f : 0.f));
+                    na += wt * sm.rho[0][rho_idx<TY>(vx + ex, vy + ey)];
+                    den += ((m >> j) & 1u) ? wt : 0.f;
+                    ++j;
+                }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int ey = -2; ey <= 2; ++ey)
+#pragma unroll
+                for (int ex = -2; ex <= 2; ++ex) {
+                    if (ex == 0 && ey == 0) continue;
+                    const int r2 = ex * ex + ey * ey;
+                    const float wt = I.avg == 0 ? W25_BY_R2[r2] : (r2 == 1 ? 1.f / 9.f : (r2 == 2 ? 1.f / 36.f : 0.f));
+                    nb += wt * sm.rho[1][rho_idx<TY>(vx + ex, vy + ey)];
+                }
+            // den > 0: an interface solid has a fluid first-belt neighbour
+            sm.rt[0][k] = chi[0] * na / den;
+            sm.rt[1][k] = chi[1] * nb / den;
         }
         __syncthreads();
     }
