@@ -108,7 +108,7 @@ TileLists build_tiles(int n, int storage, InstOf inst_of, FluidOf fluid_of, std:
 // Device memory of one instance, carved from one block.
 struct InstMem {
     size_t bytes = 0;
-    size_t off_buf0, off_buf1, off_word, off_m25, off_nbr, off_cls, off_tflag, off_part, off_dd, off_fields;
+    size_t off_buf0, off_buf1, off_word, off_den7, off_nbr, off_cls, off_tflag, off_part, off_dd, off_fields;
 };
 
 inline size_t al(size_t x) { return (x + 255) / 256 * 256; }
@@ -127,7 +127,7 @@ InstMem layout(const lbm_params &p, int ty) {
     m.off_buf0 = take(pop_buffer_bytes(p));
     m.off_buf1 = take(pop_buffer_bytes(p));
     m.off_word = take(plane * sizeof(uint16_t));
-    m.off_m25 = take(plane * sizeof(uint32_t));
+    m.off_den7 = take(plane * sizeof(float));
     m.off_nbr = take(n);
     m.off_cls = take(n);
     m.off_tflag = take(tiles);
@@ -178,7 +178,7 @@ int prepare(Prepared &P, const lbm_params &p, int ty, char *base, const uint8_t 
     P.I.buf[0] = base + P.m.off_buf0;
     P.I.buf[1] = base + P.m.off_buf1;
     uint16_t *word = (uint16_t *)(base + P.m.off_word);
-    uint32_t *m25 = (uint32_t *)(base + P.m.off_m25);
+    float *den7 = (float *)(base + P.m.off_den7);
     P.nbr = (uint8_t *)(base + P.m.off_nbr);
     P.cls = (uint8_t *)(base + P.m.off_cls);
     uint8_t *tflag = (uint8_t *)(base + P.m.off_tflag);
@@ -193,12 +193,12 @@ int prepare(Prepared &P, const lbm_params &p, int ty, char *base, const uint8_t 
     MCLBM_HIP(hipMemsetAsync(P.I.buf[1], 0, bufbytes, s));
     MCLBM_HIP(hipMemsetAsync(word, 0, np * sizeof(uint16_t), s));
     MCLBM_HIP(hipMemsetAsync(word0, 0, np * sizeof(uint16_t), s));
-    MCLBM_HIP(hipMemsetAsync(m25, 0, np * sizeof(uint32_t), s));
+    MCLBM_HIP(hipMemsetAsync(den7, 0, np * sizeof(float), s));
     MCLBM_HIP(hipMemcpyAsync(P.dd, &P.dd0, sizeof(DiagDev), hipMemcpyHostToDevice, s));
     MCLBM_HIP(hipMemcpyAsync(dmask, mask, n, hipMemcpyHostToDevice, s));
     MCLBM_HIP(hipMemcpyAsync(drA, rA, n * sizeof(double), hipMemcpyHostToDevice, s));
     MCLBM_HIP(hipMemcpyAsync(drB, rB, n * sizeof(double), hipMemcpyHostToDevice, s));
-    const Geometry g{P.nbr, P.cls, word, m25, tflag, word0};
+    const Geometry g{P.nbr, P.cls, word, den7, tflag, word0};
     int rc = enqueue_setup(P.I, p, ty, dmask, drA, drB, g, s);
     if (rc) return rc;
     // step-0 mass, recorded by the first fields pass

@@ -303,16 +303,18 @@ static __global__ void k_near(const uint16_t *__restrict__ word0, int nx, int ny
     word[(int64_t)y * pitch + x] = (uint16_t)f;
 }
 
-// For interface solids: bit j set when the j-th D2Q25 neighbour (rows dy = -2..2,
-// columns dx = -2..2, centre skipped) is fluid and inside the domain (Eq. 7).
-static __global__ void k_m25(const uint16_t *__restrict__ word, int nx, int ny, uint32_t periodic, int pitch,
-                             uint32_t *__restrict__ m25) {
+// For interface solids: the denominator of Eq. 7, the sum of the averaging
+// weights (D2Q25, or D2Q9 with avg = 1) over the fluid neighbours inside the
+// domain, accumulated in FP32 over rows dy = -2..2 and columns dx = -2..2
+// (centre skipped) in that order; 0 elsewhere.  It depends on the geometry
+// only, so the step reads it instead of summing it every step.
+static __global__ void k_den7(const uint16_t *__restrict__ word, int nx, int ny, uint32_t periodic, int pitch,
+                              int avg, float *__restrict__ den7) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= (int64_t)nx * ny) return;
     const int x = (int)(k % nx), y = (int)(k / nx);
-    uint32_t m = 0;
+    float den = 0.f;
     if (word[(int64_t)y * pitch + x] & NW_IFACE) {
-        int j = 0;
         for (int dy = -2; dy <= 2; ++dy)
             for (int dx = -2; dx <= 2; ++dx) {
                 if (dx == 0 && dy == 0) continue;
@@ -326,11 +328,10 @@ static __global__ void k_m25(const uint16_t *__restrict__ word, int nx, int ny, 
                     if (periodic & 2u) yn = wrap(yn, ny, true);
                     else in = false;
                 }
-                if (in && !(word[(int64_t)yn * pitch + xn] & NW_SOLID)) m |= 1u << j;
-                ++j;
+                if (in && !(word[(int64_t)yn * pitch + xn] & NW_SOLID)) den += eq7_weight(dx * dx + dy * dy, avg);
             }
     }
-    m25[(int64_t)y * pitch + x] = m;
+    den7[(int64_t)y * pitch + x] = den;
 }
 
 // Per tile: does an owned fluid node touch a solid (then the improved scheme
@@ -405,17 +406,17 @@ __global__ void k_init_sc1(Inst I, const double *__restrict__ rA, double rref, i
 struct Geometry {
     uint8_t *nbr, *cls;   // nx * ny, the classification returned by the ABI
     uint16_t *word;       // ny * pitch node words
-    uint32_t *m25;        // ny * pitch D2Q25 fluid masks of interface solids
+    float *den7;          // ny * pitch Eq. 7 denominators of interface solids
     uint8_t *tflag;       // tiles
     uint16_t *word0;      // ny * pitch scratch for the set-up
 };
 
 inline size_t geometry_bytes(int nx, int ny, int pitch, int ntiles) {
     const size_t n = (size_t)nx * ny, np = (size_t)ny * pitch;
-    return 2 * n + 2 * np * sizeof(uint16_t) + np * sizeof(uint32_t) + (size_t)ntiles;
+    return 2 * n + 2 * np * sizeof(uint16_t) + np * sizeof(float) + (size_t)ntiles;
 }
 
-// Classification, node words, Eq. 7 masks, tile flags and the initial
+// Classification, node words, Eq. 7 denominators, tile flags and the initial
 // populations of one simulation, enqueued on stream s (I.buf[0] is written).
 inline int enqueue_setup(Inst &I, const lbm_params &p, int ty, const uint8_t *dmask, const double *drA,
                          const double *drB, const Geometry &g, hipStream_t s) {
@@ -424,11 +425,11 @@ inline int enqueue_setup(Inst &I, const lbm_params &p, int ty, const uint8_t *dm
     hipLaunchKernelGGL(k_classify, dim3(nb), dim3(256), 0, s, dmask, p.nx, p.ny, p.periodic, I.pitch, g.nbr, g.cls,
                        g.word0);
     hipLaunchKernelGGL(k_near, dim3(nb), dim3(256), 0, s, g.word0, p.nx, p.ny, p.periodic, I.pitch, g.word);
-    hipLaunchKernelGGL(k_m25, dim3(nb), dim3(256), 0, s, g.word, p.nx, p.ny, p.periodic, I.pitch, g.m25);
+    hipLaunchKernelGGL(k_den7, dim3(nb), dim3(256), 0, s, g.word, p.nx, p.ny, p.periodic, I.pitch, p.avg, g.den7);
     hipLaunchKernelGGL(k_tileflags, dim3((unsigned)(I.tiles_x * I.tiles_y)), dim3(256), 0, s, g.cls, p.nx, p.ny, ty,
                        I.tiles_x, g.tflag);
     I.node = g.word;
-    I.m25 = g.m25;
+    I.den7 = g.den7;
     I.tflag = g.tflag;
     if (p.model == LBM_MODEL_SC1) {
         if (p.storage == LBM_STORE_F16)

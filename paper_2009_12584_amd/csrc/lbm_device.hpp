@@ -77,6 +77,11 @@ __device__ constexpr float WF[9] = {4.f / 9.f,  1.f / 9.f,  1.f / 9.f,  1.f / 9.
 // D2Q25 averaging weights of Eq. 7, indexed by |e|^2 (0 for the absent 3, 6, 7).
 __device__ constexpr float W25_BY_R2[9] = {0.f,        4.f / 21.f, 4.f / 45.f, 0.f, 1.f / 60.f,
                                            2.f / 315.f, 0.f,        0.f,        1.f / 5040.f};
+// Weight of a neighbour at squared distance r2 in the average of Eq. 7: the
+// D2Q25 weights (avg = 0), or the D2Q9 ones on the first belt (avg = 1).
+__device__ __forceinline__ float eq7_weight(int r2, int avg) {
+    return avg == 0 ? W25_BY_R2[r2] : (r2 == 1 ? 1.f / 9.f : (r2 == 2 ? 1.f / 36.f : 0.f));
+}
 
 // c_i . (x, y), without the products by a zero lattice
 // component: once the direction loops are unrolled i is a constant, and those
@@ -311,7 +316,7 @@ struct DiagDev {
 struct Inst {
     void *buf[2];             // population buffers; parity selects the one read
     const uint16_t *node;     // node words, row pitch `pitch`
-    const uint32_t *m25;      // fluid D2Q25 neighbours of interface solids, row pitch `pitch`
+    const float *den7;        // Eq. 7 denominators of interface solids (k_den7), row pitch `pitch`
     const uint8_t *tflag;     // TF_* per tile
     int nx, ny, pitch, tiles_x, tiles_y;
     int64_t plane;            // nodes per padded lattice = ny * pitch (node words, masks)
@@ -347,10 +352,10 @@ template <int TY> struct Smem {
     double red[threads_for(TY) / 64][5];
     int redi[threads_for(TY) / 64];
     // the interface solids of tile + 1 as a dense list for Eq. 7: position,
-    // fluid D2Q25 mask, and per (slot, wavefront) how many each lists
+    // denominator, and per (slot, wavefront) how many each lists
     static constexpr int NVS = (VW * VH + threads_for(TY) - 1) / threads_for(TY);
     uint16_t ik[VH * VW];
-    uint32_t im[VH * VW];
+    float iden[VH * VW];
     int icnt[NVS * (threads_for(TY) / 64)];
 };
 
@@ -721,11 +726,11 @@ __device__ __forceinline__ void process_tile(const Inst &I, int tile_x, int tile
         }
     }
 
-    // fluid D2Q25 masks of the tile + 1 positions this thread treats in Eq. 7,
-    // in flight with the pulls (indices wrap into the grid; a value is used
-    // only at an interface solid)
+    // Eq. 7 denominators of the tile + 1 positions this thread treats, in
+    // flight with the pulls (indices wrap into the grid; a value is used only
+    // at an interface solid)
     constexpr int NV = (Smem<TY>::VW * Smem<TY>::VH + threads_for(TY) - 1) / threads_for(TY);
-    uint32_t m25v[NV];
+    float den7v[NV];
     if (BC == BC_IMPROVED && need_rt) {
 #pragma unroll
         for (int s = 0; s < NV; ++s) {
@@ -733,8 +738,9 @@ __device__ __forceinline__ void process_tile(const Inst &I, int tile_x, int tile
             const int vx = k % Smem<TY>::VW - 1, vy = k / Smem<TY>::VW - 1;
             const int gx = keep_in(tx0 + vx, I.nx, I.periodic & 1u, I.small != 0);
             const int gy = keep_in(ty0 + vy, I.ny, I.periodic & 2u, I.small != 0);
-            m25v[s] = k < Smem<TY>::VW * Smem<TY>::VH ? I.m25[__umul24((uint32_t)gy, (uint32_t)I.pitch) + (uint32_t)gx]
-                                                      : 0u;
+            den7v[s] = k < Smem<TY>::VW * Smem<TY>::VH
+                           ? I.den7[__umul24((uint32_t)gy, (uint32_t)I.pitch) + (uint32_t)gx]
+                           : 0.f;
         }
     }
 
@@ -789,7 +795,7 @@ __device__ __forceinline__ void process_tile(const Inst &I, int tile_x, int tile
                 int pos = __popcll(bal[s] & ((1ull << lane) - 1ull));
                 for (int q = 0; q < s * NW + wv; ++q) pos += sm.icnt[q];
                 sm.ik[pos] = (uint16_t)(tid + s * T);
-                sm.im[pos] = m25v[s];
+                sm.iden[pos] = den7v[s];
             }
         }
         __syncthreads();
@@ -798,27 +804,21 @@ __device__ __forceinline__ void process_tile(const Inst &I, int tile_x, int tile
             const int k = sm.ik[jj];
             const int vx = k % Smem<TY>::VW - 1, vy = k / Smem<TY>::VW - 1;
             // interface solids lie inside the domain or across a periodic border
-            const uint32_t m = sm.im[jj];
+            const float den = sm.iden[jj];
             // every position of the 5 x 5 block is in LDS, solids and
-            // out-of-domain positions as 0, so the numerator needs no mask:
-            // all 48 reads issue back to back; the mask enters only the
-            // denominator
+            // out-of-domain positions as 0, so the numerator needs no mask
+            // and all its reads issue back to back; the denominator, the
+            // weights of the fluid neighbours, comes with the list
             // the components one after the other: 24 LDS values in
             // flight at a time instead of 48 keeps the phase within the
             // registers of the rest of the step
-            float na = 0.f, nb = 0.f, den = 0.f;
-            int j = 0;
+            float na = 0.f, nb = 0.f;
 #pragma unroll
             for (int ey = -2; ey <= 2; ++ey)
 #pragma unroll
                 for (int ex = -2; ex <= 2; ++ex) {
                     if (ex == 0 && ey == 0) continue;
-                    const int r2 = ex * ex + ey * ey;
-                    // D2Q25 weights, or the D2Q9 ones on the first belt
-                    const float wt = I.avg == 0 ? W25_BY_R2[r2] : (r2 == 1 ? 1.f / 9.f : (r2 == 2 ? 1.f / 36.f : 0.f));
-                    na += wt * sm.rho[0][rho_idx<TY>(vx + ex, vy + ey)];
-                    den += ((m >> j) & 1u) ? wt : 0.f;
-                    ++j;
+                    na += eq7_weight(ex * ex + ey * ey, I.avg) * sm.rho[0][rho_idx<TY>(vx + ex, vy + ey)];
                 }
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -826,9 +826,7 @@ __device__ __forceinline__ void process_tile(const Inst &I, int tile_x, int tile
 #pragma unroll
                 for (int ex = -2; ex <= 2; ++ex) {
                     if (ex == 0 && ey == 0) continue;
-                    const int r2 = ex * ex + ey * ey;
-                    const float wt = I.avg == 0 ? W25_BY_R2[r2] : (r2 == 1 ? 1.f / 9.f : (r2 == 2 ? 1.f / 36.f : 0.f));
-                    nb += wt * sm.rho[1][rho_idx<TY>(vx + ex, vy + ey)];
+                    nb += eq7_weight(ex * ex + ey * ey, I.avg) * sm.rho[1][rho_idx<TY>(vx + ex, vy + ey)];
                 }
             // den > 0: an interface solid has a fluid first-belt neighbour
             sm.rt[0][k] = chi[0] * na / den;

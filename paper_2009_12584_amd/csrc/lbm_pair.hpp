@@ -212,11 +212,12 @@ __device__ __forceinline__ void process_tile_ls(const Inst &I, int tile_x, int t
         }
     }
 
-    // Eq. 7 masks of the tile + 1 positions this lane pair treats, in flight
-    // with the pulls (indices wrap into the grid; used only at interface solids)
+    // Eq. 7 denominators of the tile + 1 positions this lane pair treats, in
+    // flight with the pulls (indices wrap into the grid; used only at
+    // interface solids)
     constexpr int NVP = L::VW * L::VH;
     constexpr int NV = (NVP + NPP - 1) / NPP;
-    uint32_t m25v[NV];
+    float den7v[NV];
     if (BC == BC_IMPROVED && need_rt) {
 #pragma unroll
         for (int s = 0; s < NV; ++s) {
@@ -224,7 +225,7 @@ __device__ __forceinline__ void process_tile_ls(const Inst &I, int tile_x, int t
             const int vx = k % L::VW - 1, vy = k / L::VW - 1;
             const int gx = keep_in(tx0 + vx, I.nx, I.periodic & 1u, I.small != 0);
             const int gy = keep_in(ty0 + vy, I.ny, I.periodic & 2u, I.small != 0);
-            m25v[s] = k < NVP ? I.m25[__umul24((uint32_t)gy, (uint32_t)I.pitch) + (uint32_t)gx] : 0u;
+            den7v[s] = k < NVP ? I.den7[__umul24((uint32_t)gy, (uint32_t)I.pitch) + (uint32_t)gx] : 0.f;
         }
     }
 
@@ -256,20 +257,16 @@ __device__ __forceinline__ void process_tile_ls(const Inst &I, int tile_x, int t
             float tc = 0.f;
             if (sm.lf[k] & LF_IFACE) {
                 // every position of the 5 x 5 block is in LDS, solids and
-                // out-of-domain positions as 0: the numerator needs no mask
-                const uint32_t m = m25v[s];
-                float na = 0.f, den = 0.f;
-                int j = 0;
+                // out-of-domain positions as 0: the numerator needs no mask;
+                // the denominator was summed at set-up (k_den7)
+                const float den = den7v[s];
+                float na = 0.f;
 #pragma unroll
                 for (int ey = -2; ey <= 2; ++ey)
 #pragma unroll
                     for (int ex = -2; ex <= 2; ++ex) {
                         if (ex == 0 && ey == 0) continue;
-                        const int r2 = ex * ex + ey * ey;
-                        const float wt = I.avg == 0 ? W25_BY_R2[r2] : (r2 == 1 ? 1.f / 9.f : (r2 == 2 ? 1.f / 36.f : 0.f));
-                        na += wt * sm.rho[c][rho_idx<TY>(vx + ex, vy + ey)];
-                        den += ((m >> j) & 1u) ? wt : 0.f;
-                        ++j;
+                        na += eq7_weight(ex * ex + ey * ey, I.avg) * sm.rho[c][rho_idx<TY>(vx + ex, vy + ey)];
                     }
                 // den > 0: an interface solid has a fluid first-belt neighbour
                 tc = chi * na / den;

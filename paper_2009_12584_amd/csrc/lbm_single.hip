@@ -32,7 +32,7 @@ struct lbm_handle {
     uint8_t *tflag = nullptr, *nbr = nullptr, *cls = nullptr;
     int *tlist = nullptr;     // logical tiles holding a fluid node: the ones a step launches
     uint16_t *word = nullptr;
-    uint32_t *m25 = nullptr;
+    float *den7 = nullptr;
     double *partials = nullptr;
     DiagDev *dd = nullptr;
     float *fields = nullptr;  // lazily allocated: 10 planes of nx*ny
@@ -61,7 +61,7 @@ void release(lbm_handle *h) {
         if (h->gexec[v]) (void)hipGraphExecDestroy(h->gexec[v]);
         if (h->graph[v]) (void)hipGraphDestroy(h->graph[v]);
     }
-    for (void *q : {(void *)h->I.buf[0], (void *)h->I.buf[1], (void *)h->word, (void *)h->m25, (void *)h->tflag,
+    for (void *q : {(void *)h->I.buf[0], (void *)h->I.buf[1], (void *)h->word, (void *)h->den7, (void *)h->tflag,
                     (void *)h->nbr, (void *)h->cls, (void *)h->partials, (void *)h->dd, (void *)h->fields,
                     (void *)h->cwork, (void *)h->rho1, (void *)h->tlist})
         if (q) (void)hipFree(q);
@@ -171,7 +171,7 @@ int lbm_create(const lbm_params *p, const uint8_t *mask, const double *rhoA0, co
         MCLBM_HIP(hipMalloc(&h->I.buf[0], bufbytes));
         MCLBM_HIP(hipMalloc(&h->I.buf[1], bufbytes));
         MCLBM_HIP(hipMalloc(&h->word, np * sizeof(uint16_t)));
-        MCLBM_HIP(hipMalloc(&h->m25, np * sizeof(uint32_t)));
+        MCLBM_HIP(hipMalloc(&h->den7, np * sizeof(float)));
         MCLBM_HIP(hipMalloc(&h->nbr, n));
         MCLBM_HIP(hipMalloc(&h->cls, n));
         MCLBM_HIP(hipMalloc(&h->tflag, h->ntiles));
@@ -200,14 +200,14 @@ int lbm_create(const lbm_params *p, const uint8_t *mask, const double *rhoA0, co
         MCLBM_HIP(hipMemsetAsync(h->I.buf[1], 0, bufbytes, s));
         MCLBM_HIP(hipMemsetAsync(h->word, 0, np * sizeof(uint16_t), s));
         MCLBM_HIP(hipMemsetAsync(word0, 0, np * sizeof(uint16_t), s));
-        MCLBM_HIP(hipMemsetAsync(h->m25, 0, np * sizeof(uint32_t), s));
+        MCLBM_HIP(hipMemsetAsync(h->den7, 0, np * sizeof(float), s));
         DiagDev z{};
         z.drift_tol = p->drift_tol;
         MCLBM_HIP(hipMemcpyAsync(h->dd, &z, sizeof z, hipMemcpyHostToDevice, s));
         MCLBM_HIP(hipMemcpyAsync(dmask, mask, n, hipMemcpyHostToDevice, s));
         MCLBM_HIP(hipMemcpyAsync(drA, rhoA0, n * sizeof(double), hipMemcpyHostToDevice, s));
         if (two) MCLBM_HIP(hipMemcpyAsync(drB, rhoB0, n * sizeof(double), hipMemcpyHostToDevice, s));
-        const Geometry g{h->nbr, h->cls, h->word, h->m25, h->tflag, word0};
+        const Geometry g{h->nbr, h->cls, h->word, h->den7, h->tflag, word0};
         int r = enqueue_setup(h->I, *p, h->ty, dmask, drA, drB, g, s);
         if (r) return r;
         // mass at step 0 for the drift check
