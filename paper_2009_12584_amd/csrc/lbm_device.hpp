@@ -362,6 +362,28 @@ template <int TY> struct Smem {
 template <int TY> __device__ __forceinline__ int rho_idx(int lx, int ly) {
     return (ly + HMAX) * Smem<TY>::RW + (lx + HMAX);
 }
+// Numerator of Eq. 7 at position (vx, vy) of a density plane in LDS: the
+// weighted sum over the 24 neighbours of the 5 x 5 block (solids and
+// out-of-domain positions hold 0), each row a short chain of fused
+// multiply-adds and the five rows then added, in one fixed order that every
+// step body uses.
+template <int TY> __device__ __forceinline__ float eq7_numerator(const float *plane, int vx, int vy, int avg) {
+    float row[5];
+#pragma unroll
+    for (int ey = -2; ey <= 2; ++ey) {
+        float r = 0.f;
+#pragma unroll
+        for (int ex = -2; ex <= 2; ++ex) {
+            if (ex == 0 && ey == 0) continue;
+            r = fmaf(eq7_weight(ex * ex + ey * ey, avg), plane[rho_idx<TY>(vx + ex, vy + ey)], r);
+        }
+        row[ey + 2] = r;
+    }
+    const float a = row[0] + row[1];
+    const float b = row[3] + row[4];
+    return (a + b) + row[2];
+}
+
 template <int TY> __device__ __forceinline__ int rt_idx(int lx, int ly) {
     return (ly + 1) * Smem<TY>::VW + (lx + 1);
 }
@@ -805,29 +827,14 @@ __device__ __forceinline__ void process_tile(const Inst &I, int tile_x, int tile
             const int vx = k % Smem<TY>::VW - 1, vy = k / Smem<TY>::VW - 1;
             // interface solids lie inside the domain or across a periodic border
             const float den = sm.iden[jj];
-            // every position of the 5 x 5 block is in LDS, solids and
-            // out-of-domain positions as 0, so the numerator needs no mask
-            // and all its reads issue back to back; the denominator, the
-            // weights of the fluid neighbours, comes with the list
-            // the components one after the other: 24 LDS values in
-            // flight at a time instead of 48 keeps the phase within the
-            // registers of the rest of the step
-            float na = 0.f, nb = 0.f;
-#pragma unroll
-            for (int ey = -2; ey <= 2; ++ey)
-#pragma unroll
-                for (int ex = -2; ex <= 2; ++ex) {
-                    if (ex == 0 && ey == 0) continue;
-                    na += eq7_weight(ex * ex + ey * ey, I.avg) * sm.rho[0][rho_idx<TY>(vx + ex, vy + ey)];
-                }
+            // the numerator needs no mask (eq7_numerator); the denominator,
+            // the weights of the fluid neighbours, comes with the list; the
+            // components one after the other: 24 LDS values in flight at a
+            // time instead of 48 keeps the phase within the registers of the
+            // rest of the step
+            const float na = eq7_numerator<TY>(sm.rho[0], vx, vy, I.avg);
             __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-            for (int ey = -2; ey <= 2; ++ey)
-#pragma unroll
-                for (int ex = -2; ex <= 2; ++ex) {
-                    if (ex == 0 && ey == 0) continue;
-                    nb += eq7_weight(ex * ex + ey * ey, I.avg) * sm.rho[1][rho_idx<TY>(vx + ex, vy + ey)];
-                }
+            const float nb = eq7_numerator<TY>(sm.rho[1], vx, vy, I.avg);
             // den > 0: an interface solid has a fluid first-belt neighbour
             sm.rt[0][k] = chi[0] * na / den;
             sm.rt[1][k] = chi[1] * nb / den;

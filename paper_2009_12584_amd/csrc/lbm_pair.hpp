@@ -260,14 +260,7 @@ __device__ __forceinline__ void process_tile_ls(const Inst &I, int tile_x, int t
                 // out-of-domain positions as 0: the numerator needs no mask;
                 // the denominator was summed at set-up (k_den7)
                 const float den = den7v[s];
-                float na = 0.f;
-#pragma unroll
-                for (int ey = -2; ey <= 2; ++ey)
-#pragma unroll
-                    for (int ex = -2; ex <= 2; ++ex) {
-                        if (ex == 0 && ey == 0) continue;
-                        na += eq7_weight(ex * ex + ey * ey, I.avg) * sm.rho[c][rho_idx<TY>(vx + ex, vy + ey)];
-                    }
+                const float na = eq7_numerator<TY>(sm.rho[c], vx, vy, I.avg);
                 // den > 0: an interface solid has a fluid first-belt neighbour
                 tc = chi * na / den;
             }
