@@ -303,11 +303,12 @@ static __global__ void k_near(const uint16_t *__restrict__ word0, int nx, int ny
     word[(int64_t)y * pitch + x] = (uint16_t)f;
 }
 
-// For interface solids: the denominator of Eq. 7, the sum of the averaging
-// weights (D2Q25, or D2Q9 with avg = 1) over the fluid neighbours inside the
-// domain, accumulated in FP32 over rows dy = -2..2 and columns dx = -2..2
-// (centre skipped) in that order; 0 elsewhere.  It depends on the geometry
-// only, so the step reads it instead of summing it every step.
+// For interface solids: the reciprocal of Eq. 7's denominator, the sum of
+// the averaging weights (D2Q25, or D2Q9 with avg = 1) over the fluid
+// neighbours inside the domain, accumulated in FP32 over rows dy = -2..2 and
+// columns dx = -2..2 (centre skipped); 0 elsewhere.  It depends on the
+// geometry only, so the step multiplies by it instead of summing and dividing
+// every step.
 static __global__ void k_den7(const uint16_t *__restrict__ word, int nx, int ny, uint32_t periodic, int pitch,
                               int avg, float *__restrict__ den7) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -331,7 +332,8 @@ static __global__ void k_den7(const uint16_t *__restrict__ word, int nx, int ny,
                 if (in && !(word[(int64_t)yn * pitch + xn] & NW_SOLID)) den += eq7_weight(dx * dx + dy * dy, avg);
             }
     }
-    den7[(int64_t)y * pitch + x] = den;
+    // an interface solid has a fluid first-belt neighbour: den > 0
+    den7[(int64_t)y * pitch + x] = den > 0.f ? 1.f / den : 0.f;
 }
 
 // Per tile: does an owned fluid node touch a solid (then the improved scheme
@@ -406,7 +408,7 @@ __global__ void k_init_sc1(Inst I, const double *__restrict__ rA, double rref, i
 struct Geometry {
     uint8_t *nbr, *cls;   // nx * ny, the classification returned by the ABI
     uint16_t *word;       // ny * pitch node words
-    float *den7;          // ny * pitch Eq. 7 denominators of interface solids
+    float *den7;          // ny * pitch reciprocal Eq. 7 denominators of interface solids
     uint8_t *tflag;       // tiles
     uint16_t *word0;      // ny * pitch scratch for the set-up
 };
@@ -416,7 +418,7 @@ inline size_t geometry_bytes(int nx, int ny, int pitch, int ntiles) {
     return 2 * n + 2 * np * sizeof(uint16_t) + np * sizeof(float) + (size_t)ntiles;
 }
 
-// Classification, node words, Eq. 7 denominators, tile flags and the initial
+// Classification, node words, reciprocal Eq. 7 denominators, tile flags and the initial
 // populations of one simulation, enqueued on stream s (I.buf[0] is written).
 inline int enqueue_setup(Inst &I, const lbm_params &p, int ty, const uint8_t *dmask, const double *drA,
                          const double *drB, const Geometry &g, hipStream_t s) {

@@ -316,7 +316,7 @@ struct DiagDev {
 struct Inst {
     void *buf[2];             // population buffers; parity selects the one read
     const uint16_t *node;     // node words, row pitch `pitch`
-    const float *den7;        // Eq. 7 denominators of interface solids (k_den7), row pitch `pitch`
+    const float *den7;        // reciprocal Eq. 7 denominators of interface solids (k_den7), row pitch `pitch`
     const uint8_t *tflag;     // TF_* per tile
     int nx, ny, pitch, tiles_x, tiles_y;
     int64_t plane;            // nodes per padded lattice = ny * pitch (node words, masks)
@@ -352,7 +352,7 @@ template <int TY> struct Smem {
     double red[threads_for(TY) / 64][5];
     int redi[threads_for(TY) / 64];
     // the interface solids of tile + 1 as a dense list for Eq. 7: position,
-    // denominator, and per (slot, wavefront) how many each lists
+    // reciprocal denominator, and per (slot, wavefront) how many each lists
     static constexpr int NVS = (VW * VH + threads_for(TY) - 1) / threads_for(TY);
     uint16_t ik[VH * VW];
     float iden[VH * VW];
@@ -748,8 +748,8 @@ __device__ __forceinline__ void process_tile(const Inst &I, int tile_x, int tile
         }
     }
 
-    // Eq. 7 denominators of the tile + 1 positions this thread treats, in
-    // flight with the pulls (indices wrap into the grid; a value is used only
+    // reciprocal Eq. 7 denominators of the tile + 1 positions this thread
+    // treats, in flight with the pulls (indices wrap into the grid; a value is used only
     // at an interface solid)
     constexpr int NV = (Smem<TY>::VW * Smem<TY>::VH + threads_for(TY) - 1) / threads_for(TY);
     float den7v[NV];
@@ -826,18 +826,18 @@ __device__ __forceinline__ void process_tile(const Inst &I, int tile_x, int tile
             const int k = sm.ik[jj];
             const int vx = k % Smem<TY>::VW - 1, vy = k / Smem<TY>::VW - 1;
             // interface solids lie inside the domain or across a periodic border
-            const float den = sm.iden[jj];
-            // the numerator needs no mask (eq7_numerator); the denominator,
-            // the weights of the fluid neighbours, comes with the list; the
+            const float rden = sm.iden[jj];
+            // the numerator needs no mask (eq7_numerator); the reciprocal
+            // denominator (the weights of the fluid neighbours) comes with
+            // the list; the
             // components one after the other: 24 LDS values in flight at a
             // time instead of 48 keeps the phase within the registers of the
             // rest of the step
             const float na = eq7_numerator<TY>(sm.rho[0], vx, vy, I.avg);
             __builtin_amdgcn_sched_barrier(0);
             const float nb = eq7_numerator<TY>(sm.rho[1], vx, vy, I.avg);
-            // den > 0: an interface solid has a fluid first-belt neighbour
-            sm.rt[0][k] = chi[0] * na / den;
-            sm.rt[1][k] = chi[1] * nb / den;
+            sm.rt[0][k] = chi[0] * na * rden;
+            sm.rt[1][k] = chi[1] * nb * rden;
         }
         __syncthreads();
     }

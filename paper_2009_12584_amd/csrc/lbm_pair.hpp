@@ -212,8 +212,8 @@ __device__ __forceinline__ void process_tile_ls(const Inst &I, int tile_x, int t
         }
     }
 
-    // Eq. 7 denominators of the tile + 1 positions this lane pair treats, in
-    // flight with the pulls (indices wrap into the grid; used only at
+    // reciprocal Eq. 7 denominators of the tile + 1 positions this lane pair
+    // treats, in flight with the pulls (indices wrap into the grid; used only at
     // interface solids)
     constexpr int NVP = L::VW * L::VH;
     constexpr int NV = (NVP + NPP - 1) / NPP;
@@ -258,11 +258,10 @@ __device__ __forceinline__ void process_tile_ls(const Inst &I, int tile_x, int t
             if (sm.lf[k] & LF_IFACE) {
                 // every position of the 5 x 5 block is in LDS, solids and
                 // out-of-domain positions as 0: the numerator needs no mask;
-                // the denominator was summed at set-up (k_den7)
-                const float den = den7v[s];
+                // the reciprocal denominator comes from set-up (k_den7)
+                const float rden = den7v[s];
                 const float na = eq7_numerator<TY>(sm.rho[c], vx, vy, I.avg);
-                // den > 0: an interface solid has a fluid first-belt neighbour
-                tc = chi * na / den;
+                tc = chi * na * rden;
             }
             sm.rt[c][k] = tc;
         }
